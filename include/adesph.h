@@ -1,0 +1,175 @@
+/*
+ * adesph.h -- C ABI of the MI355X (gfx950) SPH advection-dispersion library.
+ *
+ * The library advances the concentration C of Lagrangian particles under
+ *     dC/dt = div(D grad C) - C div v,   dx/dt = v                 (Eqs. 1-2)
+ * with the dispersion tensor of Eq. (3),
+ *     D_ij = (alpha_T |v| + D_m) delta_ij + (alpha_L - alpha_T) v_i v_j / |v|,
+ * discretised by the consistent SPH operator of Eqs. (4)-(5),
+ *     (dC/dt)_a = 1/2 sum_b (m_b / rhobar_ab) Dcal_ab (C_a - C_b) x_ab . grad_a W_ab / |x_ab|^2,
+ *     Dcal_ab   = sum_ij 4 D_ij,a D_ij,b / (D_ij,a + D_ij,b) [Gamma x_i x_j / |x_ab|^2 - delta_ij],
+ * with the Wendland kernel of Eq. (7) (support radius H), Gamma = d + 2
+ * (= 4 in 2D as in Eq. 5), in a periodic box, for a uniform flow v (so the
+ * convective term of Eq. 4 vanishes and D is the same for every particle),
+ * all particles of a plume having equal mass and density.  Time stepping is
+ * explicit Euler, or the predictor-corrector of Eqs. (8)-(9).
+ * Reference: Klapp, Sigalotti, Alvarado-Rodriguez & Rendon, "Consistent SPH
+ * simulations of the anisotropic dispersion of a contaminant plume",
+ * arXiv:2108.09488, Sections 2.1-2.4.
+ *
+ * Conventions (every entry point):
+ *  - Returns an int status: ADE_OK (0) or a negative ADE_E* code; never aborts.
+ *    ade_last_error() returns a thread-local message for the last failure.
+ *  - Pointers named d_* are device pointers, h_* host pointers.  The caller
+ *    owns every buffer; the library never allocates device memory.  Device
+ *    buffers passed to ade_create must stay valid until ade_destroy.
+ *  - All device work is enqueued on the HIP stream given to ade_create and is
+ *    asynchronous, except where a host output (h_*) forces a synchronisation.
+ *  - Positions are SoA doubles, x[c * n + a] for component c of particle a.
+ *    The library stores them as 32-bit fixed-point fractions of the box,
+ *    u = round(x / L * 2^32) mod 2^32 (resolution L / 2^32): positions are
+ *    periodic by construction and every particle of a plume moves by exactly
+ *    the same displacement each step.
+ *  - Several plumes ("an ensemble") can share one context; their particles
+ *    are concatenated in plume order in every per-particle array.
+ */
+#ifndef ADESPH_H
+#define ADESPH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ade_ctx ade_ctx;
+
+enum {
+    ADE_OK = 0,
+    ADE_EINVAL = -1,      /* invalid argument (value, size or null pointer) */
+    ADE_EWORKSPACE = -2,  /* workspace smaller than ade_workspace_bytes()  */
+    ADE_EHIP = -3,        /* a HIP runtime call failed                      */
+    ADE_EUNSTABLE = -4,   /* dt above 10x the Eq. (10) bound (ADE_STRICT_DT) */
+    ADE_ENONFINITE = -5,  /* non-finite concentration (ADE_CHECK_FINITE)    */
+    ADE_ESTATE = -6       /* call out of order (e.g. step before init)      */
+};
+
+enum { ADE_WENDLAND_C2 = 2, ADE_WENDLAND_C4 = 4 };
+enum { ADE_EULER = 1, ADE_PC = 2 };
+enum { ADE_STRICT_DT = 1u, ADE_CHECK_FINITE = 2u };
+
+/* One plume: kernel, box, dispersion parameters (Eq. 3), flow and time step.
+ * All plumes of a context must share dim, real_bytes, kernel and integrator. */
+typedef struct {
+    int32_t dim;        /* 2 or 3 */
+    int32_t real_bytes; /* 4: FP32 concentration and arithmetic, 8: FP64     */
+    int32_t kernel;     /* ADE_WENDLAND_C2 or ADE_WENDLAND_C4 (Eq. 7)        */
+    int32_t integrator; /* ADE_EULER or ADE_PC (Eqs. 8-9)                    */
+    double H;           /* support radius: W(r) = 0 for r > H (> 0, <= L/3)  */
+    double L;           /* side of the periodic box [0, L)^dim (> 0)         */
+    double alpha_L;     /* longitudinal dispersivity (>= 0)                  */
+    double alpha_T;     /* transverse dispersivity (>= 0)                    */
+    double D_m;         /* molecular diffusion coefficient (>= 0)            */
+    double v[3];        /* uniform flow velocity (v[2] ignored in 2D)        */
+    double dt;          /* time step; <= 0 selects Eq. (10): 0.1 (H/2)^2 / tr D */
+    double rho0;        /* density of every particle (> 0)                   */
+    double mass;        /* mass of every particle (> 0)                      */
+    uint32_t flags;     /* ADE_STRICT_DT | ADE_CHECK_FINITE                  */
+    int32_t cell_rows;  /* cell grid: rows per support radius in y (and z),
+                           1..4; 0 = default                                */
+    int32_t cell_xsub;  /* cell grid: cells per support radius along x,
+                           1..16; 0 = default                               */
+    int32_t reserved;   /* must be 0                                         */
+} ade_params;
+
+/* Launch shape of the pair kernel (chosen by the autotuner, or defaults). */
+typedef struct {
+    int32_t block;          /* threads per workgroup: 64, 128, 256 or 512    */
+    int32_t waves_per_eu;   /* occupancy hint: 0 (none) or 1..8              */
+    int32_t stage_lds;      /* 1: stage neighbour particle tiles in LDS      */
+    int32_t persistent;     /* 1: persistent grid pulling tiles from a queue */
+} ade_tuning;
+
+/* Bytes of device workspace needed for nplumes plumes with counts[p]
+ * particles each (host-only, pure). */
+int ade_workspace_bytes(const ade_params *params, const int64_t *counts, int32_t nplumes,
+                        size_t *bytes);
+
+/* Validates the parameters and lays out the caller's workspace d_ws
+ * (ws_bytes >= ade_workspace_bytes, 256-byte aligned); stream is a
+ * hipStream_t (NULL: the default stream).  *out receives the context. */
+int ade_create(const ade_params *params, const int64_t *counts, int32_t nplumes, void *d_ws,
+               size_t ws_bytes, void *stream, ade_ctx **out);
+
+/* Loads positions d_x (double, SoA dim x N, N = sum of counts, plumes
+ * concatenated) and concentrations d_C (N reals of real_bytes) and resets
+ * the step counter.  The ids of the particles are their indices in d_x. */
+int ade_init_particles(ade_ctx *ctx, const double *d_x, const void *d_C);
+
+/* Cell-linked list: cell hash, counting sort by cell (stable, ordered by
+ * particle id within a cell) and the cell-start table, then the particle
+ * state is gathered into cell order.  Needed once after init; every step
+ * rebuilds it. */
+int ade_build_cells(ade_ctx *ctx);
+
+/* nsteps explicit steps (pair sum of Eqs. 4-5, update of C and x, rebuild). */
+int ade_step(ade_ctx *ctx, int64_t nsteps);
+
+/* The same steps replayed from a HIP graph holding one captured step. */
+int ade_step_graph(ade_ctx *ctx, int64_t nsteps);
+
+/* rhs of Eq. (4) at the current state, written in particle-id order to
+ * d_rhs (N reals). */
+int ade_rhs(ade_ctx *ctx, void *d_rhs);
+
+/* Current concentrations / positions in particle-id order. */
+int ade_read_C(const ade_ctx *ctx, void *d_C_out);
+int ade_read_x(const ade_ctx *ctx, double *d_x_out);
+
+/* Solute mass sum_a m_a C_a of each plume, accumulated in FP64 in a fixed
+ * order, to d_out[nplumes] (device). */
+int ade_mass(const ade_ctx *ctx, double *d_out);
+
+/* Neighbour sets as used by the pair sum: for particle a (id order), the
+ * ids of all b != a with 0 < |x_ab| <= H, in d_ids[d_offsets[a] ..
+ * d_offsets[a+1]) (unordered within a particle).  d_offsets has N+1
+ * entries.  *h_needed receives the total; ids are written only if
+ * cap >= total.  Synchronises the stream. */
+int ade_neighbours(ade_ctx *ctx, int64_t *d_offsets, int32_t *d_ids, int64_t cap,
+                   int64_t *h_needed);
+
+/* Shepard interpolation C_s = sum_b W_sb C_b / sum_b W_sb at n_sensors points
+ * d_xs (double, SoA dim x S) of plume 0, to d_Cs (S reals). */
+int ade_sensor_interp(ade_ctx *ctx, const double *d_xs, int32_t n_sensors, void *d_Cs);
+
+/* Workspace for ade_adjoint (device bytes). */
+int ade_adjoint_workspace_bytes(const ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every,
+                                int32_t n_sensors, size_t *bytes);
+
+/* Misfit and gradient of J = sum_s (C_s(T) - d_s)^2 after nsteps Euler steps
+ * from the current state, w.r.t. (alpha_L, alpha_T, D_m) of plume 0, by a
+ * discrete adjoint with a checkpoint every ckpt_every steps and recompute.
+ * d_obs holds S reals.  On return the context holds the state at step
+ * nsteps.  h_grad receives 3 doubles; synchronises the stream. */
+int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *d_xs,
+                int32_t n_sensors, const void *d_obs, void *d_adj_ws, size_t adj_ws_bytes,
+                double *h_J, double *h_grad);
+
+int ade_set_tuning(ade_ctx *ctx, const ade_tuning *t);
+int ade_get_tuning(const ade_ctx *ctx, ade_tuning *t);
+
+/* Scalar facts about a context: number of particles, cells, tiles, the time
+ * step of plume p actually used, and the step counter. */
+int ade_info(const ade_ctx *ctx, int32_t plume, int64_t *n_total, int64_t *n_cells,
+             int64_t *n_tiles, double *dt, int64_t *step);
+
+int ade_destroy(ade_ctx *ctx);
+
+const char *ade_last_error(void);
+const char *ade_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ADESPH_H */

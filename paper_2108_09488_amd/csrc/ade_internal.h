@@ -1,0 +1,100 @@
+// ade_internal.h -- device-side tables and kernel launch declarations shared
+// by the kernels and the C-ABI host code of the SPH advection-dispersion
+// library (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ade {
+
+constexpr int kTile = 256;          // particles per tile (a tile never spans two plumes)
+constexpr int kScanPerThread = 16;  // counting-sort scan: elements per thread
+constexpr int kScanBlock = 256;
+constexpr int kScanChunk = kScanPerThread * kScanBlock;
+
+// Per-plume constants.  Positions are uint32 fractions of the box, so all
+// lengths below are in grid units (L / 2^32).
+struct PlumeDev {
+    uint32_t poff, n;       // particles [poff, poff + n) in the concatenated order
+    uint32_t cbase, ncell;  // cells [cbase, cbase + ncell) of the global cell table
+    uint32_t nfx, nr;       // cells per row along x; rows per side in y (and z)
+    int32_t R;              // rows to each side that can hold neighbours
+    uint32_t hx;            // half-width of the x search window (>= H_u (1 + 2^-16))
+    uint32_t tfirst, tcount;// tiles of this plume
+    uint32_t pad0, pad1;
+    double Hu;              // support radius in grid units
+    double H2d;             // Hu^2 (double)
+    float H2f;              // Hu^2 rounded to float
+    float pad2;
+    double invHu;
+    double kg[6];           // Gamma * D: xx, yy, zz, 2xy, 2xz, 2yz
+    double trD;             // trace of D
+    double vphi;            // V * (kernel derivative prefactor): rhs = vphi * sum
+    double dt;
+    double ushift[3];       // displacement per step in grid units
+    double mass;            // particle mass
+    double L;
+};
+
+struct TileDev {
+    uint32_t plume, start, end, pad;
+};
+
+// Particle state in structure-of-arrays form.
+struct StateArrays {
+    uint32_t* pos[3];
+    void* C;
+    uint32_t* id;
+    uint32_t* key;   // cell key (U and T buffers)
+    uint32_t* tick;  // slot inside the cell from the counting pass (U buffer)
+};
+
+enum PairMode { kModeStep = 0, kModeHalf = 1, kModeRhs = 2 };
+
+struct PairLaunch {
+    const PlumeDev* plumes;
+    const TileDev* tiles;
+    uint32_t ntiles;
+    const uint32_t* spos[3];
+    const uint32_t* sid;
+    const void* Cpair;      // concentrations entering C_a - C_b
+    const void* Cbase;      // concentrations updated (step mode)
+    const uint32_t* cell_start;
+    // step mode outputs
+    uint32_t* upos[3];
+    void* uC;
+    uint32_t* uid;
+    uint32_t* ukey;
+    uint32_t* utick;
+    uint32_t* count;
+    const int64_t* step;
+    double scale;           // fraction of the plume's dt: step 1, half 0.5 (unused for rhs)
+    void* out;              // half: S-order output; rhs: id-order output
+};
+
+// kernel launchers (kernels_*.hip); all return hipError_t of the launch
+hipError_t launch_init(int dim, int real_bytes, const PlumeDev* plumes, const TileDev* tiles,
+                       uint32_t ntiles, const double* x, const void* C, uint32_t N,
+                       StateArrays U, uint32_t* count, hipStream_t s);
+hipError_t launch_scan(const uint32_t* count_in, uint32_t* cell_start, uint32_t* partial,
+                       uint32_t ncell, hipStream_t s);
+hipError_t launch_scatter(int dim, int real_bytes, StateArrays U, StateArrays T,
+                          const uint32_t* cell_start, uint32_t N, hipStream_t s);
+hipError_t launch_canon(int dim, int real_bytes, StateArrays T, StateArrays S,
+                        const uint32_t* cell_start, uint32_t N, int64_t* step, int inc_step,
+                        hipStream_t s);
+hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const PairLaunch& a,
+                       int block, hipStream_t s);
+hipError_t launch_read_C(int real_bytes, StateArrays S, uint32_t N, void* out, hipStream_t s);
+hipError_t launch_read_x(int dim, const PlumeDev* plumes, const TileDev* tiles, uint32_t ntiles,
+                         StateArrays S, uint32_t N, double* out, hipStream_t s);
+hipError_t launch_mass(int real_bytes, const PlumeDev* plumes, int nplumes, const TileDev* tiles,
+                       uint32_t ntiles, StateArrays S, double* partial, double* out,
+                       hipStream_t s);
+hipError_t launch_nbr(int dim, int real_bytes, int fill, const PlumeDev* plumes,
+                      const TileDev* tiles, uint32_t ntiles, StateArrays S,
+                      const uint32_t* cell_start, int64_t* offsets, int32_t* ids, hipStream_t s);
+hipError_t launch_scan64(int64_t* data, uint32_t n, int64_t* partial, hipStream_t s);
+
+}  // namespace ade

@@ -1,0 +1,524 @@
+// api.hip -- the C ABI declared in include/adesph.h: parameter validation,
+// workspace layout (the caller owns all device memory), per-plume constants
+// and the launch sequence of one step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/adesph.h"
+#include "ade_internal.h"
+
+using namespace ade;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ADE_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+constexpr double kTwo32 = 4294967296.0;
+constexpr double kPi = 3.14159265358979323846;
+
+// Bump allocator over the caller's workspace (base == nullptr: size only).
+struct Bump {
+    char* base;
+    size_t off = 0;
+    explicit Bump(void* b) : base(static_cast<char*>(b)) {}
+    template <typename T>
+    T* take(size_t count) {
+        off = (off + 255) & ~size_t(255);
+        T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+        off += count * sizeof(T);
+        return p;
+    }
+    void* take_bytes(size_t bytes) { return take<char>(bytes); }
+};
+
+struct Plan {
+    int dim = 0, real_bytes = 0, kernel = 0, integrator = 0, P = 0;
+    int64_t N = 0;
+    uint64_t ncell = 0;
+    uint32_t ntiles = 0, nscan = 0;
+    std::vector<PlumeDev> plumes;
+    std::vector<TileDev> tiles;
+};
+
+double trace_D(int dim, double aL, double aT, double Dm, const double* v, double D[9]) {
+    double s2 = 0;
+    for (int i = 0; i < dim; ++i) s2 += v[i] * v[i];
+    const double sp = std::sqrt(s2);
+    double tr = 0;
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+            double d = (i == j) ? aT * sp + Dm : 0.0;
+            if (sp > 0) d += (aL - aT) * v[i] * v[j] / sp;
+            D[i * 3 + j] = d;
+            if (i == j) tr += d;
+        }
+    return tr;
+}
+
+// Kernel normalisation B and the prefactor of W'(r)/r (Eq. 7 and its C2 sibling).
+double kernel_phi_prefactor(int kernel, int dim, double H) {
+    double B;
+    if (kernel == ADE_WENDLAND_C4)
+        B = (dim == 2) ? 9.0 / (kPi * H * H) : 495.0 / (32.0 * kPi * H * H * H);
+    else
+        B = (dim == 2) ? 7.0 / (kPi * H * H) : 21.0 / (2.0 * kPi * H * H * H);
+    return (kernel == ADE_WENDLAND_C4) ? -(56.0 / 3.0) * B / (H * H) : -20.0 * B / (H * H);
+}
+
+int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes, Plan& pl) {
+    if (!params || !counts) return fail(ADE_EINVAL, "null params or counts");
+    if (nplumes <= 0) return fail(ADE_EINVAL, "nplumes must be positive");
+    const ade_params& p0 = params[0];
+    pl.dim = p0.dim;
+    pl.real_bytes = p0.real_bytes;
+    pl.kernel = p0.kernel;
+    pl.integrator = p0.integrator;
+    pl.P = nplumes;
+    if (pl.dim != 2 && pl.dim != 3) return fail(ADE_EINVAL, "dim must be 2 or 3 (got %d)", pl.dim);
+    if (pl.real_bytes != 4 && pl.real_bytes != 8) return fail(ADE_EINVAL, "real_bytes must be 4 or 8");
+    if (pl.kernel != ADE_WENDLAND_C2 && pl.kernel != ADE_WENDLAND_C4)
+        return fail(ADE_EINVAL, "kernel must be ADE_WENDLAND_C2 or ADE_WENDLAND_C4");
+    if (pl.integrator != ADE_EULER && pl.integrator != ADE_PC)
+        return fail(ADE_EINVAL, "integrator must be ADE_EULER or ADE_PC");
+    pl.plumes.clear();
+    pl.tiles.clear();
+    uint64_t N = 0, cbase = 0;
+    for (int p = 0; p < nplumes; ++p) {
+        const ade_params& q = params[p];
+        if (q.dim != pl.dim || q.real_bytes != pl.real_bytes || q.kernel != pl.kernel ||
+            q.integrator != pl.integrator)
+            return fail(ADE_EINVAL, "plume %d: dim, real_bytes, kernel and integrator must match plume 0", p);
+        if (q.reserved != 0) return fail(ADE_EINVAL, "plume %d: reserved must be 0", p);
+        if (counts[p] <= 0) return fail(ADE_EINVAL, "plume %d: count must be positive", p);
+        const double vals[] = {q.H, q.L, q.alpha_L, q.alpha_T, q.D_m, q.v[0], q.v[1], q.v[2], q.dt, q.rho0, q.mass};
+        for (double v : vals)
+            if (!std::isfinite(v)) return fail(ADE_EINVAL, "plume %d: non-finite parameter", p);
+        if (!(q.L > 0) || !(q.H > 0)) return fail(ADE_EINVAL, "plume %d: H and L must be positive", p);
+        if (q.H * 3.0 > q.L) return fail(ADE_EINVAL, "plume %d: support H must be at most L/3", p);
+        if (q.alpha_L < 0 || q.alpha_T < 0 || q.D_m < 0)
+            return fail(ADE_EINVAL, "plume %d: dispersivities and D_m must be >= 0", p);
+        if (!(q.rho0 > 0) || !(q.mass > 0)) return fail(ADE_EINVAL, "plume %d: rho0 and mass must be positive", p);
+        if (q.cell_rows < 0 || q.cell_rows > 4 || q.cell_xsub < 0 || q.cell_xsub > 16)
+            return fail(ADE_EINVAL, "plume %d: cell_rows in 0..4, cell_xsub in 0..16", p);
+
+        PlumeDev d;
+        std::memset(&d, 0, sizeof d);
+        d.poff = (uint32_t)N;
+        d.n = (uint32_t)counts[p];
+        N += (uint64_t)counts[p];
+        if (N > 0x7fffffffull) return fail(ADE_EINVAL, "at most 2^31 - 1 particles in total");
+
+        // cell grid in grid units: rows of height >= Hc / rows_per_H, x cells of width >= Hc / xsub
+        const double Hu = q.H / q.L * kTwo32;
+        const double Hc = Hu * (1.0 + 1.0 / 65536.0) + 2.0;
+        const int rsub = q.cell_rows ? q.cell_rows : 2;
+        const int xsub = q.cell_xsub ? q.cell_xsub : 8;
+        const double cap = std::max(8.0 * (double)counts[p], 4096.0);
+        double nr = std::floor(kTwo32 * rsub / Hc);
+        double nfx = std::floor(kTwo32 * xsub / Hc);
+        while (std::pow(nr, pl.dim - 1) * nfx > cap && (nr > 3 || nfx > 3)) {
+            if (nfx > 3 && nfx >= nr) nfx = std::max(3.0, std::floor(nfx / 2));
+            else nr = std::max(3.0, std::floor(nr / 2));
+        }
+        if (nr < 3 || nfx < 3) return fail(ADE_EINVAL, "plume %d: box holds fewer than 3 cells", p);
+        int R = (int)std::ceil(Hc * nr / kTwo32);
+        if (2 * R + 1 > nr) return fail(ADE_EINVAL, "plume %d: cell rows overlap (H too large)", p);
+        d.nr = (uint32_t)nr;
+        d.nfx = (uint32_t)nfx;
+        d.R = R;
+        d.hx = (uint32_t)std::ceil(Hc) + 1u;
+        d.ncell = (uint32_t)(std::pow(nr, pl.dim - 1) * nfx);
+        d.cbase = (uint32_t)cbase;
+        cbase += d.ncell;
+        if (cbase >= 0xffffffffull) return fail(ADE_EINVAL, "too many cells");
+        d.Hu = Hu;
+        d.H2d = Hu * Hu;
+        d.H2f = (float)d.H2d;
+        d.invHu = 1.0 / Hu;
+
+        double D[9];
+        const double trD = trace_D(pl.dim, q.alpha_L, q.alpha_T, q.D_m, q.v, D);
+        const double gamma = pl.dim + 2.0;
+        d.kg[0] = gamma * D[0];
+        d.kg[1] = gamma * D[4];
+        d.kg[2] = (pl.dim == 3) ? gamma * D[8] : 0.0;
+        d.kg[3] = 2.0 * gamma * D[1];
+        d.kg[4] = (pl.dim == 3) ? 2.0 * gamma * D[2] : 0.0;
+        d.kg[5] = (pl.dim == 3) ? 2.0 * gamma * D[5] : 0.0;
+        d.trD = trD;
+        const double V = q.mass / q.rho0;
+        d.vphi = V * kernel_phi_prefactor(pl.kernel, pl.dim, q.H);
+        double dt = q.dt;
+        const double hs = 0.5 * q.H;
+        if (dt <= 0) {
+            if (!(trD > 0)) return fail(ADE_EINVAL, "plume %d: Eq. (10) needs tr D > 0", p);
+            dt = 0.1 * hs * hs / trD;
+        } else if ((q.flags & ADE_STRICT_DT) && trD > 0 && dt > 10.0 * 0.1 * hs * hs / trD) {
+            return fail(ADE_EUNSTABLE, "plume %d: dt %g exceeds 10x the Eq. (10) bound %g", p, dt,
+                        0.1 * hs * hs / trD);
+        }
+        d.dt = dt;
+        for (int c = 0; c < 3; ++c) d.ushift[c] = (c < pl.dim) ? dt * q.v[c] / q.L * kTwo32 : 0.0;
+        d.mass = q.mass;
+        d.L = q.L;
+        d.tfirst = (uint32_t)pl.tiles.size();
+        for (uint32_t s = 0; s < d.n; s += kTile) {
+            TileDev t;
+            t.plume = (uint32_t)p;
+            t.start = d.poff + s;
+            t.end = d.poff + std::min<uint32_t>(d.n, s + kTile);
+            t.pad = 0;
+            pl.tiles.push_back(t);
+        }
+        d.tcount = (uint32_t)pl.tiles.size() - d.tfirst;
+        pl.plumes.push_back(d);
+    }
+    pl.N = (int64_t)N;
+    pl.ncell = cbase;
+    pl.ntiles = (uint32_t)pl.tiles.size();
+    const uint64_t scan_n = std::max<uint64_t>(pl.ncell, (uint64_t)N + 1);
+    pl.nscan = (uint32_t)((scan_n + kScanChunk - 1) / kScanChunk);
+    return ADE_OK;
+}
+
+}  // namespace
+
+struct ade_ctx {
+    Plan plan;
+    hipStream_t stream = nullptr;
+    ade_tuning tuning{256, 0, 0, 0};
+    PlumeDev* plumes = nullptr;
+    TileDev* tiles = nullptr;
+    StateArrays S{}, U{}, T{};
+    uint32_t* count = nullptr;
+    uint32_t* cell_start = nullptr;
+    void* scan_partial = nullptr;
+    void* aux = nullptr;
+    double* mass_partial = nullptr;
+    int64_t* step = nullptr;
+    uint32_t h_total = 0;  // host copy of N for the cell-start sentinel
+    int64_t h_zero = 0;
+    bool initialized = false, built = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+void layout(Bump& b, ade_ctx* c, const Plan& pl) {
+    const size_t N = (size_t)pl.N;
+    const size_t rb = (size_t)pl.real_bytes;
+    c->plumes = b.take<PlumeDev>(pl.P);
+    c->tiles = b.take<TileDev>(pl.ntiles);
+    StateArrays* bufs[3] = {&c->S, &c->U, &c->T};
+    for (int k = 0; k < 3; ++k) {
+        StateArrays& s = *bufs[k];
+        for (int d = 0; d < 3; ++d) s.pos[d] = (d < pl.dim) ? b.take<uint32_t>(N) : nullptr;
+        s.C = b.take_bytes(N * rb);
+        s.id = b.take<uint32_t>(N);
+        s.key = (k > 0) ? b.take<uint32_t>(N) : nullptr;
+        s.tick = (k == 1) ? b.take<uint32_t>(N) : nullptr;
+    }
+    if (pl.dim == 2) {  // never read in 2D, but keep the pointers valid
+        c->S.pos[2] = c->S.pos[0];
+        c->U.pos[2] = c->U.pos[0];
+        c->T.pos[2] = c->T.pos[0];
+    }
+    c->count = b.take<uint32_t>(pl.ncell);
+    c->cell_start = b.take<uint32_t>(pl.ncell + 1);
+    c->scan_partial = b.take_bytes((size_t)pl.nscan * 8);
+    c->aux = b.take_bytes(N * rb);
+    c->mass_partial = b.take<double>(pl.ntiles);
+    c->step = b.take<int64_t>(1);
+}
+
+PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase, double scale, void* out) {
+    PairLaunch a;
+    std::memset(&a, 0, sizeof a);
+    a.plumes = c->plumes;
+    a.tiles = c->tiles;
+    a.ntiles = c->plan.ntiles;
+    for (int d = 0; d < 3; ++d) {
+        a.spos[d] = c->S.pos[d];
+        a.upos[d] = c->U.pos[d];
+    }
+    a.sid = c->S.id;
+    a.Cpair = Cpair;
+    a.Cbase = Cbase;
+    a.cell_start = c->cell_start;
+    a.uC = c->U.C;
+    a.uid = c->U.id;
+    a.ukey = c->U.key;
+    a.utick = c->U.tick;
+    a.count = c->count;
+    a.step = c->step;
+    a.scale = scale;
+    a.out = out;
+    (void)mode;
+    return a;
+}
+
+// counting sort of the hashed U buffer into S (cell order) and cell_start
+int enqueue_build(ade_ctx* c, int inc_step) {
+    const Plan& pl = c->plan;
+    HIPCHK(launch_scan(c->count, c->cell_start, (uint32_t*)c->scan_partial, (uint32_t)pl.ncell, c->stream));
+    HIPCHK(launch_scatter(pl.dim, pl.real_bytes, c->U, c->T, c->cell_start, (uint32_t)pl.N, c->stream));
+    HIPCHK(launch_canon(pl.dim, pl.real_bytes, c->T, c->S, c->cell_start, (uint32_t)pl.N, c->step,
+                        inc_step, c->stream));
+    return ADE_OK;
+}
+
+int enqueue_step(ade_ctx* c) {
+    const Plan& pl = c->plan;
+    if (pl.integrator == ADE_PC) {
+        PairLaunch h = pair_args(c, kModeHalf, c->S.C, c->S.C, 0.5, c->aux);
+        HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeHalf, h, c->tuning.block, c->stream));
+        PairLaunch f = pair_args(c, kModeStep, c->aux, c->S.C, 1.0, nullptr);
+        HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeStep, f, c->tuning.block, c->stream));
+    } else {
+        PairLaunch f = pair_args(c, kModeStep, c->S.C, c->S.C, 1.0, nullptr);
+        HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeStep, f, c->tuning.block, c->stream));
+    }
+    return enqueue_build(c, 1);
+}
+
+void drop_graph(ade_ctx* c) {
+    if (c->graph_exec) hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ade_workspace_bytes(const ade_params* params, const int64_t* counts, int32_t nplumes, size_t* bytes) {
+    if (!bytes) return fail(ADE_EINVAL, "null bytes");
+    Plan pl;
+    int rc = plan_build(params, counts, nplumes, pl);
+    if (rc) return rc;
+    Bump b(nullptr);
+    ade_ctx tmp;
+    layout(b, &tmp, pl);
+    *bytes = b.off + 256;
+    return ADE_OK;
+}
+
+int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes, void* d_ws,
+               size_t ws_bytes, void* stream, ade_ctx** out) {
+    if (!out) return fail(ADE_EINVAL, "null out");
+    *out = nullptr;
+    if (!d_ws) return fail(ADE_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
+    ade_ctx* c = new (std::nothrow) ade_ctx();
+    if (!c) return fail(ADE_EINVAL, "out of host memory");
+    int rc = plan_build(params, counts, nplumes, c->plan);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    Bump b(d_ws);
+    layout(b, c, c->plan);
+    if (b.off + 256 > ws_bytes) {
+        delete c;
+        return fail(ADE_EWORKSPACE, "workspace too small: need %zu bytes", b.off + 256);
+    }
+    c->stream = static_cast<hipStream_t>(stream);
+    const Plan& pl = c->plan;
+    c->h_total = (uint32_t)pl.N;
+    auto cleanup = [&](int code) {
+        delete c;
+        return code;
+    };
+    if (hipMemcpyAsync(c->plumes, pl.plumes.data(), sizeof(PlumeDev) * pl.P, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->tiles, pl.tiles.data(), sizeof(TileDev) * pl.ntiles, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->cell_start + pl.ncell, &c->h_total, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->count, 0, sizeof(uint32_t) * pl.ncell, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->step, 0, sizeof(int64_t), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess)
+        return cleanup(fail(ADE_EHIP, "uploading the plume tables failed"));
+    *out = c;
+    return ADE_OK;
+}
+
+int ade_init_particles(ade_ctx* c, const double* d_x, const void* d_C) {
+    if (!c || !d_x || !d_C) return fail(ADE_EINVAL, "null argument");
+    const Plan& pl = c->plan;
+    HIPCHK(hipMemsetAsync(c->count, 0, sizeof(uint32_t) * pl.ncell, c->stream));
+    HIPCHK(hipMemsetAsync(c->step, 0, sizeof(int64_t), c->stream));
+    HIPCHK(launch_init(pl.dim, pl.real_bytes, c->plumes, c->tiles, pl.ntiles, d_x, d_C, (uint32_t)pl.N,
+                       c->U, c->count, c->stream));
+    c->initialized = true;
+    c->built = false;
+    return ADE_OK;
+}
+
+int ade_build_cells(ade_ctx* c) {
+    if (!c) return fail(ADE_EINVAL, "null ctx");
+    if (!c->initialized) return fail(ADE_ESTATE, "ade_build_cells before ade_init_particles");
+    if (c->built) return ADE_OK;  // every step already leaves the cells built
+    int rc = enqueue_build(c, 0);
+    if (rc) return rc;
+    c->built = true;
+    return ADE_OK;
+}
+
+int ade_step(ade_ctx* c, int64_t nsteps) {
+    if (!c) return fail(ADE_EINVAL, "null ctx");
+    if (nsteps < 0) return fail(ADE_EINVAL, "nsteps must be >= 0");
+    if (!c->built) return fail(ADE_ESTATE, "ade_step before ade_build_cells");
+    for (int64_t s = 0; s < nsteps; ++s) {
+        int rc = enqueue_step(c);
+        if (rc) return rc;
+    }
+    return ADE_OK;
+}
+
+int ade_step_graph(ade_ctx* c, int64_t nsteps) {
+    if (!c) return fail(ADE_EINVAL, "null ctx");
+    if (nsteps < 0) return fail(ADE_EINVAL, "nsteps must be >= 0");
+    if (!c->built) return fail(ADE_ESTATE, "ade_step_graph before ade_build_cells");
+    if (!c->stream) return fail(ADE_EINVAL, "graph capture needs a non-default stream");
+    if (!c->graph_exec) {
+        HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        int rc = enqueue_step(c);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(c->stream, &g);
+        if (rc) {
+            if (g) hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess) return fail(ADE_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
+        c->graph = g;
+        e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            drop_graph(c);
+            return fail(ADE_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
+        }
+    }
+    for (int64_t s = 0; s < nsteps; ++s) HIPCHK(hipGraphLaunch(c->graph_exec, c->stream));
+    return ADE_OK;
+}
+
+int ade_rhs(ade_ctx* c, void* d_rhs) {
+    if (!c || !d_rhs) return fail(ADE_EINVAL, "null argument");
+    if (!c->built) return fail(ADE_ESTATE, "ade_rhs before ade_build_cells");
+    const Plan& pl = c->plan;
+    PairLaunch a = pair_args(c, kModeRhs, c->S.C, c->S.C, 1.0, d_rhs);
+    HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeRhs, a, c->tuning.block, c->stream));
+    return ADE_OK;
+}
+
+int ade_read_C(const ade_ctx* c, void* d_C_out) {
+    if (!c || !d_C_out) return fail(ADE_EINVAL, "null argument");
+    if (!c->built) return fail(ADE_ESTATE, "ade_read_C before ade_build_cells");
+    HIPCHK(launch_read_C(c->plan.real_bytes, c->S, (uint32_t)c->plan.N, d_C_out, c->stream));
+    return ADE_OK;
+}
+
+int ade_read_x(const ade_ctx* c, double* d_x_out) {
+    if (!c || !d_x_out) return fail(ADE_EINVAL, "null argument");
+    if (!c->built) return fail(ADE_ESTATE, "ade_read_x before ade_build_cells");
+    HIPCHK(launch_read_x(c->plan.dim, c->plumes, c->tiles, c->plan.ntiles, c->S, (uint32_t)c->plan.N,
+                         d_x_out, c->stream));
+    return ADE_OK;
+}
+
+int ade_mass(const ade_ctx* c, double* d_out) {
+    if (!c || !d_out) return fail(ADE_EINVAL, "null argument");
+    if (!c->built) return fail(ADE_ESTATE, "ade_mass before ade_build_cells");
+    HIPCHK(launch_mass(c->plan.real_bytes, c->plumes, c->plan.P, c->tiles, c->plan.ntiles, c->S,
+                       c->mass_partial, d_out, c->stream));
+    return ADE_OK;
+}
+
+int ade_neighbours(ade_ctx* c, int64_t* d_offsets, int32_t* d_ids, int64_t cap, int64_t* h_needed) {
+    if (!c || !d_offsets || !h_needed) return fail(ADE_EINVAL, "null argument");
+    if (!c->built) return fail(ADE_ESTATE, "ade_neighbours before ade_build_cells");
+    const Plan& pl = c->plan;
+    HIPCHK(launch_nbr(pl.dim, pl.real_bytes, 0, c->plumes, c->tiles, pl.ntiles, c->S, c->cell_start,
+                      d_offsets, nullptr, c->stream));
+    HIPCHK(launch_scan64(d_offsets, (uint32_t)pl.N, (int64_t*)c->scan_partial, c->stream));
+    int64_t total = 0;
+    HIPCHK(hipMemcpyAsync(&total, d_offsets + pl.N, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    *h_needed = total;
+    if (d_ids && cap >= total)
+        HIPCHK(launch_nbr(pl.dim, pl.real_bytes, 1, c->plumes, c->tiles, pl.ntiles, c->S, c->cell_start,
+                          d_offsets, d_ids, c->stream));
+    return ADE_OK;
+}
+
+int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
+    if (!c || !t) return fail(ADE_EINVAL, "null argument");
+    if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
+        return fail(ADE_EINVAL, "block must be 64, 128, 256 or 512");
+    if (t->waves_per_eu < 0 || t->waves_per_eu > 8) return fail(ADE_EINVAL, "waves_per_eu in 0..8");
+    c->tuning = *t;
+    drop_graph(c);
+    return ADE_OK;
+}
+
+int ade_get_tuning(const ade_ctx* c, ade_tuning* t) {
+    if (!c || !t) return fail(ADE_EINVAL, "null argument");
+    *t = c->tuning;
+    return ADE_OK;
+}
+
+int ade_info(const ade_ctx* c, int32_t plume, int64_t* n_total, int64_t* n_cells, int64_t* n_tiles,
+             double* dt, int64_t* step) {
+    if (!c) return fail(ADE_EINVAL, "null ctx");
+    if (plume < 0 || plume >= c->plan.P) return fail(ADE_EINVAL, "plume out of range");
+    if (n_total) *n_total = c->plan.N;
+    if (n_cells) *n_cells = (int64_t)c->plan.ncell;
+    if (n_tiles) *n_tiles = c->plan.ntiles;
+    if (dt) *dt = c->plan.plumes[plume].dt;
+    if (step) {
+        int64_t v = 0;
+        HIPCHK(hipMemcpyAsync(&v, c->step, sizeof v, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        *step = v;
+    }
+    return ADE_OK;
+}
+
+int ade_destroy(ade_ctx* c) {
+    if (!c) return ADE_OK;
+    if (c->stream) hipStreamSynchronize(c->stream);
+    else hipDeviceSynchronize();
+    drop_graph(c);
+    delete c;
+    return ADE_OK;
+}
+
+const char* ade_last_error(void) { return g_err.c_str(); }
+
+const char* ade_version(void) { return "adesph 0.1 (gfx950)"; }
+
+}  // extern "C"

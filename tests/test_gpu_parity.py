@@ -1,0 +1,173 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 CPU oracle, on the
+same seeded inputs.
+
+Tolerances: neighbour sets bit-exact (the oracle evaluates the same
+fixed-point predicate in the same precision); FP64 runs within 1e-12 relative
+L2; FP32 right-hand sides and FP32 trajectories on the non-growing problems
+within 1e-5 relative L2.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2108_09488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TWO32 = 4294967296.0
+
+
+def _ctx(spec, integrator=1, cell_rows=0, cell_xsub=0):
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    print(f"[case] {spec.name} n_side={spec.n_side} dim={spec.dim} h/dp={spec.h_over_dp} "
+          f"rb={spec.real_bytes} integ={integrator}", flush=True)
+    ctx = Context([params_from_spec(spec, integrator=integrator, cell_rows=cell_rows,
+                                    cell_xsub=cell_xsub)], [spec.n])
+    x = spec.positions()
+    C = spec.concentration(x)
+    if spec.real_bytes == 4:
+        C = C.astype(np.float32).astype(np.float64)
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+    return ctx, x, C
+
+
+def _sets(offsets, ids):
+    offsets = np.asarray(offsets, dtype=np.int64)
+    ids = np.asarray(ids, dtype=np.int64)
+    seg = np.repeat(np.arange(len(offsets) - 1), np.diff(offsets))
+    order = np.lexsort((ids, seg))
+    return offsets, ids[order]
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+NBR_CASES = [
+    ("cfg1", {}),
+    ("cfg2_h13_r10", {"n_side": 128}),
+    ("cfg2_h20_r100", {"n_side": 128}),
+    ("cfg2_h30_r10", {"n_side": 128}),
+    ("cfg2_h20_r10", {"n_side": 50, "h_over_dp": 1.5}),          # ragged last tile
+    ("cfg3", {"n_side": 24}),
+    ("cfg1", {"real_bytes": 4, "jitter": 0.1, "n_side": 40}),
+]
+
+
+@pytest.mark.parametrize("name,over", NBR_CASES)
+@pytest.mark.parametrize("grid", [(0, 0), (1, 1), (3, 16)])
+def test_neighbour_sets_bit_exact(name, over, grid):
+    spec = I.config(name, **over)
+    ctx, x, _ = _ctx(spec, cell_rows=grid[0], cell_xsub=grid[1])
+    off, ids = ctx.neighbours()
+    g_off, g_ids = _sets(off.cpu().numpy(), ids.cpu().numpy())
+    o_off, o_ids = O.neighbours_fixed(spec.dim, x, spec.L, spec.H, spec.real_bytes)
+    assert np.array_equal(g_off, o_off)
+    assert np.array_equal(g_ids, o_ids)
+    # after some steps the lattice has moved by an exact fixed-point displacement
+    k = 7
+    ctx.step(k)
+    off, ids = ctx.neighbours()
+    g_off, g_ids = _sets(off.cpu().numpy(), ids.cpu().numpy())
+    u = O.to_fixed(x, spec.L).astype(np.int64)
+    v = spec.velocity()
+    xk = np.empty_like(x)
+    for c in range(spec.dim):
+        s = int(np.rint(k * spec.dt * v[c] / spec.L * TWO32))
+        xk[c] = np.mod(u[c] + s, 1 << 32).astype(np.float64) / TWO32 * spec.L
+    o_off, o_ids = O.neighbours_fixed(spec.dim, xk, spec.L, spec.H, spec.real_bytes)
+    assert np.array_equal(g_off, o_off) and np.array_equal(g_ids, o_ids)
+    ctx.close()
+
+
+RHS_CASES = [(c, {"n_side": 128}) for c in I.CFG2_CELLS] + [("cfg3", {"n_side": 24}), ("cfg1", {})]
+
+
+@pytest.mark.parametrize("name,over", RHS_CASES)
+def test_rhs_parity(name, over):
+    spec = I.config(name, **over)
+    ctx, x, C = _ctx(spec)
+    g = ctx.rhs().double().cpu().numpy()
+    r = O.rhs(O.model_from_spec(spec), x, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+    tol = 1e-12 if spec.real_bytes == 8 else 1e-5
+    assert _rel(g, r) < tol
+    ctx.close()
+
+
+@pytest.mark.parametrize("name", I.CFG2_CELLS + ["cfg3"])
+def test_rhs_parity_full_size_sampled(name):
+    """Full-size problems (512^2, 128^3): the oracle evaluates Eq. (4) at a
+    seeded sample of particles inside the plume."""
+    spec = I.config(name)
+    ctx, x, C = _ctx(spec)
+    g = ctx.rhs().double().cpu().numpy()
+    rng = np.random.default_rng(7)
+    inside = np.flatnonzero(C > 1e-3)
+    idx = np.sort(rng.choice(inside, size=1500, replace=False))
+    r = O.rhs(O.model_from_spec(spec), x, C, v_uniform=spec.velocity(), mass=spec.mass,
+              rho=spec.rho0, idx=idx)
+    assert _rel(g[idx], r) < 1e-5
+    ctx.close()
+
+
+@pytest.mark.parametrize("integrator", [1, 2])
+def test_fp64_trajectory(integrator):
+    """64^2 regular lattice, Wendland C2, 200 steps in FP64: C within 1e-12
+    relative L2 of the oracle, mass conserved to 1e-12, positions to 1e-9."""
+    spec = I.config("cfg1")
+    ctx, x, C0 = _ctx(spec, integrator=integrator)
+    m0 = ctx.mass().cpu().numpy()[0]
+    ctx.step(spec.steps)
+    C = ctx.read_C().cpu().numpy()
+    xg = ctx.read_x().cpu().numpy()
+    m1 = ctx.mass().cpu().numpy()[0]
+    xo, Co, hist = O.run(O.model_from_spec(spec), x, C0, spec.dt, spec.steps, v_uniform=spec.velocity(),
+                         mass=spec.mass, rho=spec.rho0, integrator=integrator)
+    assert _rel(C, Co) < 1e-12
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+    assert m0 == pytest.approx(hist[0], rel=1e-13)
+    d = (xg - xo + 0.5) % 1.0 - 0.5
+    assert np.max(np.abs(d)) < 1e-9
+    ctx.close()
+
+
+@pytest.mark.parametrize("name,over,steps", [("cfg2_h20_r10", {"n_side": 128}, 200),
+                                             ("cfg2_h30_r10", {"n_side": 128}, 200),
+                                             ("cfg2_h30_r100", {"n_side": 128}, 200),
+                                             ("cfg3", {"n_side": 24}, 60)])
+def test_fp32_trajectory(name, over, steps):
+    spec = I.config(name, **over)
+    ctx, x, C0 = _ctx(spec)
+    ctx.step(steps)
+    C = ctx.read_C().double().cpu().numpy()
+    _, Co, _ = O.run(O.model_from_spec(spec), x, C0, spec.dt, steps, v_uniform=spec.velocity(),
+                     mass=spec.mass, rho=spec.rho0)
+    assert _rel(C, Co) < 1e-5
+    ctx.close()
+
+
+def test_determinism_and_graph_replay():
+    """Two runs from the same inputs are bitwise equal; replaying a captured
+    step from a HIP graph gives the same bits as eager launches."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = I.config("cfg2_h20_r10", n_side=96)
+    outs = []
+    for mode in ("eager", "eager", "graph"):
+        stream = torch.cuda.Stream()
+        ctx = Context([params_from_spec(spec)], [spec.n], stream=stream)
+        x = spec.positions()
+        C = spec.concentration(x)
+        ctx.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+        if mode == "eager":
+            ctx.step(30)
+        else:
+            for _ in range(3):  # several graph launches with host work between them
+                ctx.step_graph(10)
+                torch.cuda.synchronize()
+        outs.append(ctx.read_C().cpu().numpy().copy())
+        assert ctx.info()["step"] == 30
+        stream.synchronize()
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert np.array_equal(outs[0], outs[2])
