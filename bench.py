@@ -1,0 +1,223 @@
+"""Benchmark: particle-neighbour interactions per second of the SPH
+advection-dispersion step on one MI355X.
+
+Workload (default): the 2D consistency sweep -- six 512^2-particle plumes on
+jittered lattices (+-0.1 dp), Wendland C4, h/dp in {1.3, 2, 3} x
+alpha_L/alpha_T in {10, 100}, FP32, dt from Eq. (10).  One bench step
+advances each of the six plumes by one explicit step (pair sum of Eqs. 4-5,
+update of C and x, cell-list rebuild).  value = sum over plumes of the
+directed interactions per step (pairs b != a with 0 < r <= H) times the
+steps, divided by the wall time of the timed region.
+
+Also reported: the HIP-event time of the pair kernel and its roofline, the
+same sweep replayed from HIP graphs, the batched ensemble (256 plumes of
+32^2..256^2 particles in one context), and the FP64 CPU oracle on a bounded
+sample of the same workload (cpu_baseline).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# algorithmic floating-point work of one directed interaction (FMA = 2 flops):
+# separation (d), r^2 (2d - 1), rsqrt (1), q (2), Wendland C4 polynomial (7),
+# quadratic form x^T (Gamma D) x (7 in 2D, 14 in 3D), A = Q / r^2 - tr D (3),
+# C_a - C_b (1), accumulation (3).
+FLOPS_PER_INTERACTION = {2: 29, 3: 39}
+PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published vector FP32 (packed FMA)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA)
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def build_sweep(cells, device):
+    import numpy as np
+    import torch
+    from paper_2108_09488_amd import inputs as I
+    from paper_2108_09488_amd.context import Context, params_from_spec
+
+    out = []
+    stream = torch.cuda.Stream(device=device)  # one stream: plumes run back to back
+    for name in cells:
+        spec = I.config(name)
+        ctx = Context([params_from_spec(spec)], [spec.n], device=device, stream=stream)
+        x = spec.positions()
+        C = spec.concentration(x)
+        ctx.init(torch.from_numpy(x), torch.from_numpy(C.astype(np.float32))).build()
+        off, _ = ctx.neighbours()
+        inter = int(off[-1].item())
+        out.append({"name": name, "spec": spec, "ctx": ctx, "interactions": inter})
+    return out
+
+
+def time_sweep(sweep, steps, warmup, graph):
+    import torch
+    for s in sweep:
+        (s["ctx"].step_graph if graph else s["ctx"].step)(warmup)
+    _sync()
+    if not graph:
+        for s in sweep:
+            s["ctx"].timing_start()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        for s in sweep:
+            (s["ctx"].step_graph if graph else s["ctx"].step)(1)
+    _sync()
+    wall = time.perf_counter() - t0
+    pair = None
+    if not graph:
+        ms = 0.0
+        n = 0
+        flops = 0.0
+        for s in sweep:
+            m, c = s["ctx"].timing_stop()
+            ms += m
+            n += c
+            flops += s["interactions"] * FLOPS_PER_INTERACTION[s["spec"].dim] * c
+        pair = {"ms_total": ms, "launches": n, "flops": flops}
+    return wall, pair
+
+
+def batched(device, steps, warmup, n_plumes=256):
+    import numpy as np
+    import torch
+    from paper_2108_09488_amd import inputs as I
+    from paper_2108_09488_amd.context import Context, params_from_spec
+
+    specs = I.ensemble(n_plumes)
+    stream = torch.cuda.Stream(device=device)
+    ctx = Context([params_from_spec(s) for s in specs], [s.n for s in specs], device=device, stream=stream)
+    xs = np.concatenate([s.positions() for s in specs], axis=1)
+    Cs = np.concatenate([s.concentration(s.positions()) for s in specs])
+    ctx.init(torch.from_numpy(xs), torch.from_numpy(Cs.astype(np.float32))).build()
+    off, _ = ctx.neighbours()
+    inter = int(off[-1].item())
+    ctx.step_graph(warmup)
+    _sync()
+    t0 = time.perf_counter()
+    ctx.step_graph(steps)
+    _sync()
+    wall = time.perf_counter() - t0
+    n = ctx.N
+    ctx.close()
+    return {"plumes": n_plumes, "particles": n, "interactions_per_step": inter,
+            "steps": steps, "ms_per_step": 1e3 * wall / steps,
+            "interactions_per_s": inter * steps / wall}
+
+
+def cpu_baseline(cells, budget_s=20.0):
+    """The FP64 oracle on the host cores: one explicit step of each plume of
+    the sweep (full 512^2 size), repeated while within the time budget."""
+    import numpy as np
+    import oracle as O
+    from paper_2108_09488_amd import inputs as I
+
+    total_inter = 0
+    total_wall = 0.0
+    reps = 0
+    specs = [I.config(c) for c in cells]
+    prepared = []
+    for s in specs:
+        x = s.positions()
+        C = s.concentration(x).astype(np.float32).astype(np.float64)
+        m = O.model_from_spec(s)
+        off, _ = O.neighbours_cells(m, x)
+        prepared.append((s, m, x, C, int(off[-1])))
+    while total_wall < budget_s and reps < 3:
+        for s, m, x, C, inter in prepared:
+            t0 = time.perf_counter()
+            O.run(m, x, C, s.dt, 1, v_uniform=s.velocity(), mass=s.mass, rho=s.rho0)
+            total_wall += time.perf_counter() - t0
+            total_inter += inter
+        reps += 1
+    return {"value": total_inter / total_wall, "unit": "interactions/s", "cores": O.num_threads(),
+            "kind": "oracle",
+            "sample": f"{reps} explicit step(s) of each of the {len(cells)} 512^2 sweep plumes, FP64"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extras", action="store_true", help="skip graph replay and batched runs")
+    ap.add_argument("--cells", default="", help="comma-separated subset of the sweep plumes")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep and the "
+              "ensemble are single-GPU workloads here.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2108_09488_amd import inputs as I
+
+    device = "cuda:0"
+    cells = args.cells.split(",") if args.cells else list(I.CFG2_CELLS)
+    sweep = build_sweep(cells, device)
+    inter_step = sum(s["interactions"] for s in sweep)
+    print(f"[bench] sweep built: {len(sweep)} plumes, {inter_step} interactions per step", file=sys.stderr, flush=True)
+
+    wall, pair = time_sweep(sweep, args.steps, args.warmup, graph=False)
+    value = inter_step * args.steps / wall
+    print(f"[bench] eager: {1e3 * wall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    avg_ms = pair["ms_total"] / pair["launches"]
+    achieved = pair["flops"] / (pair["ms_total"] * 1e-3) / 1e12
+    extras = {}
+    if not args.no_extras:
+        gwall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
+        extras["graph_replay"] = {"ms_per_step": 1e3 * gwall / args.steps,
+                                  "interactions_per_s": inter_step * args.steps / gwall}
+        print(f"[bench] graph: {1e3 * gwall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+        b = batched(device, steps=min(args.steps, 200), warmup=args.warmup)
+        b["vs_plain"] = b["interactions_per_s"] / value
+        extras["batched"] = b
+        print(f"[bench] batched: {b['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    per_cell = {s["name"]: {"interactions_per_step": s["interactions"],
+                            "neighbours_mean": s["interactions"] / s["spec"].n} for s in sweep}
+    for s in sweep:
+        s["ctx"].close()
+
+    line = {
+        "metric": "particle-neighbour interactions/s per ADE step (fwd, fwd+adjoint, batched) vs plain",
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "2D consistency sweep: 6 plumes x 512^2 particles, jitter 0.1 dp, "
+                               "Wendland C4, h/dp {1.3,2,3} x alpha_L/alpha_T {10,100}, FP32, "
+                               "explicit Euler, dt Eq. (10)",
+                   "plumes": cells, "interactions_per_step": inter_step, "per_plume": per_cell},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "kernel": "k_pair (step mode)", "avg_launch_ms": avg_ms,
+                     "launches": pair["launches"],
+                     "flops_per_interaction": FLOPS_PER_INTERACTION[2],
+                     "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS},
+        "extras": extras,
+    }
+    if not args.no_cpu:
+        print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(cells)
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

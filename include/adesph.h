@@ -83,12 +83,20 @@ typedef struct {
     int32_t reserved;   /* must be 0                                         */
 } ade_params;
 
-/* Launch shape of the pair kernel (chosen by the autotuner, or defaults). */
+/* Launch shape of the pair kernel (chosen by the autotuner, or defaults).
+ * lanes sets how many lanes of a wavefront share one target particle (its
+ * candidates are interleaved over them and the partial sums are combined by
+ * a wavefront reduction); with N particles the kernel runs N*lanes/64
+ * wavefronts, so lanes is the waves-per-CU knob.  The summation order, and so
+ * the last bits of the result, depend on lanes and on nothing else here. */
 typedef struct {
-    int32_t block;          /* threads per workgroup: 64, 128, 256 or 512    */
-    int32_t waves_per_eu;   /* occupancy hint: 0 (none) or 1..8              */
-    int32_t stage_lds;      /* 1: stage neighbour particle tiles in LDS      */
-    int32_t persistent;     /* 1: persistent grid pulling tiles from a queue */
+    int32_t block;          /* threads per workgroup: 64, 128 or 256          */
+    int32_t lanes;          /* lanes per target particle: 1, 2 or 4           */
+    int32_t stage_lds;      /* neighbour-particle records staged in LDS per
+                               thread (16 B each; 0 = read candidates from
+                               global memory); stage_lds*block*16 <= 64 KiB  */
+    int32_t persistent;     /* 0: one workgroup per work item; > 0: a grid of
+                               that many workgroups loops over the items     */
 } ade_tuning;
 
 /* Bytes of device workspace needed for nplumes plumes with counts[p]
@@ -155,6 +163,13 @@ int ade_adjoint_workspace_bytes(const ade_ctx *ctx, int64_t nsteps, int32_t ckpt
 int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *d_xs,
                 int32_t n_sensors, const void *d_obs, void *d_adj_ws, size_t adj_ws_bytes,
                 double *h_J, double *h_grad);
+
+/* HIP-event timing of the pair kernel launches on the context's stream.
+ * mode 1: start (clears the totals; events are recorded around every pair
+ * kernel launched eagerly by ade_step / ade_rhs).  mode 0: stop, synchronise
+ * and return the summed kernel time in *h_ms and the number of launches in
+ * *h_count (either may be NULL). */
+int ade_kernel_timing(ade_ctx *ctx, int32_t mode, double *h_ms, int64_t *h_count);
 
 int ade_set_tuning(ade_ctx *ctx, const ade_tuning *t);
 int ade_get_tuning(const ade_ctx *ctx, ade_tuning *t);

@@ -24,7 +24,7 @@ ERROR_NAMES = {0: "ADE_OK", -1: "ADE_EINVAL", -2: "ADE_EWORKSPACE", -3: "ADE_EHI
 EXPORTS = ["ade_workspace_bytes", "ade_create", "ade_init_particles", "ade_build_cells",
            "ade_step", "ade_step_graph", "ade_rhs", "ade_read_C", "ade_read_x", "ade_mass",
            "ade_neighbours", "ade_sensor_interp", "ade_adjoint_workspace_bytes", "ade_adjoint",
-           "ade_set_tuning", "ade_get_tuning", "ade_info", "ade_destroy", "ade_last_error",
+           "ade_kernel_timing", "ade_set_tuning", "ade_get_tuning", "ade_info", "ade_destroy", "ade_last_error",
            "ade_version"]
 
 
@@ -38,7 +38,7 @@ class AdeParams(ct.Structure):
 
 
 class AdeTuning(ct.Structure):
-    _fields_ = [("block", ct.c_int32), ("waves_per_eu", ct.c_int32), ("stage_lds", ct.c_int32),
+    _fields_ = [("block", ct.c_int32), ("lanes", ct.c_int32), ("stage_lds", ct.c_int32),
                 ("persistent", ct.c_int32)]
 
 
@@ -79,6 +79,7 @@ def lib() -> ct.CDLL:
         "ade_sensor_interp": [p, p, i32, p],
         "ade_adjoint_workspace_bytes": [p, i64, i32, i32, psz],
         "ade_adjoint": [p, i64, i32, p, i32, p, p, sz, pd, pd],
+        "ade_kernel_timing": [p, i32, pd, pi64],
         "ade_set_tuning": [p, T],
         "ade_get_tuning": [p, T],
         "ade_info": [p, i32, pi64, pi64, pi64, pd, pi64],

@@ -159,14 +159,24 @@ class Context:
                              ct.byref(st)))
         return {"n": n.value, "cells": c.value, "tiles": t.value, "dt": dt.value, "step": st.value}
 
-    def set_tuning(self, block=256, waves_per_eu=0, stage_lds=0, persistent=0):
-        t = AdeTuning(block, waves_per_eu, stage_lds, persistent)
+    def timing_start(self):
+        """Start HIP-event timing of the pair kernel launches."""
+        check(lib().ade_kernel_timing(self._h, 1, None, None))
+
+    def timing_stop(self):
+        """Stop timing; returns (summed pair-kernel ms, number of launches)."""
+        ms, n = ct.c_double(), ct.c_int64()
+        check(lib().ade_kernel_timing(self._h, 0, ct.byref(ms), ct.byref(n)))
+        return ms.value, n.value
+
+    def set_tuning(self, block=256, lanes=2, stage_lds=0, persistent=0):
+        t = AdeTuning(block, lanes, stage_lds, persistent)
         check(lib().ade_set_tuning(self._h, ct.byref(t)))
 
     def get_tuning(self) -> dict:
         t = AdeTuning()
         check(lib().ade_get_tuning(self._h, ct.byref(t)))
-        return {"block": t.block, "waves_per_eu": t.waves_per_eu, "stage_lds": t.stage_lds,
+        return {"block": t.block, "lanes": t.lanes, "stage_lds": t.stage_lds,
                 "persistent": t.persistent}
 
     def adjoint(self, nsteps: int, ckpt_every: int, xs: torch.Tensor, obs: torch.Tensor):

@@ -80,4 +80,31 @@ __device__ __forceinline__ T block_sum(T v, T* lds) {
     return tot;
 }
 
+// 16-byte record of a particle for the candidate loops: fixed-point position
+// and concentration (2D: x, y, C[, C high word]; 3D FP32: x, y, z, C).  3D FP64
+// does not fit and uses the structure-of-arrays state instead.
+template <int DIM, typename real>
+struct Rec {
+    static constexpr bool kStageable = !(DIM == 3 && sizeof(real) == 8);
+    static __device__ __forceinline__ uint4 pack(uint32_t x, uint32_t y, uint32_t z, real c) {
+        uint4 r;
+        r.x = x;
+        r.y = y;
+        if (sizeof(real) == 4) {
+            const uint32_t cb = __float_as_uint((float)c);
+            r.z = (DIM == 3) ? z : cb;
+            r.w = (DIM == 3) ? cb : 0u;
+        } else {
+            const unsigned long long cb = (unsigned long long)__double_as_longlong((double)c);
+            r.z = (uint32_t)cb;
+            r.w = (uint32_t)(cb >> 32);
+        }
+        return r;
+    }
+    static __device__ __forceinline__ real conc(const uint4& r) {
+        if (sizeof(real) == 4) return (real)__uint_as_float(DIM == 3 ? r.w : r.z);
+        return (real)__longlong_as_double((long long)(((unsigned long long)r.w << 32) | r.z));
+    }
+};
+
 }  // namespace ade

@@ -28,6 +28,8 @@ struct PlumeDev {
     float H2f;              // Hu^2 rounded to float
     float pad2;
     double invHu;
+    float Hc2f;             // square of the search radius Hc = H_u (1 + 2^-16) + 2
+    float rowh2f;           // square of the row height in grid units, (2^32 / nr)^2
     double kg[6];           // Gamma * D: xx, yy, zz, 2xy, 2xz, 2yz
     double trD;             // trace of D
     double vphi;            // V * (kernel derivative prefactor): rhs = vphi * sum
@@ -44,6 +46,7 @@ struct TileDev {
 // Particle state in structure-of-arrays form.
 struct StateArrays {
     uint32_t* pos[3];
+    uint4* rec;      // 16-byte candidate records (sorted buffer S only; null if unused)
     void* C;
     uint32_t* id;
     uint32_t* key;   // cell key (U and T buffers)
@@ -56,6 +59,11 @@ struct PairLaunch {
     const PlumeDev* plumes;
     const TileDev* tiles;
     uint32_t ntiles;
+    int block;              // threads per workgroup
+    int lanes;              // lanes per target particle (1, 2 or 4)
+    int stage;              // LDS records staged per thread (0: read candidates from global memory)
+    int persistent;         // 0: one workgroup per work item; > 0: that many workgroups loop
+    const uint4* rec;       // candidate records (position + C of Cpair), or null: SoA reads
     const uint32_t* spos[3];
     const uint32_t* sid;
     const void* Cpair;      // concentrations entering C_a - C_b
@@ -71,6 +79,7 @@ struct PairLaunch {
     const int64_t* step;
     double scale;           // fraction of the plume's dt: step 1, half 0.5 (unused for rhs)
     void* out;              // half: S-order output; rhs: id-order output
+    uint4* out_rec;         // half: candidate records with the half-step C (S order)
 };
 
 // kernel launchers (kernels_*.hip); all return hipError_t of the launch

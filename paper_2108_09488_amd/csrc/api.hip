@@ -160,6 +160,8 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         d.H2d = Hu * Hu;
         d.H2f = (float)d.H2d;
         d.invHu = 1.0 / Hu;
+        d.Hc2f = (float)(Hc * Hc);
+        d.rowh2f = (float)((kTwo32 / nr) * (kTwo32 / nr));
 
         double D[9];
         const double trD = trace_D(pl.dim, q.alpha_L, q.alpha_T, q.D_m, q.v, D);
@@ -211,7 +213,7 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
 struct ade_ctx {
     Plan plan;
     hipStream_t stream = nullptr;
-    ade_tuning tuning{256, 0, 0, 0};
+    ade_tuning tuning{256, 2, 0, 0};
     PlumeDev* plumes = nullptr;
     TileDev* tiles = nullptr;
     StateArrays S{}, U{}, T{};
@@ -219,6 +221,7 @@ struct ade_ctx {
     uint32_t* cell_start = nullptr;
     void* scan_partial = nullptr;
     void* aux = nullptr;
+    uint4* aux_rec = nullptr;
     double* mass_partial = nullptr;
     int64_t* step = nullptr;
     uint32_t h_total = 0;  // host copy of N for the cell-start sentinel
@@ -226,6 +229,13 @@ struct ade_ctx {
     bool initialized = false, built = false;
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    bool capturing = false;
+    // pair-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
 };
 
 namespace {
@@ -239,6 +249,7 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
     for (int k = 0; k < 3; ++k) {
         StateArrays& s = *bufs[k];
         for (int d = 0; d < 3; ++d) s.pos[d] = (d < pl.dim) ? b.take<uint32_t>(N) : nullptr;
+        s.rec = (k == 0 && !(pl.dim == 3 && pl.real_bytes == 8)) ? b.take<uint4>(N) : nullptr;
         s.C = b.take_bytes(N * rb);
         s.id = b.take<uint32_t>(N);
         s.key = (k > 0) ? b.take<uint32_t>(N) : nullptr;
@@ -253,8 +264,45 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
     c->cell_start = b.take<uint32_t>(pl.ncell + 1);
     c->scan_partial = b.take_bytes((size_t)pl.nscan * 8);
     c->aux = b.take_bytes(N * rb);
+    c->aux_rec = (pl.dim == 3 && pl.real_bytes == 8) ? nullptr : b.take<uint4>(N);
     c->mass_partial = b.take<double>(pl.ntiles);
     c->step = b.take<int64_t>(1);
+}
+
+// Sum the recorded event pairs into the totals and recycle the events.
+int flush_events(ade_ctx* c) {
+    if (c->ev_used == 0) return ADE_OK;
+    HIPCHK(hipEventSynchronize(c->events[c->ev_used - 1]));
+    for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+        float ms = 0.f;
+        HIPCHK(hipEventElapsedTime(&ms, c->events[k], c->events[k + 1]));
+        c->timed_ms += ms;
+        c->timed_launches += 1;
+    }
+    c->ev_used = 0;
+    return ADE_OK;
+}
+
+// launch a pair kernel, bracketed by timing events when timing is on
+int run_pair(ade_ctx* c, int mode, const PairLaunch& a) {
+    const Plan& pl = c->plan;
+    const bool t = c->timing && !c->capturing;
+    if (t) {
+        if (c->ev_used + 2 > c->events.size()) {
+            if (c->events.size() < 4096) {
+                size_t old = c->events.size();
+                c->events.resize(old + 512);
+                for (size_t k = old; k < c->events.size(); ++k) HIPCHK(hipEventCreate(&c->events[k]));
+            } else {
+                int rc = flush_events(c);
+                if (rc) return rc;
+            }
+        }
+        HIPCHK(hipEventRecord(c->events[c->ev_used++], c->stream));
+    }
+    HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, mode, a, c->tuning.block, c->stream));
+    if (t) HIPCHK(hipEventRecord(c->events[c->ev_used++], c->stream));
+    return ADE_OK;
 }
 
 PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase, double scale, void* out) {
@@ -263,6 +311,13 @@ PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase,
     a.plumes = c->plumes;
     a.tiles = c->tiles;
     a.ntiles = c->plan.ntiles;
+    a.block = c->tuning.block;
+    a.lanes = c->tuning.lanes;
+    a.stage = c->tuning.stage_lds;
+    a.persistent = c->tuning.persistent;
+    // candidate records carrying the concentrations the pair sum reads
+    a.rec = (Cpair == c->aux) ? c->aux_rec : c->S.rec;
+    a.out_rec = c->aux_rec;
     for (int d = 0; d < 3; ++d) {
         a.spos[d] = c->S.pos[d];
         a.upos[d] = c->U.pos[d];
@@ -295,16 +350,23 @@ int enqueue_build(ade_ctx* c, int inc_step) {
 
 int enqueue_step(ade_ctx* c) {
     const Plan& pl = c->plan;
+    int rc;
     if (pl.integrator == ADE_PC) {
         PairLaunch h = pair_args(c, kModeHalf, c->S.C, c->S.C, 0.5, c->aux);
-        HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeHalf, h, c->tuning.block, c->stream));
+        if ((rc = run_pair(c, kModeHalf, h))) return rc;
         PairLaunch f = pair_args(c, kModeStep, c->aux, c->S.C, 1.0, nullptr);
-        HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeStep, f, c->tuning.block, c->stream));
+        if ((rc = run_pair(c, kModeStep, f))) return rc;
     } else {
         PairLaunch f = pair_args(c, kModeStep, c->S.C, c->S.C, 1.0, nullptr);
-        HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeStep, f, c->tuning.block, c->stream));
+        if ((rc = run_pair(c, kModeStep, f))) return rc;
     }
     return enqueue_build(c, 1);
+}
+
+void drop_events(ade_ctx* c) {
+    for (hipEvent_t e : c->events) hipEventDestroy(e);
+    c->events.clear();
+    c->ev_used = 0;
 }
 
 void drop_graph(ade_ctx* c) {
@@ -407,7 +469,9 @@ int ade_step_graph(ade_ctx* c, int64_t nsteps) {
     if (!c->stream) return fail(ADE_EINVAL, "graph capture needs a non-default stream");
     if (!c->graph_exec) {
         HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        c->capturing = true;
         int rc = enqueue_step(c);
+        c->capturing = false;
         hipGraph_t g = nullptr;
         hipError_t e = hipStreamEndCapture(c->stream, &g);
         if (rc) {
@@ -430,9 +494,9 @@ int ade_rhs(ade_ctx* c, void* d_rhs) {
     if (!c || !d_rhs) return fail(ADE_EINVAL, "null argument");
     if (!c->built) return fail(ADE_ESTATE, "ade_rhs before ade_build_cells");
     const Plan& pl = c->plan;
+    (void)pl;
     PairLaunch a = pair_args(c, kModeRhs, c->S.C, c->S.C, 1.0, d_rhs);
-    HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeRhs, a, c->tuning.block, c->stream));
-    return ADE_OK;
+    return run_pair(c, kModeRhs, a);
 }
 
 int ade_read_C(const ade_ctx* c, void* d_C_out) {
@@ -475,11 +539,33 @@ int ade_neighbours(ade_ctx* c, int64_t* d_offsets, int32_t* d_ids, int64_t cap, 
     return ADE_OK;
 }
 
+int ade_kernel_timing(ade_ctx* c, int32_t mode, double* h_ms, int64_t* h_count) {
+    if (!c) return fail(ADE_EINVAL, "null ctx");
+    if (mode == 1) {
+        int rc = flush_events(c);
+        if (rc) return rc;
+        c->timed_ms = 0.0;
+        c->timed_launches = 0;
+        c->timing = true;
+        return ADE_OK;
+    }
+    if (mode != 0) return fail(ADE_EINVAL, "mode must be 0 or 1");
+    int rc = flush_events(c);
+    if (rc) return rc;
+    c->timing = false;
+    if (h_ms) *h_ms = c->timed_ms;
+    if (h_count) *h_count = c->timed_launches;
+    return ADE_OK;
+}
+
 int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
     if (!c || !t) return fail(ADE_EINVAL, "null argument");
-    if (t->block != 64 && t->block != 128 && t->block != 256 && t->block != 512)
-        return fail(ADE_EINVAL, "block must be 64, 128, 256 or 512");
-    if (t->waves_per_eu < 0 || t->waves_per_eu > 8) return fail(ADE_EINVAL, "waves_per_eu in 0..8");
+    if (t->block != 64 && t->block != 128 && t->block != 256)
+        return fail(ADE_EINVAL, "block must be 64, 128 or 256");
+    if (t->lanes != 1 && t->lanes != 2 && t->lanes != 4) return fail(ADE_EINVAL, "lanes must be 1, 2 or 4");
+    if (t->stage_lds < 0 || (size_t)t->stage_lds * (size_t)t->block * 16u > 65536u)
+        return fail(ADE_EINVAL, "stage_lds * block * 16 bytes must fit in 64 KiB of LDS");
+    if (t->persistent < 0 || t->persistent > 65536) return fail(ADE_EINVAL, "persistent in 0..65536");
     c->tuning = *t;
     drop_graph(c);
     return ADE_OK;
@@ -513,6 +599,7 @@ int ade_destroy(ade_ctx* c) {
     if (c->stream) hipStreamSynchronize(c->stream);
     else hipDeviceSynchronize();
     drop_graph(c);
+    drop_events(c);
     delete c;
     return ADE_OK;
 }

@@ -172,10 +172,16 @@ __global__ __launch_bounds__(256) void k_canon(StateArrays T, StateArrays S,
     uint32_t rank = 0;
     for (uint32_t k = s; k < e; ++k) rank += (T.id[k] < my) ? 1u : 0u;
     const uint32_t d = s + rank;
+    uint32_t u[3] = {0u, 0u, 0u};
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) S.pos[c][d] = T.pos[c][j];
-    static_cast<real*>(S.C)[d] = static_cast<const real*>(T.C)[j];
+    for (int c = 0; c < DIM; ++c) {
+        u[c] = T.pos[c][j];
+        S.pos[c][d] = u[c];
+    }
+    const real C = static_cast<const real*>(T.C)[j];
+    static_cast<real*>(S.C)[d] = C;
     S.id[d] = my;
+    if (Rec<DIM, real>::kStageable) S.rec[d] = Rec<DIM, real>::pack(u[0], u[1], u[2], C);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,13 +16,27 @@
 // (u_a - u_b) per component (the two's-complement wrap is the minimum image),
 // converted to the working precision, r2 = d_x d_x, r2 = fma(d_y, d_y, r2)
 // [, r2 = fma(d_z, d_z, r2)], pair iff 0 < r2 <= H_u^2 (inclusive support).
+//
+// Candidates: particles are sorted by (row, x cell), rows being a grid of
+// height >= Hc / R in y (and z).  For each of the (2R+1)^(d-1) rows around a
+// target, the x cells that can hold neighbours form one contiguous range of
+// the sorted order (two at the periodic seam), cut to the chord of the
+// search radius at the row's nearest edge.  Each lane walks its ranges in
+// batches of kBatch candidate records, the next batch in flight while the
+// current one is evaluated, and the cell-start bounds of the next row in
+// flight while the current row is walked.  Optionally a workgroup first
+// stages the union of its candidate ranges in LDS (coalesced reads) and the
+// lanes walk the staged copy, falling back to global memory for a range
+// outside it.
 #include "ade_device.h"
 
 namespace ade {
 
 __device__ __forceinline__ float fmar(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmar(double a, double b, double c) { return __builtin_fma(a, b, c); }
-__device__ __forceinline__ float rsqrt_r(float x) { return rsqrtf(x); }
+// r2 >= 1 in grid units, so the hardware reciprocal square root needs no
+// denormal scaling
+__device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
 
 template <typename real>
@@ -30,83 +44,127 @@ __device__ __forceinline__ real h2_of(const PlumeDev& P) {
     return sizeof(real) == 4 ? (real)P.H2f : (real)P.H2d;
 }
 
-// Visit every particle b (sorted index) of the plume with 0 < r2 <= H_u^2
-// around the fixed-point position (ux, uy, uz).  Candidates: the rows within
-// R rows (y, and z in 3D) of the target's row, and in each row the x cells
-// covering [x - hx, x + hx]; each such cell range is contiguous in the sorted
-// order, so a row costs two loads of the cell-start table.
-template <int DIM, typename real, typename F>
-__device__ __forceinline__ void for_each_neighbour(const PlumeDev& P,
-                                                   const uint32_t* __restrict__ cs,
-                                                   const uint32_t* __restrict__ px,
-                                                   const uint32_t* __restrict__ py,
-                                                   const uint32_t* __restrict__ pz,
-                                                   uint32_t ux, uint32_t uy, uint32_t uz,
-                                                   F&& visit) {
-    const real H2 = h2_of<real>(P);
-    const int R = P.R;
-    const int nr = (int)P.nr;
-    const uint32_t nfx = P.nfx;
-    const int ry = (int)__umulhi(uy, P.nr);
-    const int rz = (DIM == 3) ? (int)__umulhi(uz, P.nr) : 0;
-    const uint32_t clo = __umulhi(ux - P.hx, nfx);
-    const uint32_t chi = __umulhi(ux + P.hx, nfx);
-    const bool wrapx = clo > chi;
+constexpr int kMaxRowOffsets = 81;  // (2R+1)^2 for R <= 4
+constexpr int kBatch = 4;           // candidate records fetched together before use
 
-    auto scan = [&](uint32_t s, uint32_t e) {
-        for (uint32_t b = s; b < e; ++b) {
-            const real dx = (real)(int32_t)(ux - px[b]);
-            const real dy = (real)(int32_t)(uy - py[b]);
-            const real dz = (DIM == 3) ? (real)(int32_t)(uz - pz[b]) : (real)0;
-            real r2 = dx * dx;
-            r2 = fmar(dy, dy, r2);
-            if (DIM == 3) r2 = fmar(dz, dz, r2);
-            if (r2 > (real)0 && r2 <= H2) visit(b, dx, dy, dz, r2);
-        }
-    };
+// A target particle: fixed-point position, its row and the fractional
+// position inside the row (in row heights, from the low word of u * nr).
+struct Target {
+    uint32_t ux, uy, uz;
+    int ry, rz;
+    float fy, fz;
+};
 
-    const int zlo = (DIM == 3) ? -R : 0, zhi = (DIM == 3) ? R : 0;
-    for (int oz = zlo; oz <= zhi; ++oz) {
-        int zz = rz + oz;
-        zz += (zz < 0) ? nr : 0;
-        zz -= (zz >= nr) ? nr : 0;
-        for (int oy = -R; oy <= R; ++oy) {
-            int yy = ry + oy;
-            yy += (yy < 0) ? nr : 0;
-            yy -= (yy >= nr) ? nr : 0;
-            const uint32_t row = P.cbase + ((uint32_t)zz * P.nr + (uint32_t)yy) * nfx;
-            const uint32_t s0 = cs[row + clo];
-            const uint32_t e0 = wrapx ? cs[row + nfx] : cs[row + chi + 1];
-            scan(s0, e0);
-            if (wrapx) scan(cs[row], cs[row + chi + 1]);
-        }
+template <int DIM>
+__device__ __forceinline__ Target make_target(const PlumeDev& P, uint32_t ux, uint32_t uy, uint32_t uz) {
+    Target t;
+    t.ux = ux;
+    t.uy = uy;
+    t.uz = uz;
+    t.ry = (int)__umulhi(uy, P.nr);
+    t.fy = (float)(uy * P.nr) * 2.3283064365386963e-10f;
+    if (DIM == 3) {
+        t.rz = (int)__umulhi(uz, P.nr);
+        t.fz = (float)(uz * P.nr) * 2.3283064365386963e-10f;
+    } else {
+        t.rz = 0;
+        t.fz = 0.f;
     }
+    return t;
 }
 
-template <int DIM, typename real, int KERN, int MODE>
-__global__ __launch_bounds__(kTile) void k_pair(PairLaunch a) {
-    const uint32_t tile = xcd_remap(blockIdx.x, gridDim.x);
-    const TileDev t = a.tiles[tile];
-    const PlumeDev& P = a.plumes[t.plume];
-    const uint32_t i = t.start + threadIdx.x;
-    if (i >= t.end) return;
+// Candidate cells of the neighbour row (oy, oz) of a target: the x window
+// [x - w, x + w], w being (an upper bound of) the chord of the search radius
+// at the row's nearest edge.  Returns false when the row lies beyond the
+// search radius.  k0 .. k1 (inclusive) is the first cell range and k2 .. k3
+// the second one, non-empty only when the window wraps around the periodic
+// seam (k2 > k3 marks it empty).  The bounds are conservative: the float
+// rounding of the distances is covered by relative slack on w^2 and an
+// absolute slack of 64 grid units on w.
+template <int DIM>
+__device__ __forceinline__ bool row_cells(const PlumeDev& P, const Target& T, int oy, int oz,
+                                          uint32_t& k0, uint32_t& k1, uint32_t& k2, uint32_t& k3) {
+    float dy = 0.f, dz = 0.f;
+    if (oy > 0) dy = (float)oy - T.fy;
+    else if (oy < 0) dy = (float)(-oy - 1) + T.fy;
+    if (DIM == 3) {
+        if (oz > 0) dz = (float)oz - T.fz;
+        else if (oz < 0) dz = (float)(-oz - 1) + T.fz;
+    }
+    const float d2 = (dy * dy + dz * dz) * P.rowh2f;
+    uint32_t w = P.hx;
+    if (d2 > 0.f) {
+        const float w2 = P.Hc2f * 1.000001f - d2 * 0.999999f;
+        if (w2 <= 0.f) return false;
+        const float wf = __builtin_amdgcn_sqrtf(w2) * 1.000001f + 64.0f;
+        w = wf < (float)P.hx ? (uint32_t)wf : P.hx;
+    }
+    const int nr = (int)P.nr;
+    int yy = T.ry + oy;
+    yy += (yy < 0) ? nr : 0;
+    yy -= (yy >= nr) ? nr : 0;
+    int zz = 0;
+    if (DIM == 3) {
+        zz = T.rz + oz;
+        zz += (zz < 0) ? nr : 0;
+        zz -= (zz >= nr) ? nr : 0;
+    }
+    const uint32_t nfx = P.nfx;
+    const uint32_t row = P.cbase + ((uint32_t)zz * P.nr + (uint32_t)yy) * nfx;
+    const uint32_t clo = __umulhi(T.ux - w, nfx);
+    const uint32_t chi = __umulhi(T.ux + w, nfx);
+    if (clo <= chi) {
+        k0 = row + clo;
+        k1 = row + chi;
+        k2 = 1u;
+        k3 = 0u;
+    } else {
+        k0 = row + clo;
+        k1 = row + nfx - 1u;
+        k2 = row;
+        k3 = row + chi;
+    }
+    return true;
+}
 
-    const uint32_t* __restrict__ px = a.spos[0];
-    const uint32_t* __restrict__ py = a.spos[1];
-    const uint32_t* __restrict__ pz = a.spos[2];
-    const real* __restrict__ Cp = static_cast<const real*>(a.Cpair);
+// Sorted-index ranges [s0, e0) and [s1, e1) of row number j (0 .. noff-1,
+// oy fastest) of a target; all empty when the row is out of reach.
+struct RowRanges {
+    uint32_t s0, e0, s1, e1;
+};
 
-    const uint32_t ux = px[i], uy = py[i], uz = (DIM == 3) ? pz[i] : 0u;
-    const real Ca = Cp[i];
-    const real invHu = (real)P.invHu;
-    const real kxx = (real)P.kg[0], kyy = (real)P.kg[1], kzz = (real)P.kg[2];
-    const real kxy = (real)P.kg[3], kxz = (real)P.kg[4], kyz = (real)P.kg[5];
-    const real trD = (real)P.trD;
-    real acc = (real)0;
+template <int DIM>
+__device__ __forceinline__ RowRanges row_ranges(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                                const Target& T, int j, int span) {
+    RowRanges r{0u, 0u, 0u, 0u};
+    const int R = P.R;
+    const int oy = j % span - R, oz = (DIM == 3) ? j / span - R : 0;
+    uint32_t k0, k1, k2, k3;
+    if (row_cells<DIM>(P, T, oy, oz, k0, k1, k2, k3)) {
+        r.s0 = cs[k0];
+        r.e0 = cs[k1 + 1];
+        if (k2 <= k3) {
+            r.s1 = cs[k2];
+            r.e1 = cs[k3 + 1];
+        }
+    }
+    return r;
+}
 
-    for_each_neighbour<DIM, real>(
-        P, a.cell_start, px, py, pz, ux, uy, uz,
-        [&](uint32_t b, real dx, real dy, real dz, real r2) {
+// One candidate: predicate and, if inside the support, the pair term.
+template <int DIM, typename real, int KERN>
+struct PairTerm {
+    real H2, invHu, kxx, kyy, kzz, kxy, kxz, kyz, trD;
+    __device__ __forceinline__ void operator()(const Target& T, real Ca, uint32_t bx, uint32_t by,
+                                               uint32_t bz, real Cb, real& acc) const {
+        const real dx = (real)(int32_t)(T.ux - bx);
+        const real dy = (real)(int32_t)(T.uy - by);
+        const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - bz) : (real)0;
+        const real dC = Ca - Cb;  // formed before the test: the whole record is fetched at once
+        real r2 = dx * dx;
+        r2 = fmar(dy, dy, r2);
+        if (DIM == 3) r2 = fmar(dz, dz, r2);
+        if (r2 > (real)0 && r2 <= H2) {
             const real rinv = rsqrt_r(r2);
             const real q = r2 * rinv * invHu;
             real omq = (real)1 - q;
@@ -124,8 +182,183 @@ __global__ __launch_bounds__(kTile) void k_pair(PairLaunch a) {
             else
                 Q = dx * (kxx * dx + kxy * dy) + kyy * dy * dy;
             const real A = Q * (rinv * rinv) - trD;
-            acc = fmar(A * f, Ca - Cp[b], acc);
-        });
+            acc = fmar(A * f, dC, acc);
+        }
+    }
+};
+
+template <typename real>
+struct Cand {
+    uint32_t x, y, z;
+    real C;
+};
+
+template <int DIM, typename real>
+__device__ __forceinline__ Cand<real> unpack(const uint4& r) {
+    return Cand<real>{r.x, r.y, (DIM == 3) ? r.z : 0u, Rec<DIM, real>::conc(r)};
+}
+
+// Walk the candidates b = s + lane, s + lane + LANES, ... < e in batches of
+// kBatch: the batch after the current one is fetched before the current one
+// is evaluated.  Past the end of the range a batch is padded with a record
+// half the box away from the target, which fails the predicate.
+template <int DIM, typename real, int KERN, int LANES, typename Fetch>
+__device__ __forceinline__ void walk_batched(const PairTerm<DIM, real, KERN>& term, const Target& T,
+                                             real Ca, uint32_t s, uint32_t e, uint32_t lj,
+                                             Fetch&& fetch, real& acc) {
+    uint32_t b = s + lj;
+    if (b >= e) return;
+    const Cand<real> pad{T.ux + 0x80000000u, T.uy, T.uz, Ca};
+    Cand<real> cur[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) {
+        const uint32_t bb = b + q * LANES;
+        cur[q] = (bb < e) ? fetch(bb) : pad;
+    }
+    for (;;) {
+        const uint32_t bn = b + kBatch * LANES;
+        const bool more = bn < e;
+        Cand<real> nxt[kBatch];
+        if (more) {
+#pragma unroll
+            for (int q = 0; q < kBatch; ++q) {
+                const uint32_t bb = bn + q * LANES;
+                nxt[q] = (bb < e) ? fetch(bb) : pad;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) term(T, Ca, cur[q].x, cur[q].y, cur[q].z, cur[q].C, acc);
+        if (!more) break;
+#pragma unroll
+        for (int q = 0; q < kBatch; ++q) cur[q] = nxt[q];
+        b = bn;
+    }
+}
+
+// One work item = `block / LANES` consecutive target particles of one tile.
+template <int DIM, typename real, int KERN, int MODE, int LANES>
+__device__ __forceinline__ void pair_item(const PairLaunch& a, uint32_t w, uint4* lds_rec,
+                                          uint32_t* o_lo, uint32_t* o_hi, uint32_t* o_base) {
+    const uint32_t tpb = (uint32_t)a.block / LANES;  // targets per workgroup
+    const uint32_t subs = kTile / tpb;
+    const TileDev t = a.tiles[w / subs];
+    const uint32_t i0 = t.start + (w % subs) * tpb;
+    if (i0 >= t.end) return;  // whole workgroup: ragged last tile
+    const uint32_t i1 = min(t.end, i0 + tpb);
+    const PlumeDev P = a.plumes[t.plume];
+    const uint32_t lt = threadIdx.x / LANES, lj = threadIdx.x % LANES;
+    const uint32_t i = i0 + lt;
+    const bool active = i < i1;
+
+    const uint32_t* __restrict__ px = a.spos[0];
+    const uint32_t* __restrict__ py = a.spos[1];
+    const uint32_t* __restrict__ pz = a.spos[2];
+    const real* __restrict__ Cp = static_cast<const real*>(a.Cpair);
+    const uint4* __restrict__ rec = a.rec;
+    const uint32_t* __restrict__ cs = a.cell_start;
+    const int R = P.R;
+    const int span = 2 * R + 1;
+    const int noff = (DIM == 3) ? span * span : span;
+    constexpr bool kRec = Rec<DIM, real>::kStageable;
+
+    // ---- stage the union of the workgroup's candidate ranges in LDS ----------
+    const bool stage = kRec && a.stage > 0;
+    if (stage) {
+        const uint32_t cap = (uint32_t)a.stage * (uint32_t)a.block;
+        __syncthreads();  // the previous item of a persistent workgroup is done with LDS
+        for (int o = threadIdx.x; o < noff; o += blockDim.x) {
+            const int oy = o % span - R, oz = (DIM == 3) ? o / span - R : 0;
+            const uint32_t fx = px[i0], lx = px[i1 - 1];
+            const int fy = (int)__umulhi(py[i0], P.nr), ly = (int)__umulhi(py[i1 - 1], P.nr);
+            const int fz = (DIM == 3) ? (int)__umulhi(pz[i0], P.nr) : 0;
+            const int lz = (DIM == 3) ? (int)__umulhi(pz[i1 - 1], P.nr) : 0;
+            const int nr = (int)P.nr;
+            uint32_t lo = 0, hi = 0;
+            const bool rows_ok = fz == lz && fy + oy >= 0 && ly + oy < nr &&
+                                 (DIM == 2 || (fz + oz >= 0 && fz + oz < nr));
+            const bool x_ok = fx >= P.hx && lx <= 0xffffffffu - P.hx;
+            if (rows_ok && x_ok) {
+                const int clo = (int)__umulhi(fx - P.hx, P.nfx) - 1;
+                const int chi = (int)__umulhi(lx + P.hx, P.nfx) + 1;
+                if (clo >= 0 && chi < (int)P.nfx) {
+                    const uint32_t zrow = (DIM == 3) ? (uint32_t)(fz + oz) * P.nr : 0u;
+                    const uint32_t klo = P.cbase + (zrow + (uint32_t)(fy + oy)) * P.nfx + (uint32_t)clo;
+                    const uint32_t khi = P.cbase + (zrow + (uint32_t)(ly + oy)) * P.nfx + (uint32_t)chi;
+                    if (klo <= khi) {
+                        lo = cs[klo];
+                        hi = cs[khi + 1];
+                    }
+                }
+            }
+            o_lo[o] = lo;
+            o_hi[o] = hi;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t run = 0;
+            for (int o = 0; o < noff; ++o) {
+                const uint32_t n = o_hi[o] - o_lo[o];
+                o_base[o] = run;
+                if (run + n > cap) o_hi[o] = o_lo[o];  // does not fit: that row reads global memory
+                else run += n;
+            }
+        }
+        __syncthreads();
+        for (int o = 0; o < noff; ++o) {
+            const uint32_t lo = o_lo[o], n = o_hi[o] - lo, base = o_base[o];
+            for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) lds_rec[base + j] = rec[lo + j];
+        }
+        __syncthreads();
+    }
+    if (!active) return;  // all LANES lanes of a target share `active`
+
+    const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
+    const real Ca = Cp[i];
+    PairTerm<DIM, real, KERN> term;
+    term.H2 = h2_of<real>(P);
+    term.invHu = (real)P.invHu;
+    term.kxx = (real)P.kg[0];
+    term.kyy = (real)P.kg[1];
+    term.kzz = (real)P.kg[2];
+    term.kxy = (real)P.kg[3];
+    term.kxz = (real)P.kg[4];
+    term.kyz = (real)P.kg[5];
+    term.trD = (real)P.trD;
+    real acc = (real)0;
+
+    auto walk = [&](int o, uint32_t s, uint32_t e) {
+        if (kRec) {
+            if (stage && s >= o_lo[o] && e <= o_hi[o]) {
+                const uint32_t shift = o_base[o] - o_lo[o];
+                walk_batched<DIM, real, KERN, LANES>(
+                    term, T, Ca, s + shift, e + shift, lj,
+                    [&](uint32_t k) { return unpack<DIM, real>(lds_rec[k]); }, acc);
+            } else {
+                walk_batched<DIM, real, KERN, LANES>(
+                    term, T, Ca, s, e, lj, [&](uint32_t k) { return unpack<DIM, real>(rec[k]); }, acc);
+            }
+        } else {
+            walk_batched<DIM, real, KERN, LANES>(
+                term, T, Ca, s, e, lj,
+                [&](uint32_t k) { return Cand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, Cp[k]}; },
+                acc);
+        }
+    };
+
+    // rows in order (oz major, oy minor); the cell-start bounds of the next
+    // row are in flight while the current row is walked
+    RowRanges cur = row_ranges<DIM>(P, cs, T, 0, span);
+    for (int j = 0; j < noff; ++j) {
+        RowRanges nxt{0u, 0u, 0u, 0u};
+        if (j + 1 < noff) nxt = row_ranges<DIM>(P, cs, T, j + 1, span);
+        walk(j, cur.s0, cur.e0);
+        if (cur.e1 > cur.s1) walk(j, cur.s1, cur.e1);
+        cur = nxt;
+    }
+    // wavefront reduction over the lanes of a target (fixed order: deterministic)
+    if (LANES >= 2) acc += __shfl_xor(acc, 1, kWave);
+    if (LANES >= 4) acc += __shfl_xor(acc, 2, kWave);
+    if (lj != 0) return;
 
     if (MODE == kModeRhs) {
         static_cast<real*>(a.out)[a.sid[i]] = (real)P.vphi * acc;
@@ -134,12 +367,14 @@ __global__ __launch_bounds__(kTile) void k_pair(PairLaunch a) {
     const real sc = (real)(a.scale * P.dt * P.vphi);
     const real Cb = static_cast<const real*>(a.Cbase)[i];
     if (MODE == kModeHalf) {
-        static_cast<real*>(a.out)[i] = fmar(sc, acc, Cb);
+        const real Ch = fmar(sc, acc, Cb);
+        static_cast<real*>(a.out)[i] = Ch;
+        if (kRec) a.out_rec[i] = Rec<DIM, real>::pack(T.ux, T.uy, T.uz, Ch);
         return;
     }
     // step: update C and x, hash the moved particle for the next build
     const int64_t k = *a.step;
-    uint32_t u[3] = {ux, uy, uz};
+    uint32_t u[3] = {T.ux, T.uy, T.uz};
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         const double us = P.ushift[c];
@@ -155,8 +390,27 @@ __global__ __launch_bounds__(kTile) void k_pair(PairLaunch a) {
     a.utick[i] = atomicAdd(&a.count[key], 1u);
 }
 
-// Neighbour-set export: fill = 0 writes the count of particle id at
-// offsets[id]; fill = 1 writes the ids from offsets[id] on.
+template <int DIM, typename real, int KERN, int MODE, int LANES>
+__global__ __launch_bounds__(256) void k_pair(PairLaunch a, uint32_t nwork) {
+    extern __shared__ uint4 lds_rec[];
+    __shared__ uint32_t o_lo[kMaxRowOffsets], o_hi[kMaxRowOffsets], o_base[kMaxRowOffsets];
+    if (a.persistent == 0) {
+        pair_item<DIM, real, KERN, MODE, LANES>(a, xcd_remap(blockIdx.x, gridDim.x), lds_rec, o_lo,
+                                                o_hi, o_base);
+        return;
+    }
+    // persistent grid: each workgroup takes every per_x-th item of a
+    // contiguous per-XCD share of the items (no queue, fixed assignment)
+    const uint32_t nx = 8, x = blockIdx.x % nx, k = blockIdx.x / nx;
+    const uint32_t per_x = (gridDim.x + nx - 1 - x) / nx;  // workgroups on this XCD
+    const uint32_t lo = (uint32_t)(((uint64_t)nwork * x) / nx), hi = (uint32_t)(((uint64_t)nwork * (x + 1)) / nx);
+    for (uint32_t w = lo + k; w < hi; w += per_x)
+        pair_item<DIM, real, KERN, MODE, LANES>(a, w, lds_rec, o_lo, o_hi, o_base);
+}
+
+// Neighbour-set export through the same candidate ranges and predicate:
+// fill = 0 writes the count of particle id at offsets[id]; fill = 1 writes
+// the ids from offsets[id] on.
 template <int DIM, typename real>
 __global__ __launch_bounds__(kTile) void k_nbr(const PlumeDev* __restrict__ plumes,
                                               const TileDev* __restrict__ tiles, StateArrays S,
@@ -164,49 +418,81 @@ __global__ __launch_bounds__(kTile) void k_nbr(const PlumeDev* __restrict__ plum
                                               int64_t* __restrict__ offsets,
                                               int32_t* __restrict__ ids) {
     const TileDev t = tiles[blockIdx.x];
-    const PlumeDev& P = plumes[t.plume];
+    const PlumeDev P = plumes[t.plume];
     const uint32_t i = t.start + threadIdx.x;
     if (i >= t.end) return;
     const uint32_t* px = S.pos[0];
     const uint32_t* py = S.pos[1];
     const uint32_t* pz = S.pos[2];
-    const uint32_t ux = px[i], uy = py[i], uz = (DIM == 3) ? pz[i] : 0u;
+    const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
     const uint32_t me = S.id[i];
+    const real H2 = h2_of<real>(P);
+    const int span = 2 * P.R + 1, noff = (DIM == 3) ? span * span : span;
     int64_t k = fill ? offsets[me] : 0;
-    for_each_neighbour<DIM, real>(P, cs, px, py, pz, ux, uy, uz,
-                                  [&](uint32_t b, real, real, real, real) {
-                                      if (fill) ids[k] = (int32_t)S.id[b];
-                                      ++k;
-                                  });
+    auto walk = [&](uint32_t s, uint32_t e) {
+        for (uint32_t b = s; b < e; ++b) {
+            const real dx = (real)(int32_t)(T.ux - px[b]);
+            const real dy = (real)(int32_t)(T.uy - py[b]);
+            const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - pz[b]) : (real)0;
+            real r2 = dx * dx;
+            r2 = fmar(dy, dy, r2);
+            if (DIM == 3) r2 = fmar(dz, dz, r2);
+            if (r2 > (real)0 && r2 <= H2) {
+                if (fill) ids[k] = (int32_t)S.id[b];
+                ++k;
+            }
+        }
+    };
+    for (int j = 0; j < noff; ++j) {
+        const RowRanges r = row_ranges<DIM>(P, cs, T, j, span);
+        walk(r.s0, r.e0);
+        if (r.e1 > r.s1) walk(r.s1, r.e1);
+    }
     if (!fill) offsets[me] = k;
 }
 
+template <int DIM, typename real, int KERN, int LANES>
+static void launch_pair_l(int mode, const PairLaunch& a, hipStream_t s) {
+    const uint32_t tpb = (uint32_t)a.block / LANES;
+    const uint32_t nwork = a.ntiles * (kTile / tpb);
+    PairLaunch c = a;
+    if (nwork < 8) c.persistent = 0;  // a persistent grid needs a workgroup on every XCD
+    const uint32_t grid = (c.persistent > 0) ? max(8u, min(nwork, (uint32_t)c.persistent)) : nwork;
+    dim3 g(grid), b(a.block);
+    const size_t shm = (Rec<DIM, real>::kStageable && a.stage > 0)
+                           ? sizeof(uint4) * (size_t)a.stage * (size_t)a.block : 0;
+    if (mode == kModeStep) hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeStep, LANES>), g, b, shm, s, c, nwork);
+    else if (mode == kModeHalf) hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeHalf, LANES>), g, b, shm, s, c, nwork);
+    else hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeRhs, LANES>), g, b, shm, s, c, nwork);
+}
+
 template <int DIM, typename real, int KERN>
-static void launch_pair_t(int mode, const PairLaunch& a, int block, hipStream_t s) {
-    (void)block;
-    dim3 g(a.ntiles), b(kTile);
-    if (mode == kModeStep) hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeStep>), g, b, 0, s, a);
-    else if (mode == kModeHalf) hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeHalf>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeRhs>), g, b, 0, s, a);
+static void launch_pair_t(int mode, const PairLaunch& a, hipStream_t s) {
+    if (a.lanes == 4) launch_pair_l<DIM, real, KERN, 4>(mode, a, s);
+    else if (a.lanes == 2) launch_pair_l<DIM, real, KERN, 2>(mode, a, s);
+    else launch_pair_l<DIM, real, KERN, 1>(mode, a, s);
 }
 
 hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const PairLaunch& a,
                        int block, hipStream_t s) {
+    (void)block;
+    if (a.block <= 0 || a.block > kTile || kTile % a.block != 0) return hipErrorInvalidValue;
+    if (a.lanes != 1 && a.lanes != 2 && a.lanes != 4) return hipErrorInvalidValue;
     if (dim == 2) {
         if (real_bytes == 4) {
-            if (kernel == 4) launch_pair_t<2, float, 4>(mode, a, block, s);
-            else launch_pair_t<2, float, 2>(mode, a, block, s);
+            if (kernel == 4) launch_pair_t<2, float, 4>(mode, a, s);
+            else launch_pair_t<2, float, 2>(mode, a, s);
         } else {
-            if (kernel == 4) launch_pair_t<2, double, 4>(mode, a, block, s);
-            else launch_pair_t<2, double, 2>(mode, a, block, s);
+            if (kernel == 4) launch_pair_t<2, double, 4>(mode, a, s);
+            else launch_pair_t<2, double, 2>(mode, a, s);
         }
     } else {
         if (real_bytes == 4) {
-            if (kernel == 4) launch_pair_t<3, float, 4>(mode, a, block, s);
-            else launch_pair_t<3, float, 2>(mode, a, block, s);
+            if (kernel == 4) launch_pair_t<3, float, 4>(mode, a, s);
+            else launch_pair_t<3, float, 2>(mode, a, s);
         } else {
-            if (kernel == 4) launch_pair_t<3, double, 4>(mode, a, block, s);
-            else launch_pair_t<3, double, 2>(mode, a, block, s);
+            if (kernel == 4) launch_pair_t<3, double, 4>(mode, a, s);
+            else launch_pair_t<3, double, 2>(mode, a, s);
         }
     }
     return hipGetLastError();
