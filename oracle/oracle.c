@@ -703,36 +703,47 @@ static void sensor_interp_T(const or_model *m, int64_t n, const double *x, int64
 
 /* ------------------------------------------------------------------------- */
 /* Transposed operator: with rhs = L C written as rhs_a = sum_b w_ab (C_a - C_b) */
-/* (+ the convective part, zero for uniform v), returns y = L^T lam, i.e.       */
-/* y_a += w_ab lam_a and y_b -= w_ab lam_a for every pair (a, b).              */
-/* Uniform velocity only.                                                     */
+/* (+ the convective part, zero for uniform v), returns y = L^T lam, evaluated */
+/* entry by entry (row b of L^T at a time).  Uniform velocity only.            */
 /* ------------------------------------------------------------------------- */
-typedef struct {
-    const or_model *m;
-    int64_t n, a;
-    const double *mass, *rho, *h;
-    double *wlist;      /* weights w_ab in visiting order */
-    int32_t *blist;
-    int64_t k;
-} wt_ctx;
-
-static void weight_visit(int64_t b, const double *xab, double r2, void *vctx)
+/* Weight w_ij of the pair (i, j) in row i of the operator, for the separation
+ * x_ij (r2 = |x_ij|^2): the dispersion term of Eq. (4) for particle i reads
+ * sum_j w_ij (C_i - C_j) with
+ *   w_ij = 1/2 (m_j / rhobar_ij) Dcal_ij x_ij . grad_i W_ij / |x_ij|^2. */
+static double pair_weight(const or_model *m, const double *mass, const double *rho,
+                          const double *h, int64_t i, int64_t j, const double *xij, double r2)
 {
-    wt_ctx *c = (wt_ctx *)vctx;
-    const or_model *m = c->m;
     int dim = m->dim;
     double r = sqrt(r2);
     double dWdr = or_kernel_dWdr(m->kernel, dim, m->H, r);
     double xdotgrad = 0.0;
-    for (int i = 0; i < dim; ++i) xdotgrad += xab[i] * dWdr * xab[i] / r;
-    double rhobar = 0.5 * (c->rho[c->a] + c->rho[b]);
+    for (int k = 0; k < dim; ++k) xdotgrad += xij[k] * dWdr * xij[k] / r;
+    double rhobar = 0.5 * (rho[i] + rho[j]);
     double Dcal = 0.0;
-    for (int i = 0; i < dim; ++i)
-        for (int j = 0; j < dim; ++j)
-            Dcal += c->h[i * dim + j] * (m->gamma * xab[i] * xab[j] / r2 - (i == j ? 1.0 : 0.0));
-    c->wlist[c->k] = 0.5 * c->mass[b] / rhobar * Dcal / r2 * xdotgrad;
-    c->blist[c->k] = (int32_t)b;
-    c->k++;
+    for (int k = 0; k < dim; ++k)
+        for (int l = 0; l < dim; ++l)
+            Dcal += h[k * dim + l] * (m->gamma * xij[k] * xij[l] / r2 - (k == l ? 1.0 : 0.0));
+    return 0.5 * mass[j] / rhobar * Dcal / r2 * xdotgrad;
+}
+
+typedef struct {
+    const or_model *m;
+    int64_t b;
+    const double *mass, *rho, *h, *lam;
+    double y;
+} lt_ctx;
+
+/* For row b of L^T: with L_aa = sum_j w_aj and L_ab = -w_ab (a != b),
+ * (L^T lam)_b = sum_a L_ab lam_a = (sum_a w_ba) lam_b - sum_{a != b} w_ab lam_a,
+ * visiting every neighbour a of b. */
+static void lt_visit(int64_t a, const double *xba, double r2, void *vctx)
+{
+    lt_ctx *c = (lt_ctx *)vctx;
+    double xab[3];
+    for (int k = 0; k < c->m->dim; ++k) xab[k] = -xba[k];
+    double w_ba = pair_weight(c->m, c->mass, c->rho, c->h, c->b, a, xba, r2);
+    double w_ab = pair_weight(c->m, c->mass, c->rho, c->h, a, c->b, xab, r2);
+    c->y += w_ba * c->lam[c->b] - w_ab * c->lam[a];
 }
 
 static void apply_LT(const or_model *m, int64_t n, const double *x, const double *mass,
@@ -740,21 +751,14 @@ static void apply_LT(const or_model *m, int64_t n, const double *x, const double
 {
     or_cells cl;
     cells_build(m, n, x, &cl);
-    memset(y, 0, sizeof(double) * n);
-    double *wl = (double *)malloc(sizeof(double) * n);
-    int32_t *bl = (int32_t *)malloc(sizeof(int32_t) * n);
-    for (int64_t a = 0; a < n; ++a) {
-        wt_ctx c = {m, n, a, mass, rho, h, wl, bl, 0};
-        double xa[3];
-        for (int i = 0; i < m->dim; ++i) xa[i] = x[i * n + a];
-        for_neighbours(m, n, x, &cl, xa, a, weight_visit, &c);
-        for (int64_t k = 0; k < c.k; ++k) {
-            y[a] += wl[k] * lam[a];
-            y[bl[k]] -= wl[k] * lam[a];
-        }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = 0; b < n; ++b) {
+        lt_ctx c = {m, b, mass, rho, h, lam, 0.0};
+        double xb[3];
+        for (int i = 0; i < m->dim; ++i) xb[i] = x[i * n + b];
+        for_neighbours(m, n, x, &cl, xb, b, lt_visit, &c);
+        y[b] = c.y;
     }
-    free(wl);
-    free(bl);
     cells_free(&cl);
 }
 

@@ -201,3 +201,37 @@ def workspace_bytes(params, counts) -> int:
     nb = ct.c_size_t(0)
     check(lib().ade_workspace_bytes(arr, cn, len(ps), ct.byref(nb)))
     return nb.value
+
+
+class ADEMisfit(torch.autograd.Function):
+    """J(theta) = sum_s (C_s(T) - d_s)^2 for theta = (alpha_L, alpha_T, D_m),
+    with its gradient from the library's discrete adjoint (ade_adjoint).
+
+    problem: dict with keys spec (PlumeSpec of the plume), x0 (float64 (dim, N)
+    positions), C0 (initial concentrations), xs (float64 (dim, S) sensor
+    points), obs (S observations), nsteps, ckpt_every, and optionally device.
+    The forward pass runs the adjoint too and keeps the gradient for backward.
+    """
+
+    @staticmethod
+    def forward(ctx, theta, problem):
+        import copy
+        spec = copy.copy(problem["spec"])
+        th = theta.detach().to("cpu", torch.float64)
+        spec.alpha_L, spec.alpha_T, spec.D_m = float(th[0]), float(th[1]), float(th[2])
+        dev = problem.get("device", "cuda:0")
+        x0 = torch.as_tensor(problem["x0"], dtype=torch.float64)
+        c = Context([params_from_spec(spec)], [x0.shape[1]], device=dev)
+        try:
+            c.init(x0, torch.as_tensor(problem["C0"])).build()
+            J, g = c.adjoint(problem["nsteps"], problem["ckpt_every"], torch.as_tensor(problem["xs"]),
+                             torch.as_tensor(problem["obs"]))
+        finally:
+            c.close()
+        ctx.save_for_backward(torch.tensor(g, dtype=torch.float64))
+        return torch.tensor(J, dtype=torch.float64)
+
+    @staticmethod
+    def backward(ctx, gJ):
+        (g,) = ctx.saved_tensors
+        return gJ * g.to(gJ.device), None

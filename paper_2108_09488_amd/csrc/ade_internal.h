@@ -35,6 +35,7 @@ struct PlumeDev {
     double vphi;            // V * (kernel derivative prefactor): rhs = vphi * sum
     double dt;
     double ushift[3];       // displacement per step in grid units
+    double vel[3];          // flow velocity (physical units)
     double mass;            // particle mass
     double L;
 };

@@ -1,13 +1,519 @@
-// adjoint.hip -- sensors and the discrete adjoint (filled in below).
-#include <hip/hip_runtime.h>
+// adjoint.hip -- sensor interpolation and the discrete adjoint of the explicit
+// SPH advection-dispersion step (Klapp et al., arXiv:2108.09488, Eqs. 3-5),
+// giving dJ/d(alpha_L, alpha_T, D_m) for the misfit J = sum_s (C_s - d_s)^2.
+//
+// With rhs = L C and the explicit step C^{n+1} = C^n + dt L^n C^n,
+//     lambda^N = dJ/dC^N,  lambda^n = lambda^{n+1} + dt (L^n)^T lambda^{n+1},
+//     dJ/dtheta_k = sum_n dt lambda^{n+1} . (dL^n/dtheta_k) C^n.
+// For equal particle volumes and a uniform tensor the pair weights are
+// symmetric (w_ab = w_ba), so (L^n)^T = L^n: the adjoint kernel applies the
+// same pair sum to lambda.  L depends on theta only through D (Eq. 3), which
+// is linear in theta: dD/dalpha_L = v v^T/|v|, dD/dalpha_T = |v| I - v v^T/|v|,
+// dD/dD_m = I.  With p = (x_ab . v)^2 / (|v|^2 r^2) the factor
+// A = Gamma x^T M x / r^2 - tr M of the pair term becomes
+//     alpha_L: |v| (Gamma p - 1),  alpha_T: |v| (Gamma (1 - p) - (d - 1)),
+//     D_m: Gamma - d.
+// The forward states are recomputed from checkpoints segment by segment
+// (the cell build and the pair sums are deterministic, so the recompute is
+// bit-identical to the forward run), and the gradient is accumulated in FP64
+// per workgroup in a fixed order.
+//
+// Sensors: Shepard interpolation C_s = sum_b W(r_sb) C_b / sum_b W(r_sb) with
+// the kernel of Eq. (7) (its normalisation cancels); its transpose seeds
+// lambda^N = sum_s 2 (C_s - d_s) W(r_sb) / sum_b' W(r_sb').
+#include <algorithm>
+#include <cmath>
 
-#include "../../include/adesph.h"
+#include "ade_geom.h"
+#include "ctx.h"
+
+namespace ade {
+
+// Kernel shape of Eq. (7) without its normalisation, as a function of q = r / H.
+template <typename real, int KERN>
+__device__ __forceinline__ real kernel_shape(real q) {
+    real omq = (real)1 - q;
+    omq = omq > (real)0 ? omq : (real)0;
+    const real o2 = omq * omq;
+    if (KERN == 4) return o2 * o2 * o2 * fmar(q, fmar((real)(35.0 / 3.0), q, (real)6), (real)1);
+    return o2 * o2 * fmar((real)4, q, (real)1);
+}
+
+template <int DIM>
+__device__ __forceinline__ uint32_t to_fixed(double x, double L) {
+    return (uint32_t)(int64_t)rint((x / L) * 4294967296.0);
+}
+
+// ---------------------------------------------------------------------------
+// sensors
+// ---------------------------------------------------------------------------
+template <int DIM, typename real, int KERN>
+__global__ __launch_bounds__(256) void k_sensor_fwd(const PlumeDev* __restrict__ plumes,
+                                                   const double* __restrict__ xs, int ns,
+                                                   StateArrays S, const uint32_t* __restrict__ cs,
+                                                   real* __restrict__ pred, real* __restrict__ den) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= ns) return;
+    const PlumeDev P = plumes[0];
+    uint32_t u[3] = {0u, 0u, 0u};
+    for (int c = 0; c < DIM; ++c) u[c] = to_fixed<DIM>(xs[(size_t)c * ns + s], P.L);
+    const Target T = make_target<DIM>(P, u[0], u[1], u[2]);
+    const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
+    const uint32_t* px = S.pos[0];
+    const uint32_t* py = S.pos[1];
+    const uint32_t* pz = S.pos[2];
+    const real* C = static_cast<const real*>(S.C);
+    const int span = 2 * P.R + 1, noff = (DIM == 3) ? span * span : span;
+    real num = 0, dsum = 0;
+    for (int j = 0; j < noff; ++j) {
+        const RowRanges r = row_ranges<DIM>(P, cs, T, j, span);
+        for (int part = 0; part < 2; ++part) {
+            const uint32_t b0 = part ? r.s1 : r.s0, b1 = part ? r.e1 : r.e0;
+            for (uint32_t b = b0; b < b1; ++b) {
+                const real dx = (real)(int32_t)(T.ux - px[b]);
+                const real dy = (real)(int32_t)(T.uy - py[b]);
+                const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - pz[b]) : (real)0;
+                real r2 = dx * dx;
+                r2 = fmar(dy, dy, r2);
+                if (DIM == 3) r2 = fmar(dz, dz, r2);
+                if (r2 <= H2) {
+                    const real w = kernel_shape<real, KERN>(sqrt(r2) * invHu);
+                    num = fmar(w, C[b], num);
+                    dsum += w;
+                }
+            }
+        }
+    }
+    pred[s] = dsum > (real)0 ? num / dsum : (real)0;
+    if (den) den[s] = dsum;
+}
+
+// residual weights r_s = 2 (C_s - d_s) / sum_b W_sb and J (FP64, fixed order)
+template <typename real>
+__global__ __launch_bounds__(256) void k_sensor_resid(int ns, const real* __restrict__ pred,
+                                                     const real* __restrict__ den,
+                                                     const real* __restrict__ obs,
+                                                     real* __restrict__ rw, double* __restrict__ J) {
+    __shared__ double lds[256 / kWave];
+    double acc = 0.0;
+    for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+        const double d = (double)pred[s] - (double)obs[s];
+        acc += d * d;
+        rw[s] = den[s] > (real)0 ? (real)(2.0 * d / (double)den[s]) : (real)0;
+    }
+    acc = block_sum(acc, lds);
+    if (threadIdx.x == 0) *J = acc;
+}
+
+// lambda^N[id_b] = sum_s r_s W(r_sb), sensors staged through LDS in chunks
+template <int DIM, typename real, int KERN>
+__global__ __launch_bounds__(256) void k_sensor_seed(const PlumeDev* __restrict__ plumes,
+                                                    const double* __restrict__ xs, int ns,
+                                                    const real* __restrict__ rw, StateArrays S,
+                                                    uint32_t N, real* __restrict__ lam) {
+    __shared__ uint32_t su[256][3];
+    __shared__ real sr[256];
+    const PlumeDev P = plumes[0];
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = i < N;
+    uint32_t u[3] = {0u, 0u, 0u};
+    if (active)
+        for (int c = 0; c < DIM; ++c) u[c] = S.pos[c][i];
+    const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
+    real acc = 0;
+    for (int s0 = 0; s0 < ns; s0 += 256) {
+        __syncthreads();
+        const int s = s0 + threadIdx.x;
+        if (s < ns) {
+            for (int c = 0; c < DIM; ++c) su[threadIdx.x][c] = to_fixed<DIM>(xs[(size_t)c * ns + s], P.L);
+            sr[threadIdx.x] = rw[s];
+        }
+        __syncthreads();
+        const int cnt = min(256, ns - s0);
+        if (active) {
+            for (int k = 0; k < cnt; ++k) {
+                // separation sensor - particle, as in the forward interpolation
+                const real dx = (real)(int32_t)(su[k][0] - u[0]);
+                const real dy = (real)(int32_t)(su[k][1] - u[1]);
+                const real dz = (DIM == 3) ? (real)(int32_t)(su[k][2] - u[2]) : (real)0;
+                real r2 = dx * dx;
+                r2 = fmar(dy, dy, r2);
+                if (DIM == 3) r2 = fmar(dz, dz, r2);
+                if (r2 <= H2) acc = fmar(sr[k], kernel_shape<real, KERN>(sqrt(r2) * invHu), acc);
+            }
+        }
+    }
+    if (active) lam[S.id[i]] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// adjoint step
+// ---------------------------------------------------------------------------
+template <typename real>
+__global__ __launch_bounds__(256) void k_gather_sorted(const uint32_t* __restrict__ id,
+                                                      const real* __restrict__ src, uint32_t N,
+                                                      real* __restrict__ dst) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N) dst[i] = src[id[i]];
+}
+
+struct AdjConst {
+    double vhat[3];  // unit flow direction (0 if |v| = 0)
+    double speed;    // |v|
+};
+
+template <int DIM, typename real, int KERN>
+__global__ __launch_bounds__(kTile) void k_adjoint(const PlumeDev* __restrict__ plumes,
+                                                  const TileDev* __restrict__ tiles, StateArrays S,
+                                                  const uint32_t* __restrict__ cs,
+                                                  const real* __restrict__ lam_s,
+                                                  real* __restrict__ lam_out, AdjConst ac,
+                                                  double* __restrict__ gpart) {
+    __shared__ double lds[kTile / kWave];
+    const TileDev t = tiles[blockIdx.x];
+    const PlumeDev P = plumes[t.plume];
+    const uint32_t i = t.start + threadIdx.x;
+    const bool active = i < t.end;
+    const uint32_t* px = S.pos[0];
+    const uint32_t* py = S.pos[1];
+    const uint32_t* pz = S.pos[2];
+    const real* C = static_cast<const real*>(S.C);
+    const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
+    const real kxx = (real)P.kg[0], kyy = (real)P.kg[1], kzz = (real)P.kg[2];
+    const real kxy = (real)P.kg[3], kxz = (real)P.kg[4], kyz = (real)P.kg[5];
+    const real trD = (real)P.trD;
+    const real gam = (real)(DIM + 2), spd = (real)ac.speed;
+    const real vx = (real)ac.vhat[0], vy = (real)ac.vhat[1], vz = (real)ac.vhat[2];
+    real al = 0, g1 = 0, g2 = 0, g3 = 0, li = 0;
+    if (active) {
+        const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
+        const real Ci = C[i];
+        li = lam_s[i];
+        const int span = 2 * P.R + 1, noff = (DIM == 3) ? span * span : span;
+        for (int j = 0; j < noff; ++j) {
+            const RowRanges r = row_ranges<DIM>(P, cs, T, j, span);
+            for (int part = 0; part < 2; ++part) {
+                const uint32_t b0 = part ? r.s1 : r.s0, b1 = part ? r.e1 : r.e0;
+                for (uint32_t b = b0; b < b1; ++b) {
+                    const real dx = (real)(int32_t)(T.ux - px[b]);
+                    const real dy = (real)(int32_t)(T.uy - py[b]);
+                    const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - pz[b]) : (real)0;
+                    real r2 = dx * dx;
+                    r2 = fmar(dy, dy, r2);
+                    if (DIM == 3) r2 = fmar(dz, dz, r2);
+                    if (r2 > (real)0 && r2 <= H2) {
+                        const real rinv = (real)1 / sqrt(r2);
+                        const real q = r2 * rinv * invHu;
+                        real omq = (real)1 - q;
+                        omq = omq > (real)0 ? omq : (real)0;
+                        real f;
+                        if (KERN == 4) {
+                            const real o2 = omq * omq;
+                            f = o2 * o2 * omq * fmar((real)5, q, (real)1);
+                        } else {
+                            f = omq * omq * omq;
+                        }
+                        real Q;
+                        if (DIM == 3)
+                            Q = dx * (kxx * dx + kxy * dy + kxz * dz) + dy * (kyy * dy + kyz * dz) + kzz * dz * dz;
+                        else
+                            Q = dx * (kxx * dx + kxy * dy) + kyy * dy * dy;
+                        const real ir2 = rinv * rinv;
+                        const real A = Q * ir2 - trD;
+                        const real xv = dx * vx + dy * vy + dz * vz;
+                        const real p = xv * xv * ir2;
+                        const real dCf = (Ci - C[b]) * f;
+                        al = fmar(A * f, li - lam_s[b], al);
+                        g1 = fmar(spd * (gam * p - (real)1), dCf, g1);
+                        g2 = fmar(spd * (gam * ((real)1 - p) - (real)(DIM - 1)), dCf, g2);
+                        g3 += (gam - (real)DIM) * dCf;
+                    }
+                }
+            }
+        }
+        const real s = (real)(P.dt * P.vphi);
+        lam_out[S.id[i]] = fmar(s, al, li);
+    }
+    // per-workgroup gradient partials, accumulated over the steps in FP64
+    const double s = P.dt * P.vphi;
+    const double c1 = block_sum(active ? s * (double)li * (double)g1 : 0.0, lds);
+    const double c2 = block_sum(active ? s * (double)li * (double)g2 : 0.0, lds);
+    const double c3 = block_sum(active ? s * (double)li * (double)g3 : 0.0, lds);
+    if (threadIdx.x == 0) {
+        gpart[3 * blockIdx.x + 0] += c1;
+        gpart[3 * blockIdx.x + 1] += c2;
+        gpart[3 * blockIdx.x + 2] += c3;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ gpart, uint32_t nb,
+                                                    double* __restrict__ out) {
+    __shared__ double lds[256 / kWave];
+    for (int k = 0; k < 3; ++k) {
+        double s = 0.0;
+        for (uint32_t b = threadIdx.x; b < nb; b += blockDim.x) s += gpart[3 * b + k];
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) out[k] = s;
+    }
+}
+
+namespace {
+
+#define ADE_DISPATCH3(dim, rb, kern, CALL)                              \
+    do {                                                                \
+        if (dim == 2 && rb == 4 && kern == 4) { CALL(2, float, 4); }    \
+        else if (dim == 2 && rb == 4) { CALL(2, float, 2); }            \
+        else if (dim == 2 && kern == 4) { CALL(2, double, 4); }         \
+        else if (dim == 2) { CALL(2, double, 2); }                      \
+        else if (rb == 4 && kern == 4) { CALL(3, float, 4); }           \
+        else if (rb == 4) { CALL(3, float, 2); }                        \
+        else if (kern == 4) { CALL(3, double, 4); }                     \
+        else { CALL(3, double, 2); }                                    \
+    } while (0)
+
+// One state snapshot: the sorted particle state and its cell table.
+struct Snap {
+    uint32_t* pos[3];
+    void* C;
+    uint32_t* id;
+    uint4* rec;
+    uint32_t* cs;
+    int64_t* step;
+};
+
+struct AdjLayout {
+    size_t bytes = 0;
+    std::vector<Snap> ck;   // checkpoints (every K steps, plus the final state)
+    std::vector<Snap> seg;  // states of one segment
+    void* lam[2];
+    void* lam_s;
+    void* pred;
+    void* den;
+    void* rw;
+    double* J;
+    double* gpart;
+    double* grad;
+};
+
+void take_snap(char* base, size_t& off, const ade_ctx* c, Snap& s) {
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) & ~size_t(255);
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const Plan& pl = c->plan;
+    const size_t N = (size_t)pl.N;
+    for (int d = 0; d < 3; ++d) s.pos[d] = (d < pl.dim) ? (uint32_t*)take(N * 4) : nullptr;
+    s.C = take(N * pl.real_bytes);
+    s.id = (uint32_t*)take(N * 4);
+    s.rec = c->S.rec ? (uint4*)take(N * 16) : nullptr;
+    s.cs = (uint32_t*)take((pl.ncell + 1) * 4);
+    s.step = (int64_t*)take(8);
+}
+
+void adj_layout(const ade_ctx* c, int64_t nsteps, int32_t K, int32_t ns, char* base, AdjLayout& L) {
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char* {
+        off = (off + 255) & ~size_t(255);
+        char* p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    };
+    const Plan& pl = c->plan;
+    const int64_t nck = (nsteps + K - 1) / K + 1;
+    L.ck.resize((size_t)nck);
+    L.seg.resize((size_t)K);
+    for (auto& s : L.ck) take_snap(base, off, c, s);
+    for (auto& s : L.seg) take_snap(base, off, c, s);
+    const size_t N = (size_t)pl.N, rb = (size_t)pl.real_bytes;
+    L.lam[0] = take(N * rb);
+    L.lam[1] = take(N * rb);
+    L.lam_s = take(N * rb);
+    L.pred = take((size_t)ns * rb);
+    L.den = take((size_t)ns * rb);
+    L.rw = take((size_t)ns * rb);
+    L.J = (double*)take(8);
+    L.gpart = (double*)take((size_t)pl.ntiles * 3 * 8);
+    L.grad = (double*)take(3 * 8);
+    L.bytes = off + 256;
+}
+
+int copy_state(const ade_ctx* c, const Snap& dst, const Snap& src) {
+    const Plan& pl = c->plan;
+    const size_t N = (size_t)pl.N;
+    hipStream_t st = c->stream;
+    for (int d = 0; d < pl.dim; ++d)
+        HIPCHK(hipMemcpyAsync(dst.pos[d], src.pos[d], N * 4, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(dst.C, src.C, N * pl.real_bytes, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(dst.id, src.id, N * 4, hipMemcpyDeviceToDevice, st));
+    if (dst.rec && src.rec) HIPCHK(hipMemcpyAsync(dst.rec, src.rec, N * 16, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(dst.cs, src.cs, (pl.ncell + 1) * 4, hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(dst.step, src.step, 8, hipMemcpyDeviceToDevice, st));
+    return ADE_OK;
+}
+
+Snap live(ade_ctx* c) {
+    Snap s;
+    for (int d = 0; d < 3; ++d) s.pos[d] = c->S.pos[d];
+    s.C = c->S.C;
+    s.id = c->S.id;
+    s.rec = c->S.rec;
+    s.cs = c->cell_start;
+    s.step = c->step;
+    return s;
+}
+
+StateArrays snap_arrays(const ade_ctx* c, const Snap& s) {
+    StateArrays a = c->S;
+    for (int d = 0; d < 3; ++d) a.pos[d] = s.pos[d] ? s.pos[d] : s.pos[0];
+    a.C = s.C;
+    a.id = s.id;
+    a.rec = s.rec;
+    return a;
+}
+
+int check_sensor_args(const ade_ctx* c, const double* d_xs, int32_t ns) {
+    if (!c) return fail(ADE_EINVAL, "null ctx");
+    if (!d_xs || ns <= 0) return fail(ADE_EINVAL, "sensors: null positions or n_sensors <= 0");
+    if (c->plan.P != 1) return fail(ADE_EINVAL, "sensors and the adjoint need a single-plume context");
+    if (!c->built) return fail(ADE_ESTATE, "cells not built");
+    return ADE_OK;
+}
+
+int launch_sensor_fwd(ade_ctx* c, const double* d_xs, int32_t ns, const StateArrays& S,
+                      const uint32_t* cs, void* pred, void* den) {
+    const Plan& pl = c->plan;
+    dim3 g((ns + 255) / 256), b(256);
+#define CALL(D, R, K)                                                                        \
+    hipLaunchKernelGGL((k_sensor_fwd<D, R, K>), g, b, 0, c->stream, c->plumes, d_xs, ns, S, cs, \
+                       (R*)pred, (R*)den)
+    ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, CALL);
+#undef CALL
+    HIPCHK(hipGetLastError());
+    return ADE_OK;
+}
+
+}  // namespace
+}  // namespace ade
+
+using namespace ade;
 
 extern "C" {
-int ade_sensor_interp(ade_ctx*, const double*, int32_t, void*) { return ADE_EINVAL; }
-int ade_adjoint_workspace_bytes(const ade_ctx*, int64_t, int32_t, int32_t, size_t*) { return ADE_EINVAL; }
-int ade_adjoint(ade_ctx*, int64_t, int32_t, const double*, int32_t, const void*, void*, size_t, double*,
-                double*) {
-    return ADE_EINVAL;
+
+int ade_sensor_interp(ade_ctx* c, const double* d_xs, int32_t n_sensors, void* d_Cs) {
+    int rc = check_sensor_args(c, d_xs, n_sensors);
+    if (rc) return rc;
+    if (!d_Cs) return fail(ADE_EINVAL, "null output");
+    return launch_sensor_fwd(c, d_xs, n_sensors, c->S, c->cell_start, d_Cs, nullptr);
 }
+
+int ade_adjoint_workspace_bytes(const ade_ctx* c, int64_t nsteps, int32_t ckpt_every, int32_t n_sensors,
+                                size_t* bytes) {
+    if (!c || !bytes) return fail(ADE_EINVAL, "null argument");
+    if (nsteps < 1 || ckpt_every < 1 || n_sensors < 1)
+        return fail(ADE_EINVAL, "nsteps, ckpt_every and n_sensors must be positive");
+    AdjLayout L;
+    adj_layout(c, nsteps, ckpt_every, n_sensors, nullptr, L);
+    *bytes = L.bytes;
+    return ADE_OK;
 }
+
+int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32_t ns, const void* d_obs,
+                void* d_ws, size_t ws_bytes, double* h_J, double* h_grad) {
+    int rc = check_sensor_args(c, d_xs, ns);
+    if (rc) return rc;
+    if (!d_obs || !d_ws || !h_J || !h_grad) return fail(ADE_EINVAL, "null argument");
+    if (nsteps < 1 || K < 1) return fail(ADE_EINVAL, "nsteps and ckpt_every must be positive");
+    if (c->plan.integrator != ADE_EULER) return fail(ADE_EINVAL, "the adjoint is implemented for ADE_EULER");
+    if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
+    AdjLayout L;
+    adj_layout(c, nsteps, K, ns, nullptr, L);
+    if (ws_bytes < L.bytes) return fail(ADE_EWORKSPACE, "adjoint workspace too small: need %zu bytes", L.bytes);
+    adj_layout(c, nsteps, K, ns, static_cast<char*>(d_ws), L);
+
+    const Plan& pl = c->plan;
+    const uint32_t N = (uint32_t)pl.N;
+    hipStream_t st = c->stream;
+    const Snap cur = live(c);
+    const int64_t nck = (nsteps + K - 1) / K;
+
+    // forward run with checkpoints
+    for (int64_t n = 0; n < nsteps; ++n) {
+        if (n % K == 0 && (rc = copy_state(c, L.ck[(size_t)(n / K)], cur))) return rc;
+        if ((rc = enqueue_step(c))) return rc;
+    }
+    if ((rc = copy_state(c, L.ck[(size_t)nck], cur))) return rc;
+
+    // misfit and the adjoint seed at step N
+    if ((rc = launch_sensor_fwd(c, d_xs, ns, c->S, c->cell_start, L.pred, L.den))) return rc;
+    if (pl.real_bytes == 4)
+        hipLaunchKernelGGL((k_sensor_resid<float>), dim3(1), dim3(256), 0, st, ns, (const float*)L.pred,
+                           (const float*)L.den, (const float*)d_obs, (float*)L.rw, L.J);
+    else
+        hipLaunchKernelGGL((k_sensor_resid<double>), dim3(1), dim3(256), 0, st, ns, (const double*)L.pred,
+                           (const double*)L.den, (const double*)d_obs, (double*)L.rw, L.J);
+    HIPCHK(hipGetLastError());
+    {
+        dim3 g((N + 255) / 256), b(256);
+#define CALL(D, R, KK)                                                                             \
+    hipLaunchKernelGGL((k_sensor_seed<D, R, KK>), g, b, 0, st, c->plumes, d_xs, ns, (const R*)L.rw, \
+                       c->S, N, (R*)L.lam[0])
+        ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, CALL);
+#undef CALL
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemsetAsync(L.gpart, 0, (size_t)pl.ntiles * 3 * 8, st));
+
+    AdjConst ac{};
+    {
+        const PlumeDev& P = pl.plumes[0];
+        double sp = 0;
+        for (int k = 0; k < pl.dim; ++k) sp += P.vel[k] * P.vel[k];
+        sp = std::sqrt(sp);
+        ac.speed = sp;
+        for (int k = 0; k < 3; ++k) ac.vhat[k] = sp > 0 ? P.vel[k] / sp : 0.0;
+    }
+
+    // reverse sweep, segment by segment
+    int li = 0;
+    for (int64_t sgi = nck - 1; sgi >= 0; --sgi) {
+        const int64_t n0 = sgi * K, n1 = std::min<int64_t>(n0 + K, nsteps);
+        if ((rc = copy_state(c, cur, L.ck[(size_t)sgi]))) return rc;
+        for (int64_t n = n0; n < n1; ++n) {
+            if ((rc = copy_state(c, L.seg[(size_t)(n - n0)], cur))) return rc;
+            if ((rc = enqueue_step(c))) return rc;
+        }
+        for (int64_t n = n1 - 1; n >= n0; --n) {
+            const Snap& sn = L.seg[(size_t)(n - n0)];
+            const StateArrays Sa = snap_arrays(c, sn);
+            dim3 g((N + 255) / 256), b(256);
+            if (pl.real_bytes == 4)
+                hipLaunchKernelGGL((k_gather_sorted<float>), g, b, 0, st, sn.id, (const float*)L.lam[li], N,
+                                   (float*)L.lam_s);
+            else
+                hipLaunchKernelGGL((k_gather_sorted<double>), g, b, 0, st, sn.id, (const double*)L.lam[li], N,
+                                   (double*)L.lam_s);
+#define CALL(D, R, KK)                                                                            \
+    hipLaunchKernelGGL((k_adjoint<D, R, KK>), dim3(pl.ntiles), dim3(kTile), 0, st, c->plumes, c->tiles, \
+                       Sa, sn.cs, (const R*)L.lam_s, (R*)L.lam[1 - li], ac, L.gpart)
+            ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, CALL);
+#undef CALL
+            HIPCHK(hipGetLastError());
+            li = 1 - li;
+        }
+    }
+    // leave the context at step nsteps
+    if ((rc = copy_state(c, cur, L.ck[(size_t)nck]))) return rc;
+    hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, L.gpart, pl.ntiles, L.grad);
+    HIPCHK(hipGetLastError());
+    double hostv[4];
+    HIPCHK(hipMemcpyAsync(hostv, L.grad, 3 * 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(hostv + 3, L.J, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int k = 0; k < 3; ++k) h_grad[k] = hostv[k];
+    *h_J = hostv[3];
+    return ADE_OK;
+}
+
+}  // extern "C"

@@ -12,14 +12,17 @@
 #include <string>
 #include <vector>
 
-#include "../../include/adesph.h"
-#include "ade_internal.h"
+#include "ctx.h"
 
 using namespace ade;
 
-namespace {
+namespace ade {
 
+namespace {
 thread_local std::string g_err;
+}
+
+const char* last_error() { return g_err.c_str(); }
 
 int fail(int code, const char* fmt, ...) {
     char buf[512];
@@ -31,12 +34,26 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
-#define HIPCHK(expr)                                                                     \
-    do {                                                                                 \
-        hipError_t e_ = (expr);                                                          \
-        if (e_ != hipSuccess)                                                            \
-            return fail(ADE_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
-    } while (0)
+double trace_D(int dim, double aL, double aT, double Dm, const double* v, double D[9]) {
+    double s2 = 0;
+    for (int i = 0; i < dim; ++i) s2 += v[i] * v[i];
+    const double sp = std::sqrt(s2);
+    double tr = 0;
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+            double d = (i == j) ? aT * sp + Dm : 0.0;
+            if (sp > 0) d += (aL - aT) * v[i] * v[j] / sp;
+            D[i * 3 + j] = d;
+            if (i == j) tr += d;
+        }
+    return tr;
+}
+
+}  // namespace ade
+
+namespace {
+
+
 
 constexpr double kTwo32 = 4294967296.0;
 constexpr double kPi = 3.14159265358979323846;
@@ -56,29 +73,7 @@ struct Bump {
     void* take_bytes(size_t bytes) { return take<char>(bytes); }
 };
 
-struct Plan {
-    int dim = 0, real_bytes = 0, kernel = 0, integrator = 0, P = 0;
-    int64_t N = 0;
-    uint64_t ncell = 0;
-    uint32_t ntiles = 0, nscan = 0;
-    std::vector<PlumeDev> plumes;
-    std::vector<TileDev> tiles;
-};
 
-double trace_D(int dim, double aL, double aT, double Dm, const double* v, double D[9]) {
-    double s2 = 0;
-    for (int i = 0; i < dim; ++i) s2 += v[i] * v[i];
-    const double sp = std::sqrt(s2);
-    double tr = 0;
-    for (int i = 0; i < dim; ++i)
-        for (int j = 0; j < dim; ++j) {
-            double d = (i == j) ? aT * sp + Dm : 0.0;
-            if (sp > 0) d += (aL - aT) * v[i] * v[j] / sp;
-            D[i * 3 + j] = d;
-            if (i == j) tr += d;
-        }
-    return tr;
-}
 
 // Kernel normalisation B and the prefactor of W'(r)/r (Eq. 7 and its C2 sibling).
 double kernel_phi_prefactor(int kernel, int dim, double H) {
@@ -185,7 +180,10 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
                         0.1 * hs * hs / trD);
         }
         d.dt = dt;
-        for (int c = 0; c < 3; ++c) d.ushift[c] = (c < pl.dim) ? dt * q.v[c] / q.L * kTwo32 : 0.0;
+        for (int c = 0; c < 3; ++c) {
+            d.ushift[c] = (c < pl.dim) ? dt * q.v[c] / q.L * kTwo32 : 0.0;
+            d.vel[c] = (c < pl.dim) ? q.v[c] : 0.0;
+        }
         d.mass = q.mass;
         d.L = q.L;
         d.tfirst = (uint32_t)pl.tiles.size();
@@ -209,34 +207,6 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
 }
 
 }  // namespace
-
-struct ade_ctx {
-    Plan plan;
-    hipStream_t stream = nullptr;
-    ade_tuning tuning{256, 2, 0, 0};
-    PlumeDev* plumes = nullptr;
-    TileDev* tiles = nullptr;
-    StateArrays S{}, U{}, T{};
-    uint32_t* count = nullptr;
-    uint32_t* cell_start = nullptr;
-    void* scan_partial = nullptr;
-    void* aux = nullptr;
-    uint4* aux_rec = nullptr;
-    double* mass_partial = nullptr;
-    int64_t* step = nullptr;
-    uint32_t h_total = 0;  // host copy of N for the cell-start sentinel
-    int64_t h_zero = 0;
-    bool initialized = false, built = false;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
-    bool capturing = false;
-    // pair-kernel timing
-    bool timing = false;
-    std::vector<hipEvent_t> events;
-    size_t ev_used = 0;
-    double timed_ms = 0.0;
-    int64_t timed_launches = 0;
-};
 
 namespace {
 
@@ -282,6 +252,10 @@ int flush_events(ade_ctx* c) {
     c->ev_used = 0;
     return ADE_OK;
 }
+
+}  // namespace
+
+namespace ade {
 
 // launch a pair kernel, bracketed by timing events when timing is on
 int run_pair(ade_ctx* c, int mode, const PairLaunch& a) {
@@ -362,6 +336,10 @@ int enqueue_step(ade_ctx* c) {
     }
     return enqueue_build(c, 1);
 }
+
+}  // namespace ade
+
+namespace {
 
 void drop_events(ade_ctx* c) {
     for (hipEvent_t e : c->events) hipEventDestroy(e);
@@ -604,7 +582,7 @@ int ade_destroy(ade_ctx* c) {
     return ADE_OK;
 }
 
-const char* ade_last_error(void) { return g_err.c_str(); }
+const char* ade_last_error(void) { return ade::last_error(); }
 
 const char* ade_version(void) { return "adesph 0.1 (gfx950)"; }
 

@@ -1,0 +1,78 @@
+// ctx.h -- host-side context of the C ABI shared by the API translation
+// units: the plan of a context (per-plume tables), the context itself and the
+// launch sequences every entry point builds on.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/adesph.h"
+#include "ade_internal.h"
+
+namespace ade {
+
+// records a thread-local error message and returns code
+int fail(int code, const char* fmt, ...);
+
+#define HIPCHK(expr)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (expr);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(ADE_EHIP, "%s failed: %s", #expr, hipGetErrorString(e_));       \
+    } while (0)
+
+struct Plan {
+    int dim = 0, real_bytes = 0, kernel = 0, integrator = 0, P = 0;
+    int64_t N = 0;
+    uint64_t ncell = 0;
+    uint32_t ntiles = 0, nscan = 0;
+    std::vector<PlumeDev> plumes;
+    std::vector<TileDev> tiles;
+};
+
+// D of Eq. (3) for a uniform flow (row stride 3); returns its trace.
+double trace_D(int dim, double aL, double aT, double Dm, const double* v, double D[9]);
+
+}  // namespace ade
+
+struct ade_ctx {
+    ade::Plan plan;
+    hipStream_t stream = nullptr;
+    ade_tuning tuning{256, 2, 0, 0};
+    ade::PlumeDev* plumes = nullptr;
+    ade::TileDev* tiles = nullptr;
+    ade::StateArrays S{}, U{}, T{};
+    uint32_t* count = nullptr;
+    uint32_t* cell_start = nullptr;
+    void* scan_partial = nullptr;
+    void* aux = nullptr;
+    uint4* aux_rec = nullptr;
+    double* mass_partial = nullptr;
+    int64_t* step = nullptr;
+    uint32_t h_total = 0;  // host copy of N for the cell-start sentinel
+    bool initialized = false, built = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    bool capturing = false;
+    // pair-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    size_t ev_used = 0;
+    double timed_ms = 0.0;
+    int64_t timed_launches = 0;
+};
+
+namespace ade {
+
+// enqueue a pair kernel (timed when timing is on)
+int run_pair(ade_ctx* c, int mode, const PairLaunch& a);
+// launch arguments of a pair kernel over the sorted state of c
+PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase, double scale, void* out);
+// counting sort of the hashed U buffer into S and the cell-start table
+int enqueue_build(ade_ctx* c, int inc_step);
+// one explicit step (pair sum, update, rebuild)
+int enqueue_step(ade_ctx* c);
+
+}  // namespace ade

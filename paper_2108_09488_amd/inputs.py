@@ -99,14 +99,16 @@ def gaussian_plume(x: np.ndarray, centre, sigma0: float, L: float = 1.0,
     return C0 * C
 
 
-def sensors(n_sensors: int, lo, hi, seed: int = BASE_SEED, stream: int = 7777) -> np.ndarray:
-    """Uniform random sensor points in the box [lo, hi] (dim, S), float64."""
+def sensors(n_sensors: int, lo, hi, seed: int = BASE_SEED, stream: int = 7777,
+            L: float = 1.0) -> np.ndarray:
+    """Uniform random sensor points in the box [lo, hi] (dim, S), float64,
+    rounded to the L/2**32 position grid."""
     dim = len(lo)
     key = stream_key(seed, stream)
     out = np.empty((dim, n_sensors))
     for c in range(dim):
         cnt = np.arange(n_sensors, dtype=np.uint64) * np.uint64(dim) + np.uint64(c)
-        out[c] = lo[c] + (hi[c] - lo[c]) * uniform01(key, cnt)
+        out[c] = quantize(lo[c] + (hi[c] - lo[c]) * uniform01(key, cnt), L)
     return out
 
 

@@ -1,0 +1,68 @@
+"""Writes adjoint_256.json: the misfit J and its gradient dJ/d(alpha_L,
+alpha_T, D_m) for the 2D adjoint problem (256^2 regular lattice, Wendland C4,
+h = 1.5 dp, v = (1, 0), 500 explicit steps of dt = 1e-4, 1024 seeded sensors
+in [0.05, 0.55] x [0.25, 0.75], observations generated at alpha_L = 2e-2,
+alpha_T = 2e-3, D_m = 1e-6, gradient at the guess alpha_L = 1e-2,
+alpha_T = 5e-3, D_m = 1e-6), from the FP64 CPU oracle only: its discrete
+adjoint and central finite differences of its forward misfit.
+
+Run: python tests/golden/make_adjoint_golden.py   (several minutes on 8 cores)
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+from paper_2108_09488_amd import inputs as I  # noqa: E402
+
+TRUTH = (2e-2, 2e-3, 1e-6)
+GUESS = (1e-2, 5e-3, 1e-6)
+N_SENSORS = 1024
+
+
+def problem():
+    spec = I.config("cfg5")
+    x = spec.positions()
+    C0 = spec.concentration(x)
+    xs = I.sensors(N_SENSORS, [0.05, 0.25], [0.55, 0.75])
+    return spec, x, C0, xs
+
+
+def main():
+    t0 = time.time()
+    spec, x, C0, xs = problem()
+    v = spec.velocity()
+    mt = O.model(2, 4, spec.H, alpha_L=TRUTH[0], alpha_T=TRUTH[1], D_m=TRUTH[2])
+    _, obs = O.misfit(mt, x, C0, v, spec.dt, spec.steps, xs, None, mass=spec.mass, rho=spec.rho0)
+    mg = O.model(2, 4, spec.H, alpha_L=GUESS[0], alpha_T=GUESS[1], D_m=GUESS[2])
+    J, grad, _ = O.adjoint(mg, x, C0, v, spec.dt, spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0)
+    fd = []
+    for k in range(3):
+        th = np.array(GUESS)
+        h = 1e-4 * th[k]
+        Jp = O.misfit(O.model(2, 4, spec.H, *(th + h * np.eye(3)[k])), x, C0, v, spec.dt, spec.steps,
+                      xs, obs, mass=spec.mass, rho=spec.rho0)[0]
+        Jm = O.misfit(O.model(2, 4, spec.H, *(th - h * np.eye(3)[k])), x, C0, v, spec.dt, spec.steps,
+                      xs, obs, mass=spec.mass, rho=spec.rho0)[0]
+        fd.append((Jp - Jm) / (2 * h))
+    out = {
+        "what": "2D adjoint problem: 256^2 regular lattice, Wendland C4, h = 1.5 dp (support 3 dp), "
+                "v = (1, 0), 500 Euler steps of 1e-4, 1024 sensors; FP64 oracle values",
+        "truth": TRUTH, "guess": GUESS, "n_sensors": N_SENSORS,
+        "obs": [float(o) for o in obs], "J": float(J), "grad": [float(g) for g in grad],
+        "fd_grad": [float(g) for g in fd], "seconds": time.time() - t0,
+    }
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_256.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print("wrote", path, "J", J, "grad", grad, "fd", fd, "in %.0f s" % (time.time() - t0))
+
+
+if __name__ == "__main__":
+    main()

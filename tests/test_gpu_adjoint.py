@@ -1,0 +1,125 @@
+"""Sensors and the discrete adjoint of the HIP path against the FP64 oracle:
+Shepard interpolation, J and dJ/d(alpha_L, alpha_T, D_m) (oracle adjoint and
+oracle finite differences), independence of the checkpoint spacing, and the
+state left after the sweep."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2108_09488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_256.json")
+
+
+def _ctx(spec):
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    print(f"[case] {spec.name} n_side={spec.n_side} rb={spec.real_bytes} aL={spec.alpha_L} aT={spec.alpha_T}",
+          flush=True)
+    c = Context([params_from_spec(spec)], [spec.n])
+    x = spec.positions()
+    C = spec.concentration(x)
+    if spec.real_bytes == 4:
+        C = C.astype(np.float32).astype(np.float64)
+    c.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+    return c, x, C
+
+
+@pytest.mark.parametrize("rb", [4, 8])
+def test_sensor_interpolation(rb):
+    spec = I.config("cfg5", n_side=96, real_bytes=rb)
+    c, x, C = _ctx(spec)
+    xs = I.sensors(300, [0.02, 0.02], [0.98, 0.98])
+    g = c.sensor_interp(torch.from_numpy(xs)).double().cpu().numpy()
+    o, _ = O.sensor_interp(O.model_from_spec(spec), x, C, xs)
+    err = float(np.linalg.norm(g - o) / np.linalg.norm(o))
+    assert err < (1e-12 if rb == 8 else 1e-6), err
+    c.close()
+
+
+def _small(rb=4, n_side=64, steps=60, ns=64):
+    # dt v is a multiple of 2^-32 (dt = 2^-12, v = (0.75, 0.5)): the library's
+    # fixed-point displacement per step is then exact, so positions relative to
+    # the fixed sensors agree with the oracle's to the last bit
+    spec = I.config("cfg5", n_side=n_side, steps=steps, dt=2.0 ** -12, real_bytes=rb, v=(0.75, 0.5, 0.0),
+                    alpha_L=1e-2, alpha_T=5e-3)
+    x = spec.positions()
+    C0 = spec.concentration(x)
+    if rb == 4:
+        C0 = C0.astype(np.float32).astype(np.float64)
+    xs = I.sensors(ns, [0.05, 0.25], [0.55, 0.75])
+    truth = O.model(2, 4, spec.H, alpha_L=2e-2, alpha_T=2e-3, D_m=1e-6)
+    _, obs = O.misfit(truth, x, C0, spec.velocity(), spec.dt, steps, xs, None, mass=spec.mass, rho=spec.rho0)
+    if rb == 4:
+        obs = obs.astype(np.float32).astype(np.float64)
+    return spec, x, C0, xs, obs
+
+
+@pytest.mark.parametrize("rb", [4, 8])
+def test_adjoint_matches_oracle(rb):
+    spec, x, C0, xs, obs = _small(rb)
+    c, _, _ = _ctx(spec)
+    J, g = c.adjoint(spec.steps, 7, torch.from_numpy(xs), torch.from_numpy(obs))
+    Jo, go, _ = O.adjoint(O.model_from_spec(spec), x, C0, spec.velocity(), spec.dt, spec.steps, xs, obs,
+                          mass=spec.mass, rho=spec.rho0)
+    tol = 1e-10 if rb == 8 else 1e-4
+    assert J == pytest.approx(Jo, rel=tol)
+    assert np.allclose(g, go, rtol=tol, atol=tol * np.abs(go).max())
+    c.close()
+
+
+def test_adjoint_checkpoint_spacing_and_final_state():
+    """The recompute is bit-identical to the forward run, so J and the gradient
+    do not depend on the checkpoint spacing, and the context is left at the
+    final state of a plain forward run."""
+    spec, x, C0, xs, obs = _small(4, n_side=48, steps=30, ns=40)
+    outs = []
+    for K in (1, 7, 30, 100):
+        c, _, _ = _ctx(spec)
+        J, g = c.adjoint(spec.steps, K, torch.from_numpy(xs), torch.from_numpy(obs))
+        outs.append((J, tuple(g), c.read_C().cpu().numpy().copy()))
+        c.close()
+    for o in outs[1:]:
+        assert o[0] == outs[0][0] and o[1] == outs[0][1]
+        assert np.array_equal(o[2], outs[0][2])
+    c, _, _ = _ctx(spec)
+    c.step(spec.steps)
+    assert np.array_equal(c.read_C().cpu().numpy(), outs[0][2])
+    c.close()
+
+
+def test_adjoint_dm_identity_and_autograd():
+    """For a uniform flow dD/dD_m = (dD/dalpha_L + dD/dalpha_T) / |v|, so the
+    gradient satisfies the same identity; the autograd wrapper returns it."""
+    from paper_2108_09488_amd.context import ADEMisfit
+    spec, x, C0, xs, obs = _small(4)
+    theta = torch.tensor([1e-2, 5e-3, 1e-6], dtype=torch.float64, requires_grad=True)
+    prob = {"spec": spec, "x0": x, "C0": C0.astype(np.float32), "xs": xs, "obs": obs.astype(np.float32),
+            "nsteps": spec.steps, "ckpt_every": 10}
+    J = ADEMisfit.apply(theta, prob)
+    J.backward()
+    g = theta.grad.numpy()
+    assert np.isfinite(J.item()) and J.item() > 0
+    assert g[2] == pytest.approx((g[0] + g[1]) / np.linalg.norm(spec.velocity()), rel=1e-4)
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden adjoint values not generated")
+def test_adjoint_full_size_against_golden():
+    """256^2 particles, 500 steps, 1024 sensors, checkpoints every 50 steps:
+    FP32 J and gradient within 1e-4 of the FP64 oracle adjoint and of the
+    oracle's central finite differences (tests/golden/adjoint_256.json)."""
+    gold = json.load(open(GOLDEN))
+    spec = I.config("cfg5", alpha_L=gold["guess"][0], alpha_T=gold["guess"][1], D_m=gold["guess"][2])
+    c, x, C0 = _ctx(spec)
+    xs = I.sensors(gold["n_sensors"], [0.05, 0.25], [0.55, 0.75])
+    obs = np.array(gold["obs"])
+    J, g = c.adjoint(spec.steps, 50, torch.from_numpy(xs), torch.from_numpy(obs))
+    go, fd = np.array(gold["grad"]), np.array(gold["fd_grad"])
+    assert J == pytest.approx(gold["J"], rel=1e-4)
+    for ref in (go, fd):
+        assert np.all(np.abs(np.array(g) - ref) <= 1e-4 * np.abs(ref) + 1e-6 * np.abs(ref).max())
+    c.close()

@@ -416,17 +416,25 @@ def test_sensor_interpolation_constant_and_linear():
     assert np.allclose(cl, 2.0 * nodes[0] - nodes[1], rtol=1e-13)
 
 
-def test_adjoint_dot_product():
-    """<L mu, nu> = <mu, L^T nu> for the operator and its explicit transpose."""
+@pytest.mark.parametrize("uniform", [True, False])
+def test_adjoint_dot_product(uniform):
+    """<L mu, nu> = <mu, L^T nu> for the operator and its transpose (also with
+    unequal masses and densities, where L is not symmetric)."""
     spec = I.config("cfg2_h20_r10", n_side=48, alpha_T=2e-3)
     x = spec.positions()
     m = O.model_from_spec(spec)
     rng = np.random.default_rng(3)
-    mu, nu = rng.normal(size=x.shape[1]), rng.normal(size=x.shape[1])
+    n = x.shape[1]
+    mu, nu = rng.normal(size=n), rng.normal(size=n)
     v = np.array([0.8, 0.6])
-    Lmu = O.rhs(m, x, mu, v_uniform=v, mass=spec.mass, rho=spec.rho0)
-    LTnu = O.apply_LT(m, x, nu, v, mass=spec.mass, rho=spec.rho0)
+    mass = spec.mass if uniform else spec.mass * rng.uniform(0.5, 1.5, n)
+    rho = spec.rho0 if uniform else spec.rho0 * rng.uniform(0.9, 1.1, n)
+    Lmu = O.rhs(m, x, mu, v_uniform=v, mass=mass, rho=rho)
+    LTnu = O.apply_LT(m, x, nu, v, mass=mass, rho=rho)
     assert np.dot(Lmu, nu) == pytest.approx(np.dot(mu, LTnu), rel=1e-12)
+    if not uniform:  # the transpose really differs from L here
+        Lnu = O.rhs(m, x, nu, v_uniform=v, mass=mass, rho=rho)
+        assert np.max(np.abs(Lnu - LTnu)) > 1e-3 * np.max(np.abs(Lnu))
 
 
 def _small_inverse_problem(n_side=32, steps=30, n_sensors=40):
