@@ -89,6 +89,10 @@ def time_sweep(sweep, steps, warmup, graph):
 
 
 def batched(device, steps, warmup, n_plumes=256):
+    """The ensemble: 256 plumes of 32^2..256^2 particles with their own
+    dispersivities, flow directions and time steps, in one context: one
+    launch per kernel per step, the pair kernel on a persistent grid, steps
+    replayed from a HIP graph, launch shape picked by the autotuner."""
     import numpy as np
     import torch
     from paper_2108_09488_amd import inputs as I
@@ -102,6 +106,7 @@ def batched(device, steps, warmup, n_plumes=256):
     ctx.init(torch.from_numpy(xs), torch.from_numpy(Cs.astype(np.float32))).build()
     off, _ = ctx.neighbours()
     inter = int(off[-1].item())
+    tuned = ctx.autotune(reps=3)
     ctx.step_graph(warmup)
     _sync()
     t0 = time.perf_counter()
@@ -111,8 +116,79 @@ def batched(device, steps, warmup, n_plumes=256):
     n = ctx.N
     ctx.close()
     return {"plumes": n_plumes, "particles": n, "interactions_per_step": inter,
-            "steps": steps, "ms_per_step": 1e3 * wall / steps,
+            "steps": steps, "ms_per_step": 1e3 * wall / steps, "tuning": tuned,
             "interactions_per_s": inter * steps / wall}
+
+
+def fwd_adjoint(device):
+    """The inverse problem: 256^2 particles, 500 Euler steps of 1e-4, 1024
+    sensors; J and dJ/d(alpha_L, alpha_T, D_m) by the adjoint with a
+    checkpoint every 50 steps (forward + recompute + reverse sweep), against
+    the plain forward of the same plume.  Observations come from a GPU forward
+    run at alpha_L = 2e-2, alpha_T = 2e-3 (timing only, no parity claim)."""
+    import numpy as np
+    import torch
+    from paper_2108_09488_amd import inputs as I
+    from paper_2108_09488_amd.context import Context, params_from_spec
+
+    xs = torch.from_numpy(I.sensors(1024, [0.05, 0.25], [0.55, 0.75]))
+    truth = I.config("cfg5")
+    guess = I.config("cfg5", alpha_L=1e-2, alpha_T=5e-3)
+    x = truth.positions()
+    C0 = torch.from_numpy(truth.concentration(x).astype(np.float32))
+    c = Context([params_from_spec(truth)], [truth.n], device=device)
+    c.init(torch.from_numpy(x), C0).build()
+    c.step(truth.steps)
+    obs = c.sensor_interp(xs)
+    c.close()
+    c = Context([params_from_spec(guess)], [guess.n], device=device)
+    c.init(torch.from_numpy(x), C0).build()
+    off, _ = c.neighbours()
+    inter = int(off[-1].item())
+    c.adjoint(guess.steps, 50, xs, obs)  # warm-up
+    c.init(torch.from_numpy(x), C0).build()
+    _sync()
+    t0 = time.perf_counter()
+    J, g = c.adjoint(guess.steps, 50, xs, obs)
+    _sync()
+    wall_adj = time.perf_counter() - t0
+    c.init(torch.from_numpy(x), C0).build()
+    _sync()
+    t0 = time.perf_counter()
+    c.step(guess.steps)
+    _sync()
+    wall_fwd = time.perf_counter() - t0
+    c.close()
+    return {"particles": guess.n, "steps": guess.steps, "interactions_per_step": inter,
+            "ms_fwd_adjoint": 1e3 * wall_adj, "ms_fwd": 1e3 * wall_fwd,
+            "interactions_per_s": inter * guess.steps / wall_adj,
+            "fwd_interactions_per_s": inter * guess.steps / wall_fwd,
+            "vs_plain": wall_fwd / wall_adj, "J": J, "grad": g}
+
+
+def single_3d(device, steps=10):
+    """One 3D plume, 128^3 particles, h = 2 dp (about 270 neighbours)."""
+    import numpy as np
+    import torch
+    from paper_2108_09488_amd import inputs as I
+    from paper_2108_09488_amd.context import Context, params_from_spec
+
+    s = I.config("cfg3")
+    c = Context([params_from_spec(s)], [s.n], device=device)
+    x = s.positions()
+    c.init(torch.from_numpy(x), torch.from_numpy(s.concentration(x).astype(np.float32))).build()
+    off, _ = c.neighbours()
+    inter = int(off[-1].item())
+    tuned = c.autotune(reps=2)
+    c.step(2)
+    _sync()
+    t0 = time.perf_counter()
+    c.step(steps)
+    _sync()
+    wall = time.perf_counter() - t0
+    c.close()
+    return {"particles": s.n, "interactions_per_step": inter, "steps": steps, "tuning": tuned,
+            "ms_per_step": 1e3 * wall / steps, "interactions_per_s": inter * steps / wall}
 
 
 def cpu_baseline(cells, budget_s=20.0):
@@ -165,26 +241,35 @@ def main():
     device = "cuda:0"
     cells = args.cells.split(",") if args.cells else list(I.CFG2_CELLS)
     sweep = build_sweep(cells, device)
+    for s in sweep:
+        s["tuning"] = s["ctx"].autotune(reps=3)
     inter_step = sum(s["interactions"] for s in sweep)
     print(f"[bench] sweep built: {len(sweep)} plumes, {inter_step} interactions per step", file=sys.stderr, flush=True)
 
-    wall, pair = time_sweep(sweep, args.steps, args.warmup, graph=False)
+    # timed region: every plume's captured step replayed from its HIP graph
+    wall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
     value = inter_step * args.steps / wall
-    print(f"[bench] eager: {1e3 * wall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    print(f"[bench] graph: {1e3 * wall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
+    # the same steps launched eagerly, with HIP events around every pair kernel
+    ewall, pair = time_sweep(sweep, args.steps, args.warmup, graph=False)
+    print(f"[bench] eager: {1e3 * ewall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
     avg_ms = pair["ms_total"] / pair["launches"]
     achieved = pair["flops"] / (pair["ms_total"] * 1e-3) / 1e12
-    extras = {}
+    extras = {"eager": {"ms_per_step": 1e3 * ewall / args.steps,
+                        "interactions_per_s": inter_step * args.steps / ewall,
+                        "pair_kernel_ms_per_step": pair["ms_total"] / args.steps}}
     if not args.no_extras:
-        gwall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
-        extras["graph_replay"] = {"ms_per_step": 1e3 * gwall / args.steps,
-                                  "interactions_per_s": inter_step * args.steps / gwall}
-        print(f"[bench] graph: {1e3 * gwall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
         b = batched(device, steps=min(args.steps, 200), warmup=args.warmup)
         b["vs_plain"] = b["interactions_per_s"] / value
         extras["batched"] = b
         print(f"[bench] batched: {b['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+        extras["fwd_adjoint"] = fwd_adjoint(device)
+        print(f"[bench] fwd+adjoint: {extras['fwd_adjoint']['ms_fwd_adjoint']:.1f} ms", file=sys.stderr, flush=True)
+        extras["single_3d"] = single_3d(device)
+        print(f"[bench] 3D: {extras['single_3d']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     per_cell = {s["name"]: {"interactions_per_step": s["interactions"],
-                            "neighbours_mean": s["interactions"] / s["spec"].n} for s in sweep}
+                            "neighbours_mean": s["interactions"] / s["spec"].n,
+                            "tuning": s["tuning"]} for s in sweep}
     for s in sweep:
         s["ctx"].close()
 

@@ -171,6 +171,16 @@ int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *
  * *h_count (either may be NULL). */
 int ade_kernel_timing(ade_ctx *ctx, int32_t mode, double *h_ms, int64_t *h_count);
 
+/* Autotuner: times the pair kernel (reps launches each, HIP events on the
+ * context's stream) over the launch shapes block {64,128,256} x lanes {1,2,4}
+ * x stage_lds {0, 8} x persistent {0, 8 workgroups per CU}, keeps the fastest
+ * in the context and returns it in *best (may be NULL).  With
+ * ADE_TUNE_KEEP_LANES the current lanes value is kept, so results stay
+ * bitwise identical to the untuned context.  Needs built cells; does not
+ * change the particle state.  Synchronises the stream. */
+enum { ADE_TUNE_KEEP_LANES = 1 };
+int ade_autotune(ade_ctx *ctx, int32_t reps, int32_t flags, ade_tuning *best);
+
 int ade_set_tuning(ade_ctx *ctx, const ade_tuning *t);
 int ade_get_tuning(const ade_ctx *ctx, ade_tuning *t);
 

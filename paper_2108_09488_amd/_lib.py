@@ -16,6 +16,7 @@ ADE_OK, ADE_EINVAL, ADE_EWORKSPACE, ADE_EHIP, ADE_EUNSTABLE, ADE_ENONFINITE, ADE
 ADE_WENDLAND_C2, ADE_WENDLAND_C4 = 2, 4
 ADE_EULER, ADE_PC = 1, 2
 ADE_STRICT_DT, ADE_CHECK_FINITE = 1, 2
+ADE_TUNE_KEEP_LANES = 1
 
 ERROR_NAMES = {0: "ADE_OK", -1: "ADE_EINVAL", -2: "ADE_EWORKSPACE", -3: "ADE_EHIP",
                -4: "ADE_EUNSTABLE", -5: "ADE_ENONFINITE", -6: "ADE_ESTATE"}
@@ -24,7 +25,7 @@ ERROR_NAMES = {0: "ADE_OK", -1: "ADE_EINVAL", -2: "ADE_EWORKSPACE", -3: "ADE_EHI
 EXPORTS = ["ade_workspace_bytes", "ade_create", "ade_init_particles", "ade_build_cells",
            "ade_step", "ade_step_graph", "ade_rhs", "ade_read_C", "ade_read_x", "ade_mass",
            "ade_neighbours", "ade_sensor_interp", "ade_adjoint_workspace_bytes", "ade_adjoint",
-           "ade_kernel_timing", "ade_set_tuning", "ade_get_tuning", "ade_info", "ade_destroy", "ade_last_error",
+           "ade_kernel_timing", "ade_autotune", "ade_set_tuning", "ade_get_tuning", "ade_info", "ade_destroy", "ade_last_error",
            "ade_version"]
 
 
@@ -80,6 +81,7 @@ def lib() -> ct.CDLL:
         "ade_adjoint_workspace_bytes": [p, i64, i32, i32, psz],
         "ade_adjoint": [p, i64, i32, p, i32, p, p, sz, pd, pd],
         "ade_kernel_timing": [p, i32, pd, pi64],
+        "ade_autotune": [p, i32, i32, T],
         "ade_set_tuning": [p, T],
         "ade_get_tuning": [p, T],
         "ade_info": [p, i32, pi64, pi64, pi64, pd, pi64],

@@ -169,6 +169,13 @@ class Context:
         check(lib().ade_kernel_timing(self._h, 0, ct.byref(ms), ct.byref(n)))
         return ms.value, n.value
 
+    def autotune(self, reps: int = 5, keep_lanes: bool = False) -> dict:
+        """Time the pair kernel over the launch shapes and keep the fastest."""
+        t = AdeTuning()
+        check(lib().ade_autotune(self._h, int(reps), _lib.ADE_TUNE_KEEP_LANES if keep_lanes else 0,
+                                 ct.byref(t)))
+        return {"block": t.block, "lanes": t.lanes, "stage_lds": t.stage_lds, "persistent": t.persistent}
+
     def set_tuning(self, block=256, lanes=2, stage_lds=0, persistent=0):
         t = AdeTuning(block, lanes, stage_lds, persistent)
         check(lib().ade_set_tuning(self._h, ct.byref(t)))

@@ -536,6 +536,56 @@ int ade_kernel_timing(ade_ctx* c, int32_t mode, double* h_ms, int64_t* h_count) 
     return ADE_OK;
 }
 
+int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
+    if (!c) return fail(ADE_EINVAL, "null ctx");
+    if (reps < 1) return fail(ADE_EINVAL, "reps must be positive");
+    if (!c->built) return fail(ADE_ESTATE, "ade_autotune before ade_build_cells");
+    const Plan& pl = c->plan;
+    const ade_tuning start = c->tuning;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 0.f;
+    ade_tuning best_t = start;
+    bool have = false;
+    int rc = ADE_OK;
+    const int blocks[3] = {64, 128, 256}, lanes[3] = {1, 2, 4}, stages[2] = {0, 8}, pers[2] = {0, 2048};
+    for (int lb : lanes) {
+        if ((flags & ADE_TUNE_KEEP_LANES) && lb != start.lanes) continue;
+        for (int bb : blocks)
+            for (int st : stages)
+                for (int pp : pers) {
+                    if ((size_t)st * bb * 16u > 65536u) continue;
+                    c->tuning = ade_tuning{bb, lb, st, pp};
+                    PairLaunch a = pair_args(c, kModeRhs, c->S.C, c->S.C, 1.0, c->aux);
+                    if ((rc = run_pair(c, kModeRhs, a))) break;  // warm-up
+                    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(ADE_EHIP, "event record"); break; }
+                    for (int r = 0; r < reps && !rc; ++r) rc = run_pair(c, kModeRhs, a);
+                    if (rc) break;
+                    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
+                        rc = fail(ADE_EHIP, "event synchronise");
+                        break;
+                    }
+                    float ms = 0.f;
+                    hipEventElapsedTime(&ms, e0, e1);
+                    if (!have || ms < best_ms) {
+                        best_ms = ms;
+                        best_t = c->tuning;
+                        have = true;
+                    }
+                }
+        if (rc) break;
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    (void)pl;
+    c->tuning = rc ? start : best_t;
+    drop_graph(c);
+    if (rc) return rc;
+    if (best) *best = best_t;
+    return ADE_OK;
+}
+
 int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
     if (!c || !t) return fail(ADE_EINVAL, "null argument");
     if (t->block != 64 && t->block != 128 && t->block != 256)

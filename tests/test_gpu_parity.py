@@ -233,3 +233,17 @@ def test_ensemble_matches_single_plumes():
     _, Co, _ = O.run(O.model_from_spec(s), xs[0], Cs[0], s.dt, 20, v_uniform=s.velocity(), mass=s.mass, rho=s.rho0)
     assert _rel(Ce[:s.n].astype(np.float64), Co) < 1e-5
     ens.close()
+
+
+def test_autotune_keep_lanes_is_bitwise_neutral():
+    spec = I.config("cfg2_h20_r10", n_side=80)
+    ctx, x, C = _ctx(spec)
+    before = ctx.rhs().cpu().numpy().copy()
+    t = ctx.autotune(reps=1, keep_lanes=True)
+    assert t["lanes"] == ctx.get_tuning()["lanes"]
+    after = ctx.rhs().cpu().numpy()
+    assert np.array_equal(before, after)
+    t2 = ctx.autotune(reps=1)
+    assert t2 == ctx.get_tuning()
+    ctx.step(3)
+    ctx.close()
