@@ -81,6 +81,7 @@ struct PairLaunch {
     double scale;           // fraction of the plume's dt: step 1, half 0.5 (unused for rhs)
     void* out;              // half: S-order output; rhs: id-order output
     uint4* out_rec;         // half: candidate records with the half-step C (S order)
+    hipEvent_t ev0, ev1;    // if set: events stamped at the kernel's start and end
 };
 
 // kernel launchers (kernels_*.hip); all return hipError_t of the launch

@@ -257,11 +257,13 @@ int flush_events(ade_ctx* c) {
 
 namespace ade {
 
-// launch a pair kernel, bracketed by timing events when timing is on
+// launch a pair kernel; when timing is on, events stamped with the kernel's
+// own start and end times are attached to the launch
 int run_pair(ade_ctx* c, int mode, const PairLaunch& a) {
     const Plan& pl = c->plan;
-    const bool t = c->timing && !c->capturing;
-    if (t) {
+    PairLaunch b = a;
+    b.ev0 = b.ev1 = nullptr;
+    if (c->timing && !c->capturing) {
         if (c->ev_used + 2 > c->events.size()) {
             if (c->events.size() < 4096) {
                 size_t old = c->events.size();
@@ -272,10 +274,10 @@ int run_pair(ade_ctx* c, int mode, const PairLaunch& a) {
                 if (rc) return rc;
             }
         }
-        HIPCHK(hipEventRecord(c->events[c->ev_used++], c->stream));
+        b.ev0 = c->events[c->ev_used++];
+        b.ev1 = c->events[c->ev_used++];
     }
-    HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, mode, a, c->tuning.block, c->stream));
-    if (t) HIPCHK(hipEventRecord(c->events[c->ev_used++], c->stream));
+    HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, mode, b, c->tuning.block, c->stream));
     return ADE_OK;
 }
 

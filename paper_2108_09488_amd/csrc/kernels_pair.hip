@@ -28,6 +28,8 @@
 // stages the union of its candidate ranges in LDS (coalesced reads) and the
 // lanes walk the staged copy, falling back to global memory for a range
 // outside it.
+#include <hip/hip_ext.h>
+
 #include "ade_geom.h"
 
 namespace ade {
@@ -342,9 +344,13 @@ static void launch_pair_l(int mode, const PairLaunch& a, hipStream_t s) {
     dim3 g(grid), b(a.block);
     const size_t shm = (Rec<DIM, real>::kStageable && a.stage > 0)
                            ? sizeof(uint4) * (size_t)a.stage * (size_t)a.block : 0;
-    if (mode == kModeStep) hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeStep, LANES>), g, b, shm, s, c, nwork);
-    else if (mode == kModeHalf) hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeHalf, LANES>), g, b, shm, s, c, nwork);
-    else hipLaunchKernelGGL((k_pair<DIM, real, KERN, kModeRhs, LANES>), g, b, shm, s, c, nwork);
+    auto kern = (mode == kModeStep)   ? k_pair<DIM, real, KERN, kModeStep, LANES>
+                : (mode == kModeHalf) ? k_pair<DIM, real, KERN, kModeHalf, LANES>
+                                      : k_pair<DIM, real, KERN, kModeRhs, LANES>;
+    if (c.ev0)  // timed launch: the events carry the kernel's own start and end stamps
+        hipExtLaunchKernelGGL(kern, g, b, (uint32_t)shm, s, c.ev0, c.ev1, 0u, c, nwork);
+    else
+        hipLaunchKernelGGL(kern, g, b, shm, s, c, nwork);
 }
 
 template <int DIM, typename real, int KERN>

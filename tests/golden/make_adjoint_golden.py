@@ -40,16 +40,19 @@ def main():
     v = spec.velocity()
     mt = O.model(2, 4, spec.H, alpha_L=TRUTH[0], alpha_T=TRUTH[1], D_m=TRUTH[2])
     _, obs = O.misfit(mt, x, C0, v, spec.dt, spec.steps, xs, None, mass=spec.mass, rho=spec.rho0)
+    print("observations done in %.0f s" % (time.time() - t0), flush=True)
     mg = O.model(2, 4, spec.H, alpha_L=GUESS[0], alpha_T=GUESS[1], D_m=GUESS[2])
     J, grad, _ = O.adjoint(mg, x, C0, v, spec.dt, spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0)
+    print("adjoint done in %.0f s" % (time.time() - t0), flush=True)
     fd = []
     for k in range(3):
         th = np.array(GUESS)
         h = 1e-4 * th[k]
-        Jp = O.misfit(O.model(2, 4, spec.H, *(th + h * np.eye(3)[k])), x, C0, v, spec.dt, spec.steps,
-                      xs, obs, mass=spec.mass, rho=spec.rho0)[0]
-        Jm = O.misfit(O.model(2, 4, spec.H, *(th - h * np.eye(3)[k])), x, C0, v, spec.dt, spec.steps,
-                      xs, obs, mass=spec.mass, rho=spec.rho0)[0]
+        tp, tm = th + h * np.eye(3)[k], th - h * np.eye(3)[k]
+        Jp = O.misfit(O.model(2, 4, spec.H, alpha_L=tp[0], alpha_T=tp[1], D_m=tp[2]), x, C0, v, spec.dt,
+                      spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0)[0]
+        Jm = O.misfit(O.model(2, 4, spec.H, alpha_L=tm[0], alpha_T=tm[1], D_m=tm[2]), x, C0, v, spec.dt,
+                      spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0)[0]
         fd.append((Jp - Jm) / (2 * h))
     out = {
         "what": "2D adjoint problem: 256^2 regular lattice, Wendland C4, h = 1.5 dp (support 3 dp), "
