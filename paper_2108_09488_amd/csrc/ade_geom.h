@@ -20,7 +20,12 @@ __device__ __forceinline__ real h2_of(const PlumeDev& P) {
 }
 
 constexpr int kMaxRowOffsets = 81;  // (2R+1)^2 for R <= 4
-constexpr int kBatch = 4;           // candidate records fetched together before use
+// candidate records fetched together before use: long batches when one lane
+// walks a target's rows alone, shorter ones when lanes share a target
+template <int LANES>
+struct Batch {
+    static constexpr int value = (LANES == 1) ? 8 : 4;
+};
 
 // A target particle: fixed-point position, its row and the fractional
 // position inside the row (in row heights, from the low word of u * nr).

@@ -201,8 +201,8 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
     pl.N = (int64_t)N;
     pl.ncell = cbase;
     pl.ntiles = (uint32_t)pl.tiles.size();
-    const uint64_t scan_n = std::max<uint64_t>(pl.ncell, (uint64_t)N + 1);
-    pl.nscan = (uint32_t)((scan_n + kScanChunk - 1) / kScanChunk);
+    pl.nscan = (uint32_t)std::max<uint64_t>(cell_pad(pl.ncell) / kCellChunk,
+                                            ((uint64_t)N + 1 + kScanChunk - 1) / kScanChunk);
     return ADE_OK;
 }
 
@@ -230,8 +230,8 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
         c->U.pos[2] = c->U.pos[0];
         c->T.pos[2] = c->T.pos[0];
     }
-    c->count = b.take<uint32_t>(pl.ncell);
-    c->cell_start = b.take<uint32_t>(pl.ncell + 1);
+    c->count = b.take<uint32_t>(cell_pad(pl.ncell));
+    c->cell_start = b.take<uint32_t>(cell_pad(pl.ncell));
     c->scan_partial = b.take_bytes((size_t)pl.nscan * 8);
     c->aux = b.take_bytes(N * rb);
     c->aux_rec = (pl.dim == 3 && pl.real_bytes == 8) ? nullptr : b.take<uint4>(N);
@@ -401,7 +401,7 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
     if (hipMemcpyAsync(c->plumes, pl.plumes.data(), sizeof(PlumeDev) * pl.P, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->tiles, pl.tiles.data(), sizeof(TileDev) * pl.ntiles, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->cell_start + pl.ncell, &c->h_total, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
-        hipMemsetAsync(c->count, 0, sizeof(uint32_t) * pl.ncell, c->stream) != hipSuccess ||
+        hipMemsetAsync(c->count, 0, sizeof(uint32_t) * cell_pad(pl.ncell), c->stream) != hipSuccess ||
         hipMemsetAsync(c->step, 0, sizeof(int64_t), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return cleanup(fail(ADE_EHIP, "uploading the plume tables failed"));
@@ -412,7 +412,7 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
 int ade_init_particles(ade_ctx* c, const double* d_x, const void* d_C) {
     if (!c || !d_x || !d_C) return fail(ADE_EINVAL, "null argument");
     const Plan& pl = c->plan;
-    HIPCHK(hipMemsetAsync(c->count, 0, sizeof(uint32_t) * pl.ncell, c->stream));
+    HIPCHK(hipMemsetAsync(c->count, 0, sizeof(uint32_t) * cell_pad(pl.ncell), c->stream));
     HIPCHK(hipMemsetAsync(c->step, 0, sizeof(int64_t), c->stream));
     HIPCHK(launch_init(pl.dim, pl.real_bytes, c->plumes, c->tiles, pl.ntiles, d_x, d_C, (uint32_t)pl.N,
                        c->U, c->count, c->stream));

@@ -36,60 +36,69 @@ __global__ __launch_bounds__(kTile) void k_init(const PlumeDev* __restrict__ plu
 }
 
 // ---------------------------------------------------------------------------
-// exclusive scan of the per-cell counts -> cell_start; counts are cleared
+// exclusive scan of the per-cell counts -> cell_start; counts are cleared.
+// The tables are padded to whole 1024-cell chunks with zero counts, so the
+// entry after the last cell receives the particle total (the sentinel).
+// Three launches: chunk totals, a one-workgroup scan of the totals, and the
+// chunk scans with their offsets.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kScanBlock) void k_scan_partial(const uint32_t* __restrict__ count,
-                                                            uint32_t* __restrict__ partial,
-                                                            uint32_t n) {
-    __shared__ uint32_t lds[kScanBlock / kWave];
-    const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPerThread;
-    uint32_t s = 0;
-#pragma unroll
-    for (int k = 0; k < kScanPerThread; ++k) {
-        const uint32_t j = base + k;
-        s += (j < n) ? count[j] : 0u;
-    }
-    s = block_sum(s, lds);
+__global__ __launch_bounds__(256) void k_cscan_reduce(const uint4* __restrict__ count,
+                                                     uint32_t* __restrict__ partial) {
+    __shared__ uint32_t lds[256 / kWave];
+    const uint4 c = count[blockIdx.x * 256 + threadIdx.x];
+    const uint32_t s = block_sum(c.x + c.y + c.z + c.w, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(kScanBlock) void k_scan_final(uint32_t* __restrict__ count,
-                                                          const uint32_t* __restrict__ partial,
-                                                          uint32_t* __restrict__ cell_start,
-                                                          uint32_t n) {
-    __shared__ uint32_t lds[kScanBlock / kWave];
-    // prefix of the earlier chunks
-    uint32_t pre = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += blockDim.x) pre += partial[b];
-    pre = block_sum(pre, lds);
-    const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPerThread;
-    uint32_t v[kScanPerThread];
-    uint32_t s = 0;
+__global__ __launch_bounds__(1024) void k_cscan_mid(uint32_t* __restrict__ partial, uint32_t nb) {
+    __shared__ uint32_t lds[1024 / kWave];
+    uint32_t carry = 0;
+    for (uint32_t base = 0; base < nb; base += 4096) {
+        uint32_t v[4];
+        uint32_t s = 0;
 #pragma unroll
-    for (int k = 0; k < kScanPerThread; ++k) {
-        const uint32_t j = base + k;
-        v[k] = (j < n) ? count[j] : 0u;
-        s += v[k];
-    }
-    uint32_t tot;
-    uint32_t ex = block_exclusive_scan(s, lds, tot) + pre;
-#pragma unroll
-    for (int k = 0; k < kScanPerThread; ++k) {
-        const uint32_t j = base + k;
-        if (j < n) {
-            cell_start[j] = ex;
-            count[j] = 0u;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t j = base + threadIdx.x * 4 + k;
+            v[k] = (j < nb) ? partial[j] : 0u;
+            s += v[k];
         }
-        ex += v[k];
+        uint32_t tot;
+        uint32_t ex = block_exclusive_scan(s, lds, tot) + carry;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t j = base + threadIdx.x * 4 + k;
+            if (j < nb) partial[j] = ex;
+            ex += v[k];
+        }
+        carry += tot;
     }
+}
+
+__global__ __launch_bounds__(256) void k_cscan_final(uint4* __restrict__ count,
+                                                    const uint32_t* __restrict__ prefix,
+                                                    uint4* __restrict__ cell_start) {
+    __shared__ uint32_t lds[256 / kWave];
+    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
+    const uint4 c = count[j];
+    uint32_t tot;
+    const uint32_t ex = block_exclusive_scan(c.x + c.y + c.z + c.w, lds, tot) + prefix[blockIdx.x];
+    uint4 o;
+    o.x = ex;
+    o.y = ex + c.x;
+    o.z = o.y + c.y;
+    o.w = o.z + c.z;
+    cell_start[j] = o;
+    count[j] = make_uint4(0u, 0u, 0u, 0u);
 }
 
 hipError_t launch_scan(const uint32_t* count_in, uint32_t* cell_start, uint32_t* partial,
                        uint32_t ncell, hipStream_t s) {
-    const uint32_t nb = (ncell + kScanChunk - 1) / kScanChunk;
-    hipLaunchKernelGGL(k_scan_partial, dim3(nb), dim3(kScanBlock), 0, s, count_in, partial, ncell);
-    hipLaunchKernelGGL(k_scan_final, dim3(nb), dim3(kScanBlock), 0, s,
-                       const_cast<uint32_t*>(count_in), partial, cell_start, ncell);
+    const uint32_t nb = (uint32_t)(cell_pad(ncell) / kCellChunk);
+    uint4* cnt = reinterpret_cast<uint4*>(const_cast<uint32_t*>(count_in));
+    hipLaunchKernelGGL(k_cscan_reduce, dim3(nb), dim3(256), 0, s, cnt, partial);
+    hipLaunchKernelGGL(k_cscan_mid, dim3(1), dim3(1024), 0, s, partial, nb);
+    hipLaunchKernelGGL(k_cscan_final, dim3(nb), dim3(256), 0, s, cnt, partial,
+                       reinterpret_cast<uint4*>(cell_start));
     return hipGetLastError();
 }
 

@@ -89,6 +89,7 @@ template <int DIM, typename real, int KERN, int LANES, typename Fetch>
 __device__ __forceinline__ void walk_batched(const PairTerm<DIM, real, KERN>& term, const Target& T,
                                              real Ca, uint32_t s, uint32_t e, uint32_t lj,
                                              Fetch&& fetch, real& acc) {
+    constexpr int kBatch = Batch<LANES>::value;
     uint32_t b = s + lj;
     if (b >= e) return;
     const Cand<real> pad{T.ux + 0x80000000u, T.uy, T.uz, Ca};
