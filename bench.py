@@ -32,7 +32,27 @@ sys.path.insert(0, ROOT)
 # C_a - C_b (1), accumulation (3).
 FLOPS_PER_INTERACTION = {2: 29, 3: 39}
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published vector FP32 (packed FMA)
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.md")
+PAIR_SOURCES = ["kernels_pair.hip", "ade_geom.h", "ade_device.h", "ade_internal.h"]
 PEAK_FP32_NONPACKED_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA)
+
+
+def pair_traffic():
+    """HBM bytes per pair-kernel launch from the committed FETCH_SIZE/WRITE_SIZE
+    profile, or None when the kernel sources changed since it was taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    h = hashlib.sha256()
+    for f in PAIR_SOURCES:
+        with open(os.path.join(ROOT, "paper_2108_09488_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if vals.get("source_sha256", "").strip() != h.hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch"])
 
 
 def _sync():
@@ -229,6 +249,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip graph replay and batched runs")
     ap.add_argument("--cells", default="", help="comma-separated subset of the sweep plumes")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run one device-to-device copy of this many MiB (a known-size "
+                         "reference for the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep and the "
@@ -239,6 +262,13 @@ def main():
     from paper_2108_09488_amd import inputs as I
 
     device = "cuda:0"
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration * (1 << 20) // 4, dtype=torch.float32, device=device)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cells = args.cells.split(",") if args.cells else list(I.CFG2_CELLS)
     sweep = build_sweep(cells, device)
     for s in sweep:
@@ -291,7 +321,7 @@ def main():
                                "explicit Euler, dt Eq. (10)",
                    "plumes": cells, "interactions_per_step": inter_step, "per_plume": per_cell},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": pair_traffic(),
                      "kernel": "k_pair (step mode)", "avg_launch_ms": avg_ms,
                      "launches": pair["launches"],
                      "flops_per_interaction": FLOPS_PER_INTERACTION[2],
