@@ -3,9 +3,10 @@ advection-dispersion step on one MI355X.
 
 Workload (default): the 2D consistency sweep -- six 512^2-particle plumes on
 jittered lattices (+-0.1 dp), Wendland C4, h/dp in {1.3, 2, 3} x
-alpha_L/alpha_T in {10, 100}, FP32, dt from Eq. (10).  One bench step
-advances each of the six plumes by one explicit step (pair sum of Eqs. 4-5,
-update of C and x, cell-list rebuild).  value = sum over plumes of the
+alpha_L/alpha_T in {10, 100}, FP32, dt from Eq. (10), held in one context.
+One bench step advances each of the six plumes by one explicit step (pair sum
+of Eqs. 4-5, update of C and x, cell-list rebuild), one launch per kernel for
+all six.  value = sum over plumes of the
 directed interactions per step (pairs b != a with 0 < r <= H) times the
 steps, divided by the wall time of the timed region.
 
@@ -61,50 +62,42 @@ def _sync():
 
 
 def build_sweep(cells, device):
+    """The sweep plumes in one context: every kernel of a step is one launch
+    over all plumes (each plume keeps its own cell grid, dt and parameters)."""
     import numpy as np
     import torch
     from paper_2108_09488_amd import inputs as I
     from paper_2108_09488_amd.context import Context, params_from_spec
 
-    out = []
-    stream = torch.cuda.Stream(device=device)  # one stream: plumes run back to back
-    for name in cells:
-        spec = I.config(name)
-        ctx = Context([params_from_spec(spec)], [spec.n], device=device, stream=stream)
-        x = spec.positions()
-        C = spec.concentration(x)
-        ctx.init(torch.from_numpy(x), torch.from_numpy(C.astype(np.float32))).build()
-        off, _ = ctx.neighbours()
-        inter = int(off[-1].item())
-        out.append({"name": name, "spec": spec, "ctx": ctx, "interactions": inter})
-    return out
+    specs = [I.config(name) for name in cells]
+    stream = torch.cuda.Stream(device=device)
+    ctx = Context([params_from_spec(s) for s in specs], [s.n for s in specs], device=device,
+                  stream=stream)
+    xs = [s.positions() for s in specs]
+    Cs = [s.concentration(x).astype(np.float32) for s, x in zip(specs, xs)]
+    ctx.init(torch.from_numpy(np.concatenate(xs, axis=1)),
+             torch.from_numpy(np.concatenate(Cs))).build()
+    off, _ = ctx.neighbours()
+    bounds = np.concatenate([[0], np.cumsum([s.n for s in specs])])
+    per = [int(off[bounds[p + 1]].item() - off[bounds[p]].item()) for p in range(len(specs))]
+    return {"ctx": ctx, "specs": specs, "names": list(cells), "interactions": per}
 
 
 def time_sweep(sweep, steps, warmup, graph):
-    import torch
-    for s in sweep:
-        (s["ctx"].step_graph if graph else s["ctx"].step)(warmup)
+    ctx = sweep["ctx"]
+    (ctx.step_graph if graph else ctx.step)(warmup)
     _sync()
     if not graph:
-        for s in sweep:
-            s["ctx"].timing_start()
+        ctx.timing_start()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        for s in sweep:
-            (s["ctx"].step_graph if graph else s["ctx"].step)(1)
+    (ctx.step_graph if graph else ctx.step)(steps)
     _sync()
     wall = time.perf_counter() - t0
     pair = None
     if not graph:
-        ms = 0.0
-        n = 0
-        flops = 0.0
-        for s in sweep:
-            m, c = s["ctx"].timing_stop()
-            ms += m
-            n += c
-            flops += s["interactions"] * FLOPS_PER_INTERACTION[s["spec"].dim] * c
-        pair = {"ms_total": ms, "launches": n, "flops": flops}
+        ms, c = ctx.timing_stop()
+        flops = sum(i * FLOPS_PER_INTERACTION[s.dim] for i, s in zip(sweep["interactions"], sweep["specs"]))
+        pair = {"ms_total": ms, "launches": c, "flops": flops * c}
     return wall, pair
 
 
@@ -271,10 +264,10 @@ def main():
         del src, dst
     cells = args.cells.split(",") if args.cells else list(I.CFG2_CELLS)
     sweep = build_sweep(cells, device)
-    for s in sweep:
-        s["tuning"] = s["ctx"].autotune(reps=3)
-    inter_step = sum(s["interactions"] for s in sweep)
-    print(f"[bench] sweep built: {len(sweep)} plumes, {inter_step} interactions per step", file=sys.stderr, flush=True)
+    sweep["tuning"] = sweep["ctx"].autotune(reps=3)
+    inter_step = sum(sweep["interactions"])
+    print(f"[bench] sweep built: {len(cells)} plumes, {inter_step} interactions per step, "
+          f"tuning {sweep['tuning']}", file=sys.stderr, flush=True)
 
     # timed region: every plume's captured step replayed from its HIP graph
     wall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
@@ -297,11 +290,9 @@ def main():
         print(f"[bench] fwd+adjoint: {extras['fwd_adjoint']['ms_fwd_adjoint']:.1f} ms", file=sys.stderr, flush=True)
         extras["single_3d"] = single_3d(device)
         print(f"[bench] 3D: {extras['single_3d']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
-    per_cell = {s["name"]: {"interactions_per_step": s["interactions"],
-                            "neighbours_mean": s["interactions"] / s["spec"].n,
-                            "tuning": s["tuning"]} for s in sweep}
-    for s in sweep:
-        s["ctx"].close()
+    per_cell = {n: {"interactions_per_step": i, "neighbours_mean": i / s.n}
+                for n, i, s in zip(sweep["names"], sweep["interactions"], sweep["specs"])}
+    sweep["ctx"].close()
 
     line = {
         "metric": "particle-neighbour interactions/s per ADE step (fwd, fwd+adjoint, batched) vs plain",
@@ -319,7 +310,8 @@ def main():
         "config": {"workload": "2D consistency sweep: 6 plumes x 512^2 particles, jitter 0.1 dp, "
                                "Wendland C4, h/dp {1.3,2,3} x alpha_L/alpha_T {10,100}, FP32, "
                                "explicit Euler, dt Eq. (10)",
-                   "plumes": cells, "interactions_per_step": inter_step, "per_plume": per_cell},
+                   "plumes": cells, "interactions_per_step": inter_step, "per_plume": per_cell,
+                   "tuning": sweep["tuning"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": pair_traffic(),
                      "kernel": "k_pair (step mode)", "avg_launch_ms": avg_ms,

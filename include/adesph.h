@@ -87,14 +87,19 @@ typedef struct {
  * lanes sets how many lanes of a wavefront share one target particle (its
  * candidates are interleaved over them and the partial sums are combined by
  * a wavefront reduction); with N particles the kernel runs N*lanes/64
- * wavefronts, so lanes is the waves-per-CU knob.  The summation order, and so
- * the last bits of the result, depend on lanes and on nothing else here. */
+ * wavefronts, so lanes is the waves-per-CU knob.  Each target keeps the list
+ * of its candidate ranges in LDS: 8 * (2 * rows + 2) bytes per target, rows =
+ * (2R+1)^(dim-1) neighbour rows of the plume with the most, and block / lanes
+ * targets per workgroup must fit in 64 KiB (ADE_EINVAL otherwise).  The
+ * summation order, and so the last bits of the result, depend on lanes and on
+ * nothing else here. */
 typedef struct {
     int32_t block;          /* threads per workgroup: 64, 128 or 256          */
     int32_t lanes;          /* lanes per target particle: 1, 2 or 4           */
-    int32_t stage_lds;      /* neighbour-particle records staged in LDS per
-                               thread (16 B each; 0 = read candidates from
-                               global memory); stage_lds*block*16 <= 64 KiB  */
+    int32_t xcd_group;      /* work items (tiles or parts of tiles) each XCD
+                               takes in turn, so that neighbouring items
+                               share an L2 while the XCDs share every part
+                               of the work evenly; 0 = default (32)          */
     int32_t persistent;     /* 0: one workgroup per work item; > 0: a grid of
                                that many workgroups loops over the items     */
 } ade_tuning;
@@ -106,7 +111,10 @@ int ade_workspace_bytes(const ade_params *params, const int64_t *counts, int32_t
 
 /* Validates the parameters and lays out the caller's workspace d_ws
  * (ws_bytes >= ade_workspace_bytes, 256-byte aligned); stream is a
- * hipStream_t (NULL: the default stream).  *out receives the context. */
+ * hipStream_t (NULL: the default stream).  *out receives the context.  A
+ * context holds at most 2^28 - 1 particles in total (candidate records are
+ * addressed with 32-bit byte offsets); larger ensembles take several
+ * contexts. */
 int ade_create(const ade_params *params, const int64_t *counts, int32_t nplumes, void *d_ws,
                size_t ws_bytes, void *stream, ade_ctx **out);
 
@@ -173,7 +181,8 @@ int ade_kernel_timing(ade_ctx *ctx, int32_t mode, double *h_ms, int64_t *h_count
 
 /* Autotuner: times the pair kernel (reps launches each, HIP events on the
  * context's stream) over the launch shapes block {64,128,256} x lanes {1,2,4}
- * x stage_lds {0, 8} x persistent {0, 8 workgroups per CU}, keeps the fastest
+ * x persistent {0, 8 workgroups per CU} x xcd_group {8, 32, 128} that fit the
+ * LDS limit, keeps the fastest
  * in the context and returns it in *best (may be NULL).  With
  * ADE_TUNE_KEEP_LANES the current lanes value is kept, so results stay
  * bitwise identical to the untuned context.  Needs built cells; does not

@@ -39,7 +39,7 @@ class AdeParams(ct.Structure):
 
 
 class AdeTuning(ct.Structure):
-    _fields_ = [("block", ct.c_int32), ("lanes", ct.c_int32), ("stage_lds", ct.c_int32),
+    _fields_ = [("block", ct.c_int32), ("lanes", ct.c_int32), ("xcd_group", ct.c_int32),
                 ("persistent", ct.c_int32)]
 
 

@@ -174,17 +174,16 @@ class Context:
         t = AdeTuning()
         check(lib().ade_autotune(self._h, int(reps), _lib.ADE_TUNE_KEEP_LANES if keep_lanes else 0,
                                  ct.byref(t)))
-        return {"block": t.block, "lanes": t.lanes, "stage_lds": t.stage_lds, "persistent": t.persistent}
+        return {"block": t.block, "lanes": t.lanes, "xcd_group": t.xcd_group, "persistent": t.persistent}
 
-    def set_tuning(self, block=256, lanes=2, stage_lds=0, persistent=0):
-        t = AdeTuning(block, lanes, stage_lds, persistent)
+    def set_tuning(self, block=256, lanes=2, persistent=0, xcd_group=0):
+        t = AdeTuning(block, lanes, xcd_group, persistent)
         check(lib().ade_set_tuning(self._h, ct.byref(t)))
 
     def get_tuning(self) -> dict:
         t = AdeTuning()
         check(lib().ade_get_tuning(self._h, ct.byref(t)))
-        return {"block": t.block, "lanes": t.lanes, "stage_lds": t.stage_lds,
-                "persistent": t.persistent}
+        return {"block": t.block, "lanes": t.lanes, "xcd_group": t.xcd_group, "persistent": t.persistent}
 
     def adjoint(self, nsteps: int, ckpt_every: int, xs: torch.Tensor, obs: torch.Tensor):
         """J and dJ/d(alpha_L, alpha_T, D_m) of plume 0 after nsteps Euler steps."""

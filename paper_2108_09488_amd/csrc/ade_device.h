@@ -8,14 +8,28 @@ namespace ade {
 constexpr int kWave = 64;
 
 // Workgroups of one launch are dispatched round-robin over the 8 XCDs of the
-// chip (block b runs on XCD b % 8).  Give each XCD a contiguous range of tiles
-// so that tiles sharing neighbour cells also share an L2.
-__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n) {
-    const uint32_t nx = 8;
-    if (n < nx) return b;
-    const uint32_t per = n / nx, rem = n % nx;
-    const uint32_t x = b % nx, k = b / nx;
-    return x * per + (x < rem ? x : rem) + k;
+// chip (workgroup b runs on XCD b % 8).  Items are dealt to the XCDs in turns
+// of `group` consecutive items, so that neighbouring items (which share
+// candidate cells) share an L2 while every XCD still gets an even share of
+// every part of the item list (plumes of an ensemble differ in cost per item).
+// A bijection of [0, n): the last incomplete round keeps the identity.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t n, uint32_t group) {
+    const uint32_t nx = 8, round = nx * group;
+    const uint32_t full = n / round * round;
+    if (b >= full) return b;
+    const uint32_t g = b / round, r = b % round;
+    return g * round + (r % nx) * group + r / nx;
+}
+
+// The m-th item (m = 0, 1, ...) that xcd_remap deals to XCD x, or n when
+// XCD x has fewer than m + 1 items (the persistent grid walks this list).
+__device__ __forceinline__ uint32_t xcd_item(uint32_t x, uint32_t m, uint32_t n, uint32_t group) {
+    const uint32_t nx = 8, round = nx * group;
+    const uint32_t full = n / round * round;
+    const uint32_t per = full / nx;  // items of XCD x in complete rounds
+    if (m < per) return (m / group) * round + x * group + m % group;
+    const uint32_t t = full + x + (m - per) * nx;  // the identity tail, round-robin
+    return t < n ? t : n;
 }
 
 // Cell of a fixed-point position: rows of the (y[, z]) grid, x cells inside a row.

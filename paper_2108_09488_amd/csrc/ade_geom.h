@@ -20,11 +20,10 @@ __device__ __forceinline__ real h2_of(const PlumeDev& P) {
 }
 
 constexpr int kMaxRowOffsets = 81;  // (2R+1)^2 for R <= 4
-// candidate records fetched together before use: long batches when one lane
-// walks a target's rows alone, shorter ones when lanes share a target
+// candidate records each lane fetches together, ahead of their use
 template <int LANES>
 struct Batch {
-    static constexpr int value = (LANES == 1) ? 8 : 4;
+    static constexpr int value = 4;
 };
 
 // A target particle: fixed-point position, its row and the fractional

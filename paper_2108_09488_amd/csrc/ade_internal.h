@@ -34,7 +34,10 @@ struct PlumeDev {
     double invHu;
     float Hc2f;             // square of the search radius Hc = H_u (1 + 2^-16) + 2
     float rowh2f;           // square of the row height in grid units, (2^32 / nr)^2
-    double kg[6];           // Gamma * D: xx, yy, zz, 2xy, 2xz, 2yz
+    double a0, a1;          // Gamma x^T D x / r^2 - tr D = a0 + a1 (e . x / r)^2 (Eq. 3 tensor)
+    double ehat[3];         // unit flow direction e (x axis when |v| = 0)
+    double invHu5;          // 5 / Hu
+    float fterm[8];         // FP32 pair-term constants: H2f, invHu, invHu5, a0, a1, e_x, e_y, e_z
     double trD;             // trace of D
     double vphi;            // V * (kernel derivative prefactor): rhs = vphi * sum
     double dt;
@@ -66,8 +69,9 @@ struct PairLaunch {
     uint32_t ntiles;
     int block;              // threads per workgroup
     int lanes;              // lanes per target particle (1, 2 or 4)
-    int stage;              // LDS records staged per thread (0: read candidates from global memory)
+    int list_cap;           // candidate-list entries per target in LDS (2 * rows + 2)
     int persistent;         // 0: one workgroup per work item; > 0: that many workgroups loop
+    uint32_t xcd_group;     // consecutive work items an XCD takes in turn (>= 1)
     const uint4* rec;       // candidate records (position + C of Cpair), or null: SoA reads
     const uint32_t* spos[3];
     const uint32_t* sid;
@@ -87,6 +91,16 @@ struct PairLaunch {
     uint4* out_rec;         // half: candidate records with the half-step C (S order)
     hipEvent_t ev0, ev1;    // if set: events stamped at the kernel's start and end
 };
+
+// candidate-list capacity per target for plumes with at most noff neighbour
+// rows (each row can be split in two at the periodic seam, plus a sentinel
+// and one entry read past it)
+inline int list_cap_for(int noff) { return 2 * noff + 2; }
+// LDS bytes of the pair kernel's candidate lists for a workgroup
+inline size_t pair_lds_bytes(int block, int lanes, int list_cap) {
+    return (size_t)(block / lanes) * (size_t)list_cap * 8u;
+}
+constexpr size_t kPairLdsMax = 65536;
 
 // kernel launchers (kernels_*.hip); all return hipError_t of the launch
 hipError_t launch_init(int dim, int real_bytes, const PlumeDev* plumes, const TileDev* tiles,

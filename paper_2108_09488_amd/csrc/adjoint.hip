@@ -158,7 +158,6 @@ __global__ __launch_bounds__(256) void k_gather_sorted(const uint32_t* __restric
 }
 
 struct AdjConst {
-    double vhat[3];  // unit flow direction (0 if |v| = 0)
     double speed;    // |v|
 };
 
@@ -179,11 +178,9 @@ __global__ __launch_bounds__(kTile) void k_adjoint(const PlumeDev* __restrict__ 
     const uint32_t* pz = S.pos[2];
     const real* C = static_cast<const real*>(S.C);
     const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
-    const real kxx = (real)P.kg[0], kyy = (real)P.kg[1], kzz = (real)P.kg[2];
-    const real kxy = (real)P.kg[3], kxz = (real)P.kg[4], kyz = (real)P.kg[5];
-    const real trD = (real)P.trD;
+    const real a0 = (real)P.a0, a1 = (real)P.a1;
     const real gam = (real)(DIM + 2), spd = (real)ac.speed;
-    const real vx = (real)ac.vhat[0], vy = (real)ac.vhat[1], vz = (real)ac.vhat[2];
+    const real vx = (real)P.ehat[0], vy = (real)P.ehat[1], vz = (real)P.ehat[2];
     real al = 0, g1 = 0, g2 = 0, g3 = 0, li = 0;
     if (active) {
         const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
@@ -213,15 +210,11 @@ __global__ __launch_bounds__(kTile) void k_adjoint(const PlumeDev* __restrict__ 
                         } else {
                             f = omq * omq * omq;
                         }
-                        real Q;
-                        if (DIM == 3)
-                            Q = dx * (kxx * dx + kxy * dy + kxz * dz) + dy * (kyy * dy + kyz * dz) + kzz * dz * dz;
-                        else
-                            Q = dx * (kxx * dx + kxy * dy) + kyy * dy * dy;
+                        // Gamma x^T D x / r^2 - tr D = a0 + a1 p, p = (e . x / r)^2
                         const real ir2 = rinv * rinv;
-                        const real A = Q * ir2 - trD;
                         const real xv = dx * vx + dy * vy + dz * vz;
                         const real p = xv * xv * ir2;
+                        const real A = fmar(a1, p, a0);
                         const real dCf = (Ci - C[b]) * f;
                         al = fmar(A * f, li - lam_s[b], al);
                         g1 = fmar(spd * (gam * p - (real)1), dCf, g1);
@@ -472,7 +465,6 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
         for (int k = 0; k < pl.dim; ++k) sp += P.vel[k] * P.vel[k];
         sp = std::sqrt(sp);
         ac.speed = sp;
-        for (int k = 0; k < 3; ++k) ac.vhat[k] = sp > 0 ? P.vel[k] / sp : 0.0;
     }
 
     // reverse sweep, segment by segment

@@ -34,6 +34,12 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+bool tuning_fits(const Plan& pl, const ade_tuning& t) {
+    if (t.block != 64 && t.block != 128 && t.block != 256) return false;
+    if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4) return false;
+    return pair_lds_bytes(t.block, t.lanes, pl.list_cap) <= kPairLdsMax;
+}
+
 double trace_D(int dim, double aL, double aT, double Dm, const double* v, double D[9]) {
     double s2 = 0;
     for (int i = 0; i < dim; ++i) s2 += v[i] * v[i];
@@ -126,7 +132,7 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         d.poff = (uint32_t)N;
         d.n = (uint32_t)counts[p];
         N += (uint64_t)counts[p];
-        if (N > 0x7fffffffull) return fail(ADE_EINVAL, "at most 2^31 - 1 particles in total");
+        if (N > 0x0fffffffull) return fail(ADE_EINVAL, "at most 2^28 - 1 particles per context");
 
         // cell grid in grid units: rows of height >= Hc / rows_per_H, x cells of width >= Hc / xsub
         const double Hu = q.H / q.L * kTwo32;
@@ -161,12 +167,17 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         double D[9];
         const double trD = trace_D(pl.dim, q.alpha_L, q.alpha_T, q.D_m, q.v, D);
         const double gamma = pl.dim + 2.0;
-        d.kg[0] = gamma * D[0];
-        d.kg[1] = gamma * D[4];
-        d.kg[2] = (pl.dim == 3) ? gamma * D[8] : 0.0;
-        d.kg[3] = 2.0 * gamma * D[1];
-        d.kg[4] = (pl.dim == 3) ? 2.0 * gamma * D[2] : 0.0;
-        d.kg[5] = (pl.dim == 3) ? 2.0 * gamma * D[5] : 0.0;
+        double s2 = 0.0;
+        for (int c = 0; c < pl.dim; ++c) s2 += q.v[c] * q.v[c];
+        const double sp = std::sqrt(s2);
+        // Gamma x^T D x / r^2 - tr D for the tensor of Eq. (3) split into its
+        // isotropic part and the part along the flow direction e
+        d.a0 = (gamma - pl.dim) * (q.alpha_T * sp + q.D_m) - (q.alpha_L - q.alpha_T) * sp;
+        d.a1 = gamma * (q.alpha_L - q.alpha_T) * sp;
+        for (int c = 0; c < 3; ++c) d.ehat[c] = (sp > 0) ? ((c < pl.dim) ? q.v[c] / sp : 0.0) : (c == 0 ? 1.0 : 0.0);
+        d.invHu5 = 5.0 / Hu;
+        const double ft[8] = {Hu * Hu, 1.0 / Hu, 5.0 / Hu, d.a0, d.a1, d.ehat[0], d.ehat[1], d.ehat[2]};
+        for (int k = 0; k < 8; ++k) d.fterm[k] = (float)ft[k];
         d.trD = trD;
         const double V = q.mass / q.rho0;
         d.vphi = V * kernel_phi_prefactor(pl.kernel, pl.dim, q.H);
@@ -196,6 +207,8 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
             pl.tiles.push_back(t);
         }
         d.tcount = (uint32_t)pl.tiles.size() - d.tfirst;
+        const int span = 2 * R + 1;
+        pl.list_cap = std::max(pl.list_cap, list_cap_for(pl.dim == 3 ? span * span : span));
         pl.plumes.push_back(d);
     }
     pl.N = (int64_t)N;
@@ -289,8 +302,9 @@ PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase,
     a.ntiles = c->plan.ntiles;
     a.block = c->tuning.block;
     a.lanes = c->tuning.lanes;
-    a.stage = c->tuning.stage_lds;
+    a.list_cap = c->plan.list_cap;
     a.persistent = c->tuning.persistent;
+    a.xcd_group = c->tuning.xcd_group > 0 ? (uint32_t)c->tuning.xcd_group : 32u;
     // candidate records carrying the concentrations the pair sum reads
     a.rec = (Cpair == c->aux) ? c->aux_rec : c->S.rec;
     a.out_rec = c->aux_rec;
@@ -384,6 +398,21 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
     if (rc) {
         delete c;
         return rc;
+    }
+    // default launch shape: two lanes per target, else four, else smaller
+    // workgroups, whichever first fits the LDS of the candidate lists
+    {
+        const ade_tuning defaults[4] = {{256, 2, 0, 0}, {256, 4, 0, 0}, {128, 4, 0, 0}, {64, 4, 0, 0}};
+        bool ok = false;
+        for (const ade_tuning& t : defaults)
+            if (!ok && tuning_fits(c->plan, t)) {
+                c->tuning = t;
+                ok = true;
+            }
+        if (!ok) {
+            delete c;
+            return fail(ADE_EINVAL, "too many neighbour rows: the candidate lists do not fit in LDS");
+        }
     }
     Bump b(d_ws);
     layout(b, c, c->plan);
@@ -551,14 +580,15 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     ade_tuning best_t = start;
     bool have = false;
     int rc = ADE_OK;
-    const int blocks[3] = {64, 128, 256}, lanes[3] = {1, 2, 4}, stages[2] = {0, 8}, pers[2] = {0, 2048};
+    const int blocks[3] = {64, 128, 256}, lanes[3] = {1, 2, 4}, pers[2] = {0, 2048}, groups[3] = {8, 32, 128};
     for (int lb : lanes) {
         if ((flags & ADE_TUNE_KEEP_LANES) && lb != start.lanes) continue;
         for (int bb : blocks)
-            for (int st : stages)
+            for (int xg : groups)
                 for (int pp : pers) {
-                    if ((size_t)st * bb * 16u > 65536u) continue;
-                    c->tuning = ade_tuning{bb, lb, st, pp};
+                    const ade_tuning cand{bb, lb, xg, pp};
+                    if (!tuning_fits(pl, cand)) continue;
+                    c->tuning = cand;
                     PairLaunch a = pair_args(c, kModeRhs, c->S.C, c->S.C, 1.0, c->aux);
                     if ((rc = run_pair(c, kModeRhs, a))) break;  // warm-up
                     if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(ADE_EHIP, "event record"); break; }
@@ -593,8 +623,10 @@ int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
     if (t->block != 64 && t->block != 128 && t->block != 256)
         return fail(ADE_EINVAL, "block must be 64, 128 or 256");
     if (t->lanes != 1 && t->lanes != 2 && t->lanes != 4) return fail(ADE_EINVAL, "lanes must be 1, 2 or 4");
-    if (t->stage_lds < 0 || (size_t)t->stage_lds * (size_t)t->block * 16u > 65536u)
-        return fail(ADE_EINVAL, "stage_lds * block * 16 bytes must fit in 64 KiB of LDS");
+    if (t->xcd_group < 0 || t->xcd_group > 4096) return fail(ADE_EINVAL, "xcd_group in 0..4096");
+    if (!tuning_fits(c->plan, *t))
+        return fail(ADE_EINVAL, "candidate lists of block/lanes = %d targets need %zu bytes of LDS (max %zu)",
+                    t->block / t->lanes, pair_lds_bytes(t->block, t->lanes, c->plan.list_cap), kPairLdsMax);
     if (t->persistent < 0 || t->persistent > 65536) return fail(ADE_EINVAL, "persistent in 0..65536");
     c->tuning = *t;
     drop_graph(c);

@@ -28,9 +28,13 @@ struct Plan {
     int64_t N = 0;
     uint64_t ncell = 0;
     uint32_t ntiles = 0, nscan = 0;
+    int list_cap = 0;  // candidate-list entries per target (largest plume)
     std::vector<PlumeDev> plumes;
     std::vector<TileDev> tiles;
 };
+
+// whether a launch shape fits the plan (LDS of the candidate lists)
+bool tuning_fits(const Plan& pl, const ade_tuning& t);
 
 // D of Eq. (3) for a uniform flow (row stride 3); returns its trace.
 double trace_D(int dim, double aL, double aT, double Dm, const double* v, double D[9]);

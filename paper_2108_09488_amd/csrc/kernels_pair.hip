@@ -8,9 +8,12 @@
 // with V = m / rho and, for the Wendland kernels of Eq. (7) with support H,
 //     C4: W'(r)/r = -(56/3) (B / H^2) (1 - q)^5 (1 + 5 q),
 //     C2: W'(r)/r = -20 (B / H^2) (1 - q)^3,        q = r / H.
-// Separations are taken in grid units (L / 2^32) from the fixed-point
-// positions; Gamma x^T D x / r^2 is scale free and the constant factor
-// V (W'(r)/r)/f(q) is applied once per particle (PlumeDev::vphi).
+// With D from Eq. (3) the bracket is a0 + a1 (e . x_ab / r)^2, e = v / |v|,
+// a0 = (Gamma - d)(alpha_T |v| + D_m) - (alpha_L - alpha_T)|v| and
+// a1 = Gamma (alpha_L - alpha_T)|v|.  Separations are taken in grid units
+// (L / 2^32) from the fixed-point positions; the bracket is scale free and
+// the constant factor V (W'(r)/r)/f(q) is applied once per particle
+// (PlumeDev::vphi).
 //
 // Neighbour predicate (shared with the neighbour-list export): d = (int32)
 // (u_a - u_b) per component (the two's-complement wrap is the minimum image),
@@ -21,54 +24,84 @@
 // height >= Hc / R in y (and z).  For each of the (2R+1)^(d-1) rows around a
 // target, the x cells that can hold neighbours form one contiguous range of
 // the sorted order (two at the periodic seam), cut to the chord of the
-// search radius at the row's nearest edge.  Each lane walks its ranges in
-// batches of kBatch candidate records, the next batch in flight while the
-// current one is evaluated, and the cell-start bounds of the next row in
-// flight while the current row is walked.  Optionally a workgroup first
-// stages the union of its candidate ranges in LDS (coalesced reads) and the
-// lanes walk the staged copy, falling back to global memory for a range
-// outside it.
+// search radius at the row's nearest edge.  A target's non-empty ranges are
+// listed in LDS, in row order, and its LANES lanes walk the concatenation of
+// the list as one stream (lane j takes elements j, j + LANES, ...): a lane
+// crosses from one range into the next inside a batch, so candidates are
+// fetched in batches of kBatch records with no per-row rounding and no
+// pipeline drain at a row boundary.  The next batch is in flight while the
+// current one is evaluated.
 #include <hip/hip_ext.h>
 
 #include "ade_geom.h"
 
 namespace ade {
 
-// One candidate: predicate and, if inside the support, the pair term.
+// One candidate: predicate and pair term, evaluated without a branch (the
+// lanes of a wavefront almost never all fail the predicate together) and
+// kept only inside the support.  Outside it, and for r2 = 0 where the
+// reciprocal square root is infinite, the discarded value may be anything;
+// it is never added.
 template <int DIM, typename real, int KERN>
 struct PairTerm {
-    real H2, invHu, kxx, kyy, kzz, kxy, kxz, kyz, trD;
+    real H2, invHu, invHu5, a0, a1, ex, ey, ez;
     __device__ __forceinline__ void operator()(const Target& T, real Ca, uint32_t bx, uint32_t by,
                                                uint32_t bz, real Cb, real& acc) const {
         const real dx = (real)(int32_t)(T.ux - bx);
         const real dy = (real)(int32_t)(T.uy - by);
         const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - bz) : (real)0;
-        const real dC = Ca - Cb;  // formed before the test: the whole record is fetched at once
         real r2 = dx * dx;
         r2 = fmar(dy, dy, r2);
         if (DIM == 3) r2 = fmar(dz, dz, r2);
-        if (r2 > (real)0 && r2 <= H2) {
-            const real rinv = rsqrt_r(r2);
-            const real q = r2 * rinv * invHu;
-            real omq = (real)1 - q;
-            omq = omq > (real)0 ? omq : (real)0;
-            real f;
-            if (KERN == 4) {
-                const real o2 = omq * omq;
-                f = o2 * o2 * omq * fmar((real)5, q, (real)1);
-            } else {
-                f = omq * omq * omq;
-            }
-            real Q;
-            if (DIM == 3)
-                Q = dx * (kxx * dx + kxy * dy + kxz * dz) + dy * (kyy * dy + kyz * dz) + kzz * dz * dz;
-            else
-                Q = dx * (kxx * dx + kxy * dy) + kyy * dy * dy;
-            const real A = Q * (rinv * rinv) - trD;
-            acc = fmar(A * f, dC, acc);
+        const bool inside = r2 > (real)0 && r2 <= H2;
+        const real rinv = rsqrt_r(r2);
+        const real r = r2 * rinv;
+        // 1 - q; inside the support up to the rounding of r (a negative value
+        // of a few ulps contributes a term below 1e-30 of the others)
+        const real omq = fmar(-r, invHu, (real)1);
+        real f;
+        if (KERN == 4) {
+            const real o2 = omq * omq;
+            f = o2 * o2 * omq * fmar(r, invHu5, (real)1);
+        } else {
+            f = omq * omq * omq;
         }
+        real p = ex * dx;
+        p = fmar(ey, dy, p);
+        if (DIM == 3) p = fmar(ez, dz, p);
+        const real pr = p * rinv;
+        const real A = fmar(a1 * pr, pr, a0);
+        const real w = inside ? A * f : (real)0;
+        acc = fmar(w, Ca - Cb, acc);
     }
 };
+
+// the constants come from the plume table as they are (FP32 copies for FP32),
+// so they stay in scalar registers
+template <int DIM, typename real, int KERN>
+__device__ __forceinline__ PairTerm<DIM, real, KERN> make_term(const PlumeDev& P) {
+    PairTerm<DIM, real, KERN> t;
+    if (sizeof(real) == 4) {
+        t.H2 = (real)P.fterm[0];
+        t.invHu = (real)P.fterm[1];
+        t.invHu5 = (real)P.fterm[2];
+        t.a0 = (real)P.fterm[3];
+        t.a1 = (real)P.fterm[4];
+        t.ex = (real)P.fterm[5];
+        t.ey = (real)P.fterm[6];
+        t.ez = (real)P.fterm[7];
+    } else {
+        t.H2 = (real)P.H2d;
+        t.invHu = (real)P.invHu;
+        t.invHu5 = (real)P.invHu5;
+        t.a0 = (real)P.a0;
+        t.a1 = (real)P.a1;
+        t.ex = (real)P.ehat[0];
+        t.ey = (real)P.ehat[1];
+        t.ez = (real)P.ehat[2];
+    }
+    return t;
+}
 
 template <typename real>
 struct Cand {
@@ -81,168 +114,191 @@ __device__ __forceinline__ Cand<real> unpack(const uint4& r) {
     return Cand<real>{r.x, r.y, (DIM == 3) ? r.z : 0u, Rec<DIM, real>::conc(r)};
 }
 
-// Walk the candidates b = s + lane, s + lane + LANES, ... < e in batches of
-// kBatch: the batch after the current one is fetched before the current one
-// is evaluated.  Past the end of the range a batch is padded with a record
-// half the box away from the target, which fails the predicate.
-template <int DIM, typename real, int KERN, int LANES, typename Fetch>
-__device__ __forceinline__ void walk_batched(const PairTerm<DIM, real, KERN>& term, const Target& T,
-                                             real Ca, uint32_t s, uint32_t e, uint32_t lj,
-                                             Fetch&& fetch, real& acc) {
-    constexpr int kBatch = Batch<LANES>::value;
-    uint32_t b = s + lj;
-    if (b >= e) return;
-    const Cand<real> pad{T.ux + 0x80000000u, T.uy, T.uz, Ca};
-    Cand<real> cur[kBatch];
+// ---------------------------------------------------------------------------
+// Candidate list of a target in LDS.  Entry k holds (delta_k, e_k): the range
+// [s_k, e_k) of the sorted order and delta_k = s_k - e_(k-1) (e_(-1) = 0).
+// A sentinel closes the list; stepping into it puts the cursor at 2^31 or
+// more with the end at 2^30, so no slot is valid after it and no further
+// step is taken.  Entries of one target are `stride` apart (the targets of a
+// workgroup interleaved), and list[0] is the target's first entry.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kListEndStart = 0x80000000u, kListEndEnd = 0x40000000u;
+
+template <int DIM>
+__device__ __forceinline__ uint32_t build_list(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                               const Target& T, uint2* list, uint32_t stride) {
+    const int span = 2 * P.R + 1;
+    const int noff = (DIM == 3) ? span * span : span;
+    uint32_t prev = 0, k = 0, total = 0;
+    // four rows at a time: their cell-start loads are in flight together
+    for (int j = 0; j < noff; j += 4) {
+        RowRanges r[4];
 #pragma unroll
-    for (int q = 0; q < kBatch; ++q) {
-        const uint32_t bb = b + q * LANES;
-        cur[q] = (bb < e) ? fetch(bb) : pad;
-    }
-    for (;;) {
-        const uint32_t bn = b + kBatch * LANES;
-        const bool more = bn < e;
-        Cand<real> nxt[kBatch];
-        if (more) {
-#pragma unroll
-            for (int q = 0; q < kBatch; ++q) {
-                const uint32_t bb = bn + q * LANES;
-                nxt[q] = (bb < e) ? fetch(bb) : pad;
-            }
+        for (int q = 0; q < 4; ++q) {
+            r[q] = RowRanges{0u, 0u, 0u, 0u};
+            if (j + q < noff) r[q] = row_ranges<DIM>(P, cs, T, j + q, span);
         }
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q) term(T, Ca, cur[q].x, cur[q].y, cur[q].z, cur[q].C, acc);
-        if (!more) break;
+        for (int q = 0; q < 4; ++q) {
+            if (r[q].e0 > r[q].s0) {
+                list[k * stride] = make_uint2(r[q].s0 - prev, r[q].e0);
+                total += r[q].e0 - r[q].s0;
+                prev = r[q].e0;
+                ++k;
+            }
+            if (r[q].e1 > r[q].s1) {
+                list[k * stride] = make_uint2(r[q].s1 - prev, r[q].e1);
+                total += r[q].e1 - r[q].s1;
+                prev = r[q].e1;
+                ++k;
+            }
+        }
+    }
+    list[k * stride] = make_uint2(kListEndStart - prev, kListEndEnd);
+    return total;
+}
+
+// Lane cursor over the concatenated ranges: b is the next sorted index of
+// this lane, e the end of its range; nx the entry after the current one (in
+// flight from LDS).  After a step of LANES, b - e < LANES exactly when the
+// lane has run past the end of its range by less than one stride, which is
+// the overshoot carried into the next range.
+template <int LANES>
+struct Cursor {
+    uint32_t b, e;
+    uint2 nx;
+    const uint2* lp;
+    uint32_t stride;
+    __device__ __forceinline__ void settle() {
+        while (b - e < (uint32_t)LANES) {
+            b += nx.x;
+            e = nx.y;
+            lp += stride;
+            nx = *lp;
+        }
+    }
+};
+
+// Walk a target's list: every lane evaluates its share of the concatenated
+// ranges in batches of B records.  The wavefront runs as many batches as its
+// longest share needs (a uniform count, from the list totals); a slot past
+// the end of a lane's share re-reads the target's own record (index self),
+// which the predicate rejects (r2 = 0).  So every load is unconditional, and
+// the loads of one batch stay in flight, in order, while the previous batch
+// is evaluated.
+template <int DIM, typename real, int KERN, int LANES, typename Fetch>
+__device__ __forceinline__ void walk_list(const PairTerm<DIM, real, KERN>& term, const Target& T,
+                                          real Ca, uint32_t self, const uint2* list, uint32_t stride,
+                                          uint32_t total, uint32_t lj, Fetch&& fetch, real& acc) {
+    constexpr int B = Batch<LANES>::value;
+    // batches of the wavefront: the largest share of its lanes, in batches
+    uint32_t share = total > lj ? (total - lj + LANES - 1) / LANES : 0u;
 #pragma unroll
-        for (int q = 0; q < kBatch; ++q) cur[q] = nxt[q];
-        b = bn;
+    for (int o = kWave / 2; o > 0; o >>= 1) share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
+    const uint32_t nb = __builtin_amdgcn_readfirstlane((share + B - 1) / B);
+    if (nb == 0) return;
+
+    Cursor<LANES> cur;
+    cur.b = lj;
+    cur.e = 0;
+    cur.lp = list;
+    cur.stride = stride;
+    cur.nx = list[0];
+    cur.settle();
+
+    // nothing older than the first batch is in flight when the loop starts,
+    // so both entries into the loop carry the same outstanding loads
+    __builtin_amdgcn_s_waitcnt(0);
+    Cand<real> c0[B], c1[B];
+    auto fill = [&](Cand<real>(&c)[B]) {
+        uint32_t idx[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            idx[q] = cur.b < cur.e ? cur.b : self;
+            cur.b += LANES;
+            cur.settle();
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) c[q] = fetch(idx[q]);
+        // keep the loads here, ahead of the evaluation they overlap with
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto eval = [&](const Cand<real>(&c)[B]) {
+#pragma unroll
+        for (int q = 0; q < B; ++q) term(T, Ca, c[q].x, c[q].y, c[q].z, c[q].C, acc);
+    };
+    fill(c0);
+    for (uint32_t it = 1;; it += 2) {
+        if (it >= nb) {
+            eval(c0);
+            break;
+        }
+        fill(c1);
+        eval(c0);
+        if (it + 1 >= nb) {
+            eval(c1);
+            break;
+        }
+        fill(c0);
+        eval(c1);
     }
 }
 
 // One work item = `block / LANES` consecutive target particles of one tile.
+// The plume and tile tables come in as read-only, non-aliased kernel
+// arguments so that their workgroup-uniform reads go through the scalar unit.
 template <int DIM, typename real, int KERN, int MODE, int LANES>
-__device__ __forceinline__ void pair_item(const PairLaunch& a, uint32_t w, uint4* lds_rec,
-                                          uint32_t* o_lo, uint32_t* o_hi, uint32_t* o_base) {
+__device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* __restrict__ plumes,
+                                          const TileDev* __restrict__ tiles, uint32_t w,
+                                          uint2* lds_list) {
     const uint32_t tpb = (uint32_t)a.block / LANES;  // targets per workgroup
     const uint32_t subs = kTile / tpb;
-    const TileDev t = a.tiles[w / subs];
+    const TileDev t = tiles[w / subs];
     const uint32_t i0 = t.start + (w % subs) * tpb;
     if (i0 >= t.end) return;  // whole workgroup: ragged last tile
     const uint32_t i1 = min(t.end, i0 + tpb);
-    const PlumeDev P = a.plumes[t.plume];
+    const PlumeDev P = plumes[t.plume];
     const uint32_t lt = threadIdx.x / LANES, lj = threadIdx.x % LANES;
-    const uint32_t i = i0 + lt;
-    const bool active = i < i1;
+    // Lanes past the end of a ragged tile stay in the walk (the wavefront
+    // reductions there need every lane) with an empty list and target i0.
+    const bool active = i0 + lt < i1;
+    const uint32_t i = active ? i0 + lt : i0;
 
     const uint32_t* __restrict__ px = a.spos[0];
     const uint32_t* __restrict__ py = a.spos[1];
     const uint32_t* __restrict__ pz = a.spos[2];
     const real* __restrict__ Cp = static_cast<const real*>(a.Cpair);
     const uint4* __restrict__ rec = a.rec;
-    const uint32_t* __restrict__ cs = a.cell_start;
-    const int R = P.R;
-    const int span = 2 * R + 1;
-    const int noff = (DIM == 3) ? span * span : span;
     constexpr bool kRec = Rec<DIM, real>::kStageable;
-
-    // ---- stage the union of the workgroup's candidate ranges in LDS ----------
-    const bool stage = kRec && a.stage > 0;
-    if (stage) {
-        const uint32_t cap = (uint32_t)a.stage * (uint32_t)a.block;
-        __syncthreads();  // the previous item of a persistent workgroup is done with LDS
-        for (int o = threadIdx.x; o < noff; o += blockDim.x) {
-            const int oy = o % span - R, oz = (DIM == 3) ? o / span - R : 0;
-            const uint32_t fx = px[i0], lx = px[i1 - 1];
-            const int fy = (int)__umulhi(py[i0], P.nr), ly = (int)__umulhi(py[i1 - 1], P.nr);
-            const int fz = (DIM == 3) ? (int)__umulhi(pz[i0], P.nr) : 0;
-            const int lz = (DIM == 3) ? (int)__umulhi(pz[i1 - 1], P.nr) : 0;
-            const int nr = (int)P.nr;
-            uint32_t lo = 0, hi = 0;
-            const bool rows_ok = fz == lz && fy + oy >= 0 && ly + oy < nr &&
-                                 (DIM == 2 || (fz + oz >= 0 && fz + oz < nr));
-            const bool x_ok = fx >= P.hx && lx <= 0xffffffffu - P.hx;
-            if (rows_ok && x_ok) {
-                const int clo = (int)__umulhi(fx - P.hx, P.nfx) - 1;
-                const int chi = (int)__umulhi(lx + P.hx, P.nfx) + 1;
-                if (clo >= 0 && chi < (int)P.nfx) {
-                    const uint32_t zrow = (DIM == 3) ? (uint32_t)(fz + oz) * P.nr : 0u;
-                    const uint32_t klo = P.cbase + (zrow + (uint32_t)(fy + oy)) * P.nfx + (uint32_t)clo;
-                    const uint32_t khi = P.cbase + (zrow + (uint32_t)(ly + oy)) * P.nfx + (uint32_t)chi;
-                    if (klo <= khi) {
-                        lo = cs[klo];
-                        hi = cs[khi + 1];
-                    }
-                }
-            }
-            o_lo[o] = lo;
-            o_hi[o] = hi;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t run = 0;
-            for (int o = 0; o < noff; ++o) {
-                const uint32_t n = o_hi[o] - o_lo[o];
-                o_base[o] = run;
-                if (run + n > cap) o_hi[o] = o_lo[o];  // does not fit: that row reads global memory
-                else run += n;
-            }
-        }
-        __syncthreads();
-        for (int o = 0; o < noff; ++o) {
-            const uint32_t lo = o_lo[o], n = o_hi[o] - lo, base = o_base[o];
-            for (uint32_t j = threadIdx.x; j < n; j += blockDim.x) lds_rec[base + j] = rec[lo + j];
-        }
-        __syncthreads();
-    }
-    if (!active) return;  // all LANES lanes of a target share `active`
 
     const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
     const real Ca = Cp[i];
-    PairTerm<DIM, real, KERN> term;
-    term.H2 = h2_of<real>(P);
-    term.invHu = (real)P.invHu;
-    term.kxx = (real)P.kg[0];
-    term.kyy = (real)P.kg[1];
-    term.kzz = (real)P.kg[2];
-    term.kxy = (real)P.kg[3];
-    term.kxz = (real)P.kg[4];
-    term.kyz = (real)P.kg[5];
-    term.trD = (real)P.trD;
+    const PairTerm<DIM, real, KERN> term = make_term<DIM, real, KERN>(P);
     real acc = (real)0;
 
-    auto walk = [&](int o, uint32_t s, uint32_t e) {
-        if (kRec) {
-            if (stage && s >= o_lo[o] && e <= o_hi[o]) {
-                const uint32_t shift = o_base[o] - o_lo[o];
-                walk_batched<DIM, real, KERN, LANES>(
-                    term, T, Ca, s + shift, e + shift, lj,
-                    [&](uint32_t k) { return unpack<DIM, real>(lds_rec[k]); }, acc);
-            } else {
-                walk_batched<DIM, real, KERN, LANES>(
-                    term, T, Ca, s, e, lj, [&](uint32_t k) { return unpack<DIM, real>(rec[k]); }, acc);
-            }
-        } else {
-            walk_batched<DIM, real, KERN, LANES>(
-                term, T, Ca, s, e, lj,
-                [&](uint32_t k) { return Cand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, Cp[k]}; },
-                acc);
-        }
-    };
+    // every lane of a target writes the same list (no cross-lane hand-over)
+    uint2* list = lds_list + lt;
+    uint32_t total = 0;
+    if (active) total = build_list<DIM>(P, a.cell_start, T, list, tpb);
+    else list[0] = make_uint2(kListEndStart, kListEndEnd);
+    if (kRec)
+        walk_list<DIM, real, KERN, LANES>(term, T, Ca, i, list, tpb, total, lj,
+                                          [&](uint32_t k) {
+                                              // 32-bit byte offset from a uniform base (at most
+                                              // 2^28 records): one shift per address
+                                              return unpack<DIM, real>(*reinterpret_cast<const uint4*>(
+                                                  reinterpret_cast<const char*>(rec) + (k << 4)));
+                                          },
+                                          acc);
+    else
+        walk_list<DIM, real, KERN, LANES>(
+            term, T, Ca, i, list, tpb, total, lj,
+            [&](uint32_t k) { return Cand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, Cp[k]}; }, acc);
 
-    // rows in order (oz major, oy minor); the cell-start bounds of the next
-    // row are in flight while the current row is walked
-    RowRanges cur = row_ranges<DIM>(P, cs, T, 0, span);
-    for (int j = 0; j < noff; ++j) {
-        RowRanges nxt{0u, 0u, 0u, 0u};
-        if (j + 1 < noff) nxt = row_ranges<DIM>(P, cs, T, j + 1, span);
-        walk(j, cur.s0, cur.e0);
-        if (cur.e1 > cur.s1) walk(j, cur.s1, cur.e1);
-        cur = nxt;
-    }
     // wavefront reduction over the lanes of a target (fixed order: deterministic)
     if (LANES >= 2) acc += __shfl_xor(acc, 1, kWave);
     if (LANES >= 4) acc += __shfl_xor(acc, 2, kWave);
-    if (lj != 0) return;
+    if (!active || lj != 0) return;
 
     if (MODE == kModeRhs) {
         static_cast<real*>(a.out)[a.sid[i]] = (real)P.vphi * acc;
@@ -274,22 +330,30 @@ __device__ __forceinline__ void pair_item(const PairLaunch& a, uint32_t w, uint4
     a.utick[i] = atomicAdd(&a.count[key], 1u);
 }
 
+// Eight wavefronts per SIMD for the FP32 kernels: at most 64 VGPRs and 100
+// SGPRs (kernel arguments are re-read from the argument segment rather than
+// held across the candidate loop).
 template <int DIM, typename real, int KERN, int MODE, int LANES>
-__global__ __launch_bounds__(256) void k_pair(PairLaunch a, uint32_t nwork) {
-    extern __shared__ uint4 lds_rec[];
-    __shared__ uint32_t o_lo[kMaxRowOffsets], o_hi[kMaxRowOffsets], o_base[kMaxRowOffsets];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 && DIM == 2 ? 8 : 1)))
+void k_pair(PairLaunch a, const PlumeDev* __restrict__ plumes,
+                                              const TileDev* __restrict__ tiles, uint32_t nwork) {
+    extern __shared__ uint2 lds_list[];
     if (a.persistent == 0) {
-        pair_item<DIM, real, KERN, MODE, LANES>(a, xcd_remap(blockIdx.x, gridDim.x), lds_rec, o_lo,
-                                                o_hi, o_base);
+        pair_item<DIM, real, KERN, MODE, LANES>(a, plumes, tiles, xcd_remap(blockIdx.x, gridDim.x, a.xcd_group),
+                                                lds_list);
         return;
     }
-    // persistent grid: each workgroup takes every per_x-th item of a
-    // contiguous per-XCD share of the items (no queue, fixed assignment)
+    // persistent grid: the k-th of the workgroups on XCD x takes every
+    // per_x-th of the items xcd_remap deals to that XCD (fixed assignment, no
+    // queue); a target's list is written and read by the lanes of one
+    // wavefront only, so consecutive items need no barrier
     const uint32_t nx = 8, x = blockIdx.x % nx, k = blockIdx.x / nx;
     const uint32_t per_x = (gridDim.x + nx - 1 - x) / nx;  // workgroups on this XCD
-    const uint32_t lo = (uint32_t)(((uint64_t)nwork * x) / nx), hi = (uint32_t)(((uint64_t)nwork * (x + 1)) / nx);
-    for (uint32_t w = lo + k; w < hi; w += per_x)
-        pair_item<DIM, real, KERN, MODE, LANES>(a, w, lds_rec, o_lo, o_hi, o_base);
+    for (uint32_t m = k;; m += per_x) {
+        const uint32_t w = xcd_item(x, m, nwork, a.xcd_group);
+        if (w >= nwork) break;
+        pair_item<DIM, real, KERN, MODE, LANES>(a, plumes, tiles, w, lds_list);
+    }
 }
 
 // Neighbour-set export through the same candidate ranges and predicate:
@@ -343,15 +407,14 @@ static void launch_pair_l(int mode, const PairLaunch& a, hipStream_t s) {
     if (nwork < 8) c.persistent = 0;  // a persistent grid needs a workgroup on every XCD
     const uint32_t grid = (c.persistent > 0) ? max(8u, min(nwork, (uint32_t)c.persistent)) : nwork;
     dim3 g(grid), b(a.block);
-    const size_t shm = (Rec<DIM, real>::kStageable && a.stage > 0)
-                           ? sizeof(uint4) * (size_t)a.stage * (size_t)a.block : 0;
+    const size_t shm = pair_lds_bytes(a.block, LANES, a.list_cap);
     auto kern = (mode == kModeStep)   ? k_pair<DIM, real, KERN, kModeStep, LANES>
                 : (mode == kModeHalf) ? k_pair<DIM, real, KERN, kModeHalf, LANES>
                                       : k_pair<DIM, real, KERN, kModeRhs, LANES>;
     if (c.ev0)  // timed launch: the events carry the kernel's own start and end stamps
-        hipExtLaunchKernelGGL(kern, g, b, (uint32_t)shm, s, c.ev0, c.ev1, 0u, c, nwork);
+        hipExtLaunchKernelGGL(kern, g, b, (uint32_t)shm, s, c.ev0, c.ev1, 0u, c, c.plumes, c.tiles, nwork);
     else
-        hipLaunchKernelGGL(kern, g, b, shm, s, c, nwork);
+        hipLaunchKernelGGL(kern, g, b, shm, s, c, c.plumes, c.tiles, nwork);
 }
 
 template <int DIM, typename real, int KERN>
@@ -366,6 +429,7 @@ hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const Pair
     (void)block;
     if (a.block <= 0 || a.block > kTile || kTile % a.block != 0) return hipErrorInvalidValue;
     if (a.lanes != 1 && a.lanes != 2 && a.lanes != 4) return hipErrorInvalidValue;
+    if (a.list_cap < 3 || pair_lds_bytes(a.block, a.lanes, a.list_cap) > kPairLdsMax) return hipErrorInvalidValue;
     if (dim == 2) {
         if (real_bytes == 4) {
             if (kernel == 4) launch_pair_t<2, float, 4>(mode, a, s);
