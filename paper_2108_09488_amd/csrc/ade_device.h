@@ -42,6 +42,18 @@ __device__ __forceinline__ uint32_t cell_key(const PlumeDev& P, uint32_t ux, uin
     return P.cbase + (rz * P.nr + ry) * P.nfx + fx;
 }
 
+// Counting pass: count particle i (an index into the hashed buffer U) in its
+// cell and record it in the cell's bucket, or past kBucket in the overflow list.
+__device__ __forceinline__ void enlist(const CellLists& L, uint32_t key, uint32_t i) {
+    const uint32_t t = atomicAdd(&L.count[key], 1u);
+    if (t < kBucket) {
+        L.bucket[(size_t)key * kBucket + t] = i;
+    } else {
+        const uint32_t p = atomicAdd(&L.ovf_count[0], 1u);
+        L.ovf[p] = make_uint2(key, i);
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
     const int lane = threadIdx.x & (kWave - 1);

@@ -12,7 +12,7 @@ constexpr int kTile = 256;          // particles per tile (a tile never spans tw
 constexpr int kScanPerThread = 16;  // counting-sort scan: elements per thread
 constexpr int kScanBlock = 256;
 constexpr int kScanChunk = kScanPerThread * kScanBlock;
-constexpr int kCellChunk = 1024;    // cell-count scan: 256 threads x 4 counts per workgroup
+constexpr int kCellChunk = 4096;    // cell-count scan: 256 threads x 16 counts per workgroup
 
 // cell tables are padded to a whole number of scan chunks (plus the sentinel)
 inline uint64_t cell_pad(uint64_t ncell) { return (ncell + 1 + kCellChunk - 1) / kCellChunk * kCellChunk; }
@@ -57,8 +57,18 @@ struct StateArrays {
     uint4* rec;      // 16-byte candidate records (sorted buffer S only; null if unused)
     void* C;
     uint32_t* id;
-    uint32_t* key;   // cell key (U and T buffers)
-    uint32_t* tick;  // slot inside the cell from the counting pass (U buffer)
+    uint32_t* key;   // cell key (hashed buffer U only)
+};
+
+// Counting pass of the cell build: the number of particles per cell and who
+// they are -- the first kBucket of a cell in its bucket, any further ones in
+// an overflow list of (key, index) pairs.
+constexpr uint32_t kBucket = 8;
+struct CellLists {
+    uint32_t* count;      // per cell (cleared by the scan)
+    uint32_t* bucket;     // kBucket entries per cell: indices into U
+    uint2* ovf;           // overflow pairs (key, index), up to N
+    uint32_t* ovf_count;  // [0] pairs added since the last scan, [1] pairs of the current build
 };
 
 enum PairMode { kModeStep = 0, kModeHalf = 1, kModeRhs = 2 };
@@ -83,8 +93,7 @@ struct PairLaunch {
     void* uC;
     uint32_t* uid;
     uint32_t* ukey;
-    uint32_t* utick;
-    uint32_t* count;
+    CellLists lists;
     const int64_t* step;
     double scale;           // fraction of the plume's dt: step 1, half 0.5 (unused for rhs)
     void* out;              // half: S-order output; rhs: id-order output
@@ -105,12 +114,10 @@ constexpr size_t kPairLdsMax = 65536;
 // kernel launchers (kernels_*.hip); all return hipError_t of the launch
 hipError_t launch_init(int dim, int real_bytes, const PlumeDev* plumes, const TileDev* tiles,
                        uint32_t ntiles, const double* x, const void* C, uint32_t N,
-                       StateArrays U, uint32_t* count, hipStream_t s);
-hipError_t launch_scan(const uint32_t* count_in, uint32_t* cell_start, uint32_t* partial,
-                       uint32_t ncell, hipStream_t s);
-hipError_t launch_scatter(int dim, int real_bytes, StateArrays U, StateArrays T,
-                          const uint32_t* cell_start, uint32_t N, hipStream_t s);
-hipError_t launch_canon(int dim, int real_bytes, StateArrays T, StateArrays S,
+                       StateArrays U, CellLists lists, hipStream_t s);
+hipError_t launch_scan(CellLists lists, uint32_t* cell_start, uint32_t* partial, uint32_t ncell,
+                       hipStream_t s);
+hipError_t launch_place(int dim, int real_bytes, StateArrays U, StateArrays S, CellLists lists,
                         const uint32_t* cell_start, uint32_t N, int64_t* step, int inc_step,
                         hipStream_t s);
 hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const PairLaunch& a,

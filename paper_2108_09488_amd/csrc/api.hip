@@ -228,22 +228,24 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
     const size_t rb = (size_t)pl.real_bytes;
     c->plumes = b.take<PlumeDev>(pl.P);
     c->tiles = b.take<TileDev>(pl.ntiles);
-    StateArrays* bufs[3] = {&c->S, &c->U, &c->T};
-    for (int k = 0; k < 3; ++k) {
+    StateArrays* bufs[2] = {&c->S, &c->U};
+    for (int k = 0; k < 2; ++k) {
         StateArrays& s = *bufs[k];
         for (int d = 0; d < 3; ++d) s.pos[d] = (d < pl.dim) ? b.take<uint32_t>(N) : nullptr;
         s.rec = (k == 0 && !(pl.dim == 3 && pl.real_bytes == 8)) ? b.take<uint4>(N) : nullptr;
         s.C = b.take_bytes(N * rb);
         s.id = b.take<uint32_t>(N);
-        s.key = (k > 0) ? b.take<uint32_t>(N) : nullptr;
-        s.tick = (k == 1) ? b.take<uint32_t>(N) : nullptr;
+        s.key = (k == 1) ? b.take<uint32_t>(N) : nullptr;
     }
     if (pl.dim == 2) {  // never read in 2D, but keep the pointers valid
         c->S.pos[2] = c->S.pos[0];
         c->U.pos[2] = c->U.pos[0];
-        c->T.pos[2] = c->T.pos[0];
     }
     c->count = b.take<uint32_t>(cell_pad(pl.ncell));
+    c->lists.count = c->count;
+    c->lists.bucket = b.take<uint32_t>(cell_pad(pl.ncell) * kBucket);
+    c->lists.ovf = b.take<uint2>(N);
+    c->lists.ovf_count = b.take<uint32_t>(2);
     c->cell_start = b.take<uint32_t>(cell_pad(pl.ncell));
     c->scan_partial = b.take_bytes((size_t)pl.nscan * 8);
     c->aux = b.take_bytes(N * rb);
@@ -319,8 +321,7 @@ PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase,
     a.uC = c->U.C;
     a.uid = c->U.id;
     a.ukey = c->U.key;
-    a.utick = c->U.tick;
-    a.count = c->count;
+    a.lists = c->lists;
     a.step = c->step;
     a.scale = scale;
     a.out = out;
@@ -331,9 +332,8 @@ PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase,
 // counting sort of the hashed U buffer into S (cell order) and cell_start
 int enqueue_build(ade_ctx* c, int inc_step) {
     const Plan& pl = c->plan;
-    HIPCHK(launch_scan(c->count, c->cell_start, (uint32_t*)c->scan_partial, (uint32_t)pl.ncell, c->stream));
-    HIPCHK(launch_scatter(pl.dim, pl.real_bytes, c->U, c->T, c->cell_start, (uint32_t)pl.N, c->stream));
-    HIPCHK(launch_canon(pl.dim, pl.real_bytes, c->T, c->S, c->cell_start, (uint32_t)pl.N, c->step,
+    HIPCHK(launch_scan(c->lists, c->cell_start, (uint32_t*)c->scan_partial, (uint32_t)pl.ncell, c->stream));
+    HIPCHK(launch_place(pl.dim, pl.real_bytes, c->U, c->S, c->lists, c->cell_start, (uint32_t)pl.N, c->step,
                         inc_step, c->stream));
     return ADE_OK;
 }
@@ -432,6 +432,7 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
         hipMemcpyAsync(c->cell_start + pl.ncell, &c->h_total, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemsetAsync(c->count, 0, sizeof(uint32_t) * cell_pad(pl.ncell), c->stream) != hipSuccess ||
         hipMemsetAsync(c->step, 0, sizeof(int64_t), c->stream) != hipSuccess ||
+        hipMemsetAsync(c->lists.ovf_count, 0, 2 * sizeof(uint32_t), c->stream) != hipSuccess ||
         hipStreamSynchronize(c->stream) != hipSuccess)
         return cleanup(fail(ADE_EHIP, "uploading the plume tables failed"));
     *out = c;
@@ -442,9 +443,10 @@ int ade_init_particles(ade_ctx* c, const double* d_x, const void* d_C) {
     if (!c || !d_x || !d_C) return fail(ADE_EINVAL, "null argument");
     const Plan& pl = c->plan;
     HIPCHK(hipMemsetAsync(c->count, 0, sizeof(uint32_t) * cell_pad(pl.ncell), c->stream));
+    HIPCHK(hipMemsetAsync(c->lists.ovf_count, 0, 2 * sizeof(uint32_t), c->stream));
     HIPCHK(hipMemsetAsync(c->step, 0, sizeof(int64_t), c->stream));
     HIPCHK(launch_init(pl.dim, pl.real_bytes, c->plumes, c->tiles, pl.ntiles, d_x, d_C, (uint32_t)pl.N,
-                       c->U, c->count, c->stream));
+                       c->U, c->lists, c->stream));
     c->initialized = true;
     c->built = false;
     return ADE_OK;

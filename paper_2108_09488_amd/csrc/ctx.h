@@ -47,7 +47,8 @@ struct ade_ctx {
     ade_tuning tuning{256, 2, 0, 0};
     ade::PlumeDev* plumes = nullptr;
     ade::TileDev* tiles = nullptr;
-    ade::StateArrays S{}, U{}, T{};
+    ade::StateArrays S{}, U{};
+    ade::CellLists lists{};
     uint32_t* count = nullptr;
     uint32_t* cell_start = nullptr;
     void* scan_partial = nullptr;

@@ -1,22 +1,22 @@
 // kernels_build.hip -- cell-linked list on gfx950: fixed-point hashing of the
-// particles into cells, a one-pass counting sort by cell key (histogram by
-// atomic tickets, exclusive scan = cell-start table, scatter), and a
-// canonicalisation that orders the particles of each cell by id so that the
-// sorted order is a pure function of the positions (deterministic pair sums).
+// particles into cells, a counting sort by cell key (histogram and per-cell
+// buckets by atomics, exclusive scan = cell-start table) whose placement
+// orders the particles of each cell by id, so that the sorted order is a pure
+// function of the positions (deterministic pair sums).
 // Also: read-back of C and x in id order and the FP64 mass reduction.
 #include "ade_device.h"
 
 namespace ade {
 
 // ---------------------------------------------------------------------------
-// init: positions (double, SoA) -> fixed point, first hash + ticket
+// init: positions (double, SoA) -> fixed point, first hash and counting pass
 // ---------------------------------------------------------------------------
 template <int DIM, typename real>
 __global__ __launch_bounds__(kTile) void k_init(const PlumeDev* __restrict__ plumes,
                                                const TileDev* __restrict__ tiles,
                                                const double* __restrict__ x,
                                                const real* __restrict__ C, uint32_t N,
-                                               StateArrays U, uint32_t* __restrict__ count) {
+                                               StateArrays U, CellLists lists) {
     const TileDev t = tiles[blockIdx.x];
     const PlumeDev& P = plumes[t.plume];
     const uint32_t i = t.start + threadIdx.x;
@@ -32,72 +32,74 @@ __global__ __launch_bounds__(kTile) void k_init(const PlumeDev* __restrict__ plu
     U.id[i] = i;
     const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
     U.key[i] = key;
-    U.tick[i] = atomicAdd(&count[key], 1u);
+    enlist(lists, key, i);
 }
 
 // ---------------------------------------------------------------------------
 // exclusive scan of the per-cell counts -> cell_start; counts are cleared.
-// The tables are padded to whole 1024-cell chunks with zero counts, so the
+// The tables are padded to whole 4096-cell chunks with zero counts, so the
 // entry after the last cell receives the particle total (the sentinel).
-// Three launches: chunk totals, a one-workgroup scan of the totals, and the
-// chunk scans with their offsets.
+// Two launches: the chunk totals, then every workgroup sums the totals of
+// the chunks before its own (a few hundred numbers, read by all of its
+// threads at once) and scans its chunk.
 // ---------------------------------------------------------------------------
+constexpr int kCellVec = kCellChunk / (256 * 4);  // uint4 of counts per thread, contiguous
+
 __global__ __launch_bounds__(256) void k_cscan_reduce(const uint4* __restrict__ count,
-                                                     uint32_t* __restrict__ partial) {
+                                                     uint32_t* __restrict__ partial,
+                                                     uint32_t* __restrict__ ovf_count) {
     __shared__ uint32_t lds[256 / kWave];
-    const uint4 c = count[blockIdx.x * 256 + threadIdx.x];
-    const uint32_t s = block_sum(c.x + c.y + c.z + c.w, lds);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {  // the overflow pairs of this build; restart the count
+        ovf_count[1] = ovf_count[0];
+        ovf_count[0] = 0;
+    }
+    const uint32_t j0 = (blockIdx.x * 256 + threadIdx.x) * kCellVec;
+    uint32_t mine = 0;
+#pragma unroll
+    for (int k = 0; k < kCellVec; ++k) {
+        const uint4 c = count[j0 + k];
+        mine += c.x + c.y + c.z + c.w;
+    }
+    const uint32_t s = block_sum(mine, lds);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
-__global__ __launch_bounds__(1024) void k_cscan_mid(uint32_t* __restrict__ partial, uint32_t nb) {
-    __shared__ uint32_t lds[1024 / kWave];
-    uint32_t carry = 0;
-    for (uint32_t base = 0; base < nb; base += 4096) {
-        uint32_t v[4];
-        uint32_t s = 0;
+__global__ __launch_bounds__(256) void k_cscan_final(uint4* __restrict__ count,
+                                                    const uint32_t* __restrict__ partial,
+                                                    uint4* __restrict__ cell_start) {
+    __shared__ uint32_t lds[256 / kWave];
+    uint32_t pre = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) pre += partial[b];
+    pre = block_sum(pre, lds);
+    const uint32_t j0 = (blockIdx.x * 256 + threadIdx.x) * kCellVec;
+    uint4 c[kCellVec];
+    uint32_t mine = 0;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t j = base + threadIdx.x * 4 + k;
-            v[k] = (j < nb) ? partial[j] : 0u;
-            s += v[k];
-        }
-        uint32_t tot;
-        uint32_t ex = block_exclusive_scan(s, lds, tot) + carry;
+    for (int k = 0; k < kCellVec; ++k) {
+        c[k] = count[j0 + k];
+        mine += c[k].x + c[k].y + c[k].z + c[k].w;
+    }
+    uint32_t tot;
+    uint32_t run = block_exclusive_scan(mine, lds, tot) + pre;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t j = base + threadIdx.x * 4 + k;
-            if (j < nb) partial[j] = ex;
-            ex += v[k];
-        }
-        carry += tot;
+    for (int k = 0; k < kCellVec; ++k) {
+        uint4 o;
+        o.x = run;
+        o.y = o.x + c[k].x;
+        o.z = o.y + c[k].y;
+        o.w = o.z + c[k].z;
+        run = o.w + c[k].w;
+        cell_start[j0 + k] = o;
+        count[j0 + k] = make_uint4(0u, 0u, 0u, 0u);
     }
 }
 
-__global__ __launch_bounds__(256) void k_cscan_final(uint4* __restrict__ count,
-                                                    const uint32_t* __restrict__ prefix,
-                                                    uint4* __restrict__ cell_start) {
-    __shared__ uint32_t lds[256 / kWave];
-    const uint32_t j = blockIdx.x * 256 + threadIdx.x;
-    const uint4 c = count[j];
-    uint32_t tot;
-    const uint32_t ex = block_exclusive_scan(c.x + c.y + c.z + c.w, lds, tot) + prefix[blockIdx.x];
-    uint4 o;
-    o.x = ex;
-    o.y = ex + c.x;
-    o.z = o.y + c.y;
-    o.w = o.z + c.z;
-    cell_start[j] = o;
-    count[j] = make_uint4(0u, 0u, 0u, 0u);
-}
-
-hipError_t launch_scan(const uint32_t* count_in, uint32_t* cell_start, uint32_t* partial,
-                       uint32_t ncell, hipStream_t s) {
-    const uint32_t nb = (uint32_t)(cell_pad(ncell) / kCellChunk);
-    uint4* cnt = reinterpret_cast<uint4*>(const_cast<uint32_t*>(count_in));
-    hipLaunchKernelGGL(k_cscan_reduce, dim3(nb), dim3(256), 0, s, cnt, partial);
-    hipLaunchKernelGGL(k_cscan_mid, dim3(1), dim3(1024), 0, s, partial, nb);
-    hipLaunchKernelGGL(k_cscan_final, dim3(nb), dim3(256), 0, s, cnt, partial,
+hipError_t launch_scan(CellLists lists, uint32_t* cell_start, uint32_t* partial, uint32_t ncell,
+                       hipStream_t s) {
+    const uint32_t nchunks = (uint32_t)(cell_pad(ncell) / kCellChunk);
+    uint4* cnt = reinterpret_cast<uint4*>(lists.count);
+    hipLaunchKernelGGL(k_cscan_reduce, dim3(nchunks), dim3(256), 0, s, cnt, partial, lists.ovf_count);
+    hipLaunchKernelGGL(k_cscan_final, dim3(nchunks), dim3(256), 0, s, cnt, partial,
                        reinterpret_cast<uint4*>(cell_start));
     return hipGetLastError();
 }
@@ -151,43 +153,43 @@ hipError_t launch_scan64(int64_t* data, uint32_t n, int64_t* partial, hipStream_
 }
 
 // ---------------------------------------------------------------------------
-// scatter by (cell start + ticket), then order each cell by particle id
+// placement: every particle of U goes to cell_start[key] + (its rank by id
+// among the particles of its cell), found from the cell's bucket (and, for a
+// cell of more than kBucket particles, the overflow list), so the sorted
+// order is a pure function of the positions.  Writes the sorted state S and
+// its candidate records; advances the step counter if asked.
 // ---------------------------------------------------------------------------
 template <int DIM, typename real>
-__global__ __launch_bounds__(256) void k_scatter(StateArrays U, StateArrays T,
-                                                const uint32_t* __restrict__ cell_start,
-                                                uint32_t N) {
+__global__ __launch_bounds__(256) void k_place(StateArrays U, StateArrays S, CellLists L,
+                                              const uint32_t* __restrict__ cell_start, uint32_t N,
+                                              int64_t* step, int inc_step) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (inc_step && i == 0) *step += 1;
     if (i >= N) return;
     const uint32_t key = U.key[i];
-    const uint32_t slot = cell_start[key] + U.tick[i];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) T.pos[c][slot] = U.pos[c][i];
-    static_cast<real*>(T.C)[slot] = static_cast<const real*>(U.C)[i];
-    T.id[slot] = U.id[i];
-    T.key[slot] = key;
-}
-
-template <int DIM, typename real>
-__global__ __launch_bounds__(256) void k_canon(StateArrays T, StateArrays S,
-                                              const uint32_t* __restrict__ cell_start,
-                                              uint32_t N, int64_t* step, int inc_step) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (inc_step && j == 0) *step += 1;
-    if (j >= N) return;
-    const uint32_t key = T.key[j];
-    const uint32_t s = cell_start[key], e = cell_start[key + 1];
-    const uint32_t my = T.id[j];
+    const uint32_t my = U.id[i];
+    const uint32_t s = cell_start[key];
+    const uint32_t n = cell_start[key + 1] - s;
+    const uint32_t* __restrict__ bk = L.bucket + (size_t)key * kBucket;
     uint32_t rank = 0;
-    for (uint32_t k = s; k < e; ++k) rank += (T.id[k] < my) ? 1u : 0u;
+#pragma unroll
+    for (uint32_t t = 0; t < kBucket; ++t)
+        if (t < n) rank += (U.id[bk[t]] < my) ? 1u : 0u;
+    if (n > kBucket) {  // crowded cell: the rest of it is in the overflow list
+        const uint32_t no = L.ovf_count[1];
+        for (uint32_t p = 0; p < no; ++p) {
+            const uint2 e = L.ovf[p];
+            if (e.x == key) rank += (U.id[e.y] < my) ? 1u : 0u;
+        }
+    }
     const uint32_t d = s + rank;
     uint32_t u[3] = {0u, 0u, 0u};
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        u[c] = T.pos[c][j];
+        u[c] = U.pos[c][i];
         S.pos[c][d] = u[c];
     }
-    const real C = static_cast<const real*>(T.C)[j];
+    const real C = static_cast<const real*>(U.C)[i];
     static_cast<real*>(S.C)[d] = C;
     S.id[d] = my;
     if (Rec<DIM, real>::kStageable) S.rec[d] = Rec<DIM, real>::pack(u[0], u[1], u[2], C);
@@ -243,37 +245,31 @@ __global__ __launch_bounds__(256) void k_mass_plumes(const PlumeDev* __restrict_
 // ---------------------------------------------------------------------------
 hipError_t launch_init(int dim, int real_bytes, const PlumeDev* plumes, const TileDev* tiles,
                        uint32_t ntiles, const double* x, const void* C, uint32_t N,
-                       StateArrays U, uint32_t* count, hipStream_t s) {
+                       StateArrays U, CellLists lists, hipStream_t s) {
     dim3 g(ntiles), b(kTile);
     if (dim == 2 && real_bytes == 4)
-        hipLaunchKernelGGL((k_init<2, float>), g, b, 0, s, plumes, tiles, x, (const float*)C, N, U, count);
+        hipLaunchKernelGGL((k_init<2, float>), g, b, 0, s, plumes, tiles, x, (const float*)C, N, U, lists);
     else if (dim == 2)
-        hipLaunchKernelGGL((k_init<2, double>), g, b, 0, s, plumes, tiles, x, (const double*)C, N, U, count);
+        hipLaunchKernelGGL((k_init<2, double>), g, b, 0, s, plumes, tiles, x, (const double*)C, N, U, lists);
     else if (real_bytes == 4)
-        hipLaunchKernelGGL((k_init<3, float>), g, b, 0, s, plumes, tiles, x, (const float*)C, N, U, count);
+        hipLaunchKernelGGL((k_init<3, float>), g, b, 0, s, plumes, tiles, x, (const float*)C, N, U, lists);
     else
-        hipLaunchKernelGGL((k_init<3, double>), g, b, 0, s, plumes, tiles, x, (const double*)C, N, U, count);
+        hipLaunchKernelGGL((k_init<3, double>), g, b, 0, s, plumes, tiles, x, (const double*)C, N, U, lists);
     return hipGetLastError();
 }
 
-hipError_t launch_scatter(int dim, int real_bytes, StateArrays U, StateArrays T,
-                          const uint32_t* cell_start, uint32_t N, hipStream_t s) {
-    dim3 g((N + 255) / 256), b(256);
-    if (dim == 2 && real_bytes == 4) hipLaunchKernelGGL((k_scatter<2, float>), g, b, 0, s, U, T, cell_start, N);
-    else if (dim == 2) hipLaunchKernelGGL((k_scatter<2, double>), g, b, 0, s, U, T, cell_start, N);
-    else if (real_bytes == 4) hipLaunchKernelGGL((k_scatter<3, float>), g, b, 0, s, U, T, cell_start, N);
-    else hipLaunchKernelGGL((k_scatter<3, double>), g, b, 0, s, U, T, cell_start, N);
-    return hipGetLastError();
-}
-
-hipError_t launch_canon(int dim, int real_bytes, StateArrays T, StateArrays S,
+hipError_t launch_place(int dim, int real_bytes, StateArrays U, StateArrays S, CellLists lists,
                         const uint32_t* cell_start, uint32_t N, int64_t* step, int inc_step,
                         hipStream_t s) {
     dim3 g((N + 255) / 256), b(256);
-    if (dim == 2 && real_bytes == 4) hipLaunchKernelGGL((k_canon<2, float>), g, b, 0, s, T, S, cell_start, N, step, inc_step);
-    else if (dim == 2) hipLaunchKernelGGL((k_canon<2, double>), g, b, 0, s, T, S, cell_start, N, step, inc_step);
-    else if (real_bytes == 4) hipLaunchKernelGGL((k_canon<3, float>), g, b, 0, s, T, S, cell_start, N, step, inc_step);
-    else hipLaunchKernelGGL((k_canon<3, double>), g, b, 0, s, T, S, cell_start, N, step, inc_step);
+    if (dim == 2 && real_bytes == 4)
+        hipLaunchKernelGGL((k_place<2, float>), g, b, 0, s, U, S, lists, cell_start, N, step, inc_step);
+    else if (dim == 2)
+        hipLaunchKernelGGL((k_place<2, double>), g, b, 0, s, U, S, lists, cell_start, N, step, inc_step);
+    else if (real_bytes == 4)
+        hipLaunchKernelGGL((k_place<3, float>), g, b, 0, s, U, S, lists, cell_start, N, step, inc_step);
+    else
+        hipLaunchKernelGGL((k_place<3, double>), g, b, 0, s, U, S, lists, cell_start, N, step, inc_step);
     return hipGetLastError();
 }
 

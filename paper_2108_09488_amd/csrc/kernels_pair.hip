@@ -327,7 +327,7 @@ __device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* _
     a.uid[i] = a.sid[i];
     const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
     a.ukey[i] = key;
-    a.utick[i] = atomicAdd(&a.count[key], 1u);
+    enlist(a.lists, key, i);
 }
 
 // Eight wavefronts per SIMD for the FP32 kernels: at most 64 VGPRs and 100
