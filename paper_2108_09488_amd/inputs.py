@@ -83,6 +83,23 @@ def lattice(n_side: int, dim: int, L: float = 1.0, jitter: float = 0.0,
     return x
 
 
+def clustered(n_side: int, dim: int, copies: int, spread: float, L: float = 1.0,
+              seed: int = BASE_SEED, stream: int = 0) -> np.ndarray:
+    """Crowded particles: every site of the cell-centred n_side**dim lattice
+    holds `copies` particles, each moved by U[-spread*dp, +spread*dp) per
+    component (site-major order), wrapped and rounded to the L/2**32 grid."""
+    sites = lattice(n_side, dim, L, 0.0, seed, stream)
+    dp = L / n_side
+    n = sites.shape[1] * copies
+    key = stream_key(seed, stream + 1)
+    x = np.empty((dim, n), dtype=np.float64)
+    for c in range(dim):
+        cnt = np.arange(n, dtype=np.uint64) * np.uint64(dim) + np.uint64(c)
+        off = (2.0 * uniform01(key, cnt) - 1.0) * (spread * dp)
+        x[c] = quantize(np.mod(np.repeat(sites[c], copies) + off, L), L)
+    return x
+
+
 def gaussian_plume(x: np.ndarray, centre, sigma0: float, L: float = 1.0,
                    C0: float = 1.0) -> np.ndarray:
     """Initial plume C = C0 sum_images exp(-|x - x0 - image|^2 / (2 sigma0^2))
