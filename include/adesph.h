@@ -112,7 +112,7 @@ int ade_workspace_bytes(const ade_params *params, const int64_t *counts, int32_t
 /* Validates the parameters and lays out the caller's workspace d_ws
  * (ws_bytes >= ade_workspace_bytes, 256-byte aligned); stream is a
  * hipStream_t (NULL: the default stream).  *out receives the context.  A
- * context holds at most 2^28 - 1 particles in total (candidate records are
+ * context holds at most 2^28 - 256 particles in total (candidate records are
  * addressed with 32-bit byte offsets); larger ensembles take several
  * contexts. */
 int ade_create(const ade_params *params, const int64_t *counts, int32_t nplumes, void *d_ws,

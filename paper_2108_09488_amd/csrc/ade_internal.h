@@ -36,8 +36,12 @@ struct PlumeDev {
     float rowh2f;           // square of the row height in grid units, (2^32 / nr)^2
     double a0, a1;          // Gamma x^T D x / r^2 - tr D = a0 + a1 (e . x / r)^2 (Eq. 3 tensor)
     double ehat[3];         // unit flow direction e (x axis when |v| = 0)
-    double invHu5;          // 5 / Hu
-    float fterm[8];         // FP32 pair-term constants: H2f, invHu, invHu5, a0, a1, e_x, e_y, e_z
+    double pad3;
+    // pair-term constants as the pair kernel uses them: Hu^2, 1/Hu, 5/Hu,
+    // A0, A1, E_x, E_y, E_z with A = A0 + A1 (E . x / r)^2; in 2D A1 is folded
+    // into E (A1 = 1, E = sqrt|a1| e, or its normal when a1 < 0)
+    double dterm[8];
+    float fterm[8];         // the same in FP32
     double trD;             // trace of D
     double vphi;            // V * (kernel derivative prefactor): rhs = vphi * sum
     double dt;

@@ -132,7 +132,7 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         d.poff = (uint32_t)N;
         d.n = (uint32_t)counts[p];
         N += (uint64_t)counts[p];
-        if (N > 0x0fffffffull) return fail(ADE_EINVAL, "at most 2^28 - 1 particles per context");
+        if (N > 0x0fffff00ull) return fail(ADE_EINVAL, "at most 2^28 - 256 particles per context");
 
         // cell grid in grid units: rows of height >= Hc / rows_per_H, x cells of width >= Hc / xsub
         const double Hu = q.H / q.L * kTwo32;
@@ -175,9 +175,30 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         d.a0 = (gamma - pl.dim) * (q.alpha_T * sp + q.D_m) - (q.alpha_L - q.alpha_T) * sp;
         d.a1 = gamma * (q.alpha_L - q.alpha_T) * sp;
         for (int c = 0; c < 3; ++c) d.ehat[c] = (sp > 0) ? ((c < pl.dim) ? q.v[c] / sp : 0.0) : (c == 0 ? 1.0 : 0.0);
-        d.invHu5 = 5.0 / Hu;
-        const double ft[8] = {Hu * Hu, 1.0 / Hu, 5.0 / Hu, d.a0, d.a1, d.ehat[0], d.ehat[1], d.ehat[2]};
-        for (int k = 0; k < 8; ++k) d.fterm[k] = (float)ft[k];
+        {
+            // 2D: a0 + a1 (e.n)^2 = A0 + (E.n)^2 with E = sqrt(a1) e, or, for
+            // a1 < 0 (with (e.n)^2 + (e_perp.n)^2 = 1), A0 = a0 + a1 and
+            // E = sqrt(-a1) e_perp
+            double A0 = d.a0, A1 = d.a1, E[3] = {d.ehat[0], d.ehat[1], d.ehat[2]};
+            if (pl.dim == 2) {
+                const double sa = std::sqrt(std::fabs(d.a1));
+                if (d.a1 >= 0) {
+                    E[0] = sa * d.ehat[0];
+                    E[1] = sa * d.ehat[1];
+                } else {
+                    A0 = d.a0 + d.a1;
+                    E[0] = -sa * d.ehat[1];
+                    E[1] = sa * d.ehat[0];
+                }
+                E[2] = 0.0;
+                A1 = 1.0;
+            }
+            const double t[8] = {Hu * Hu, 1.0 / Hu, 5.0 / Hu, A0, A1, E[0], E[1], E[2]};
+            for (int k = 0; k < 8; ++k) {
+                d.dterm[k] = t[k];
+                d.fterm[k] = (float)t[k];
+            }
+        }
         d.trD = trD;
         const double V = q.mass / q.rho0;
         d.vphi = V * kernel_phi_prefactor(pl.kernel, pl.dim, q.H);

@@ -10,7 +10,8 @@
 //     C2: W'(r)/r = -20 (B / H^2) (1 - q)^3,        q = r / H.
 // With D from Eq. (3) the bracket is a0 + a1 (e . x_ab / r)^2, e = v / |v|,
 // a0 = (Gamma - d)(alpha_T |v| + D_m) - (alpha_L - alpha_T)|v| and
-// a1 = Gamma (alpha_L - alpha_T)|v|.  Separations are taken in grid units
+// a1 = Gamma (alpha_L - alpha_T)|v| (in 2D a1 is folded into e, see
+// PlumeDev::dterm).  Separations are taken in grid units
 // (L / 2^32) from the fixed-point positions; the bracket is scale free and
 // the constant factor V (W'(r)/r)/f(q) is applied once per particle
 // (PlumeDev::vphi).
@@ -70,7 +71,7 @@ struct PairTerm {
         p = fmar(ey, dy, p);
         if (DIM == 3) p = fmar(ez, dz, p);
         const real pr = p * rinv;
-        const real A = fmar(a1 * pr, pr, a0);
+        const real A = (DIM == 2) ? fmar(pr, pr, a0) : fmar(a1 * pr, pr, a0);  // 2D: a1 folded into e
         const real w = inside ? A * f : (real)0;
         acc = fmar(w, Ca - Cb, acc);
     }
@@ -81,25 +82,17 @@ struct PairTerm {
 template <int DIM, typename real, int KERN>
 __device__ __forceinline__ PairTerm<DIM, real, KERN> make_term(const PlumeDev& P) {
     PairTerm<DIM, real, KERN> t;
-    if (sizeof(real) == 4) {
-        t.H2 = (real)P.fterm[0];
-        t.invHu = (real)P.fterm[1];
-        t.invHu5 = (real)P.fterm[2];
-        t.a0 = (real)P.fterm[3];
-        t.a1 = (real)P.fterm[4];
-        t.ex = (real)P.fterm[5];
-        t.ey = (real)P.fterm[6];
-        t.ez = (real)P.fterm[7];
-    } else {
-        t.H2 = (real)P.H2d;
-        t.invHu = (real)P.invHu;
-        t.invHu5 = (real)P.invHu5;
-        t.a0 = (real)P.a0;
-        t.a1 = (real)P.a1;
-        t.ex = (real)P.ehat[0];
-        t.ey = (real)P.ehat[1];
-        t.ez = (real)P.ehat[2];
-    }
+    real c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = (sizeof(real) == 4) ? (real)P.fterm[k] : (real)P.dterm[k];
+    t.H2 = c[0];
+    t.invHu = c[1];
+    t.invHu5 = c[2];
+    t.a0 = c[3];
+    t.a1 = c[4];
+    t.ex = c[5];
+    t.ey = c[6];
+    t.ez = c[7];
     return t;
 }
 
@@ -115,21 +108,32 @@ __device__ __forceinline__ Cand<real> unpack(const uint4& r) {
 }
 
 // ---------------------------------------------------------------------------
-// Candidate list of a target in LDS.  Entry k holds (delta_k, e_k): the range
-// [s_k, e_k) of the sorted order and delta_k = s_k - e_(k-1) (e_(-1) = 0).
-// A sentinel closes the list; stepping into it puts the cursor at 2^31 or
-// more with the end at 2^30, so no slot is valid after it and no further
-// step is taken.  Entries of one target are `stride` apart (the targets of a
+// Candidate list of a target in LDS, in bytes of the 16-byte record array
+// (a context holds fewer than 2^28 - 256 particles, so offsets fit 32 bits
+// with room for a cursor step past the end).  Every stored range [s_k, e_k)
+// of the sorted order is non-empty.  With one lane per target entry k holds
+// (s_k, e_k); with several, (delta_k, e_k), delta_k = s_k - e_(k-1) (e_(-1) =
+// 0), so that a lane's overshoot past one range carries into the next.  A
+// sentinel closes the list; stepping into it puts the cursor at 2^31 or more
+// with the end at 2^30, so no slot is valid after it and no further step is
+// taken.  Entries of one target are `stride` apart (the targets of a
 // workgroup interleaved), and list[0] is the target's first entry.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kListEndStart = 0x80000000u, kListEndEnd = 0x40000000u;
+constexpr uint32_t kRecBytes = 16;
 
-template <int DIM>
+template <int DIM, int LANES>
 __device__ __forceinline__ uint32_t build_list(const PlumeDev& P, const uint32_t* __restrict__ cs,
                                                const Target& T, uint2* list, uint32_t stride) {
     const int span = 2 * P.R + 1;
     const int noff = (DIM == 3) ? span * span : span;
     uint32_t prev = 0, k = 0, total = 0;
+    auto put = [&](uint32_t s, uint32_t e) {
+        list[k * stride] = make_uint2(LANES == 1 ? s * kRecBytes : s * kRecBytes - prev, e * kRecBytes);
+        total += e - s;
+        prev = e * kRecBytes;
+        ++k;
+    };
     // four rows at a time: their cell-start loads are in flight together
     for (int j = 0; j < noff; j += 4) {
         RowRanges r[4];
@@ -140,41 +144,43 @@ __device__ __forceinline__ uint32_t build_list(const PlumeDev& P, const uint32_t
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (r[q].e0 > r[q].s0) {
-                list[k * stride] = make_uint2(r[q].s0 - prev, r[q].e0);
-                total += r[q].e0 - r[q].s0;
-                prev = r[q].e0;
-                ++k;
-            }
-            if (r[q].e1 > r[q].s1) {
-                list[k * stride] = make_uint2(r[q].s1 - prev, r[q].e1);
-                total += r[q].e1 - r[q].s1;
-                prev = r[q].e1;
-                ++k;
-            }
+            if (r[q].e0 > r[q].s0) put(r[q].s0, r[q].e0);
+            if (r[q].e1 > r[q].s1) put(r[q].s1, r[q].e1);
         }
     }
-    list[k * stride] = make_uint2(kListEndStart - prev, kListEndEnd);
+    list[k * stride] = make_uint2(LANES == 1 ? kListEndStart : kListEndStart - prev, kListEndEnd);
     return total;
 }
 
-// Lane cursor over the concatenated ranges: b is the next sorted index of
-// this lane, e the end of its range; nx the entry after the current one (in
-// flight from LDS).  After a step of LANES, b - e < LANES exactly when the
-// lane has run past the end of its range by less than one stride, which is
-// the overshoot carried into the next range.
+// Lane cursor over the concatenated ranges: b is the byte offset of this
+// lane's next record, e the end of its range; nx the entry after the current
+// one (in flight from LDS).  A step advances b by LANES records.  With one
+// lane a step lands exactly on the end of a range and the cursor moves to
+// the next entry as it stands; with several, b - e < step exactly when the
+// lane has run past the end of its range by less than one step, which is the
+// overshoot carried into the next range (perhaps past it).
 template <int LANES>
 struct Cursor {
+    static constexpr uint32_t kStep = LANES * kRecBytes;
     uint32_t b, e;
     uint2 nx;
     const uint2* lp;
     uint32_t stride;
     __device__ __forceinline__ void settle() {
-        while (b - e < (uint32_t)LANES) {
-            b += nx.x;
-            e = nx.y;
-            lp += stride;
-            nx = *lp;
+        if (LANES == 1) {
+            if (b == e) {
+                b = nx.x;
+                e = nx.y;
+                lp += stride;
+                nx = *lp;
+            }
+        } else {
+            while (b - e < kStep) {
+                b += nx.x;
+                e = nx.y;
+                lp += stride;
+                nx = *lp;
+            }
         }
     }
 };
@@ -199,7 +205,7 @@ __device__ __forceinline__ void walk_list(const PairTerm<DIM, real, KERN>& term,
     if (nb == 0) return;
 
     Cursor<LANES> cur;
-    cur.b = lj;
+    cur.b = lj * kRecBytes;
     cur.e = 0;
     cur.lp = list;
     cur.stride = stride;
@@ -214,8 +220,8 @@ __device__ __forceinline__ void walk_list(const PairTerm<DIM, real, KERN>& term,
         uint32_t idx[B];
 #pragma unroll
         for (int q = 0; q < B; ++q) {
-            idx[q] = cur.b < cur.e ? cur.b : self;
-            cur.b += LANES;
+            idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
+            cur.b += Cursor<LANES>::kStep;
             cur.settle();
         }
 #pragma unroll
@@ -279,21 +285,24 @@ __device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* _
     // every lane of a target writes the same list (no cross-lane hand-over)
     uint2* list = lds_list + lt;
     uint32_t total = 0;
-    if (active) total = build_list<DIM>(P, a.cell_start, T, list, tpb);
+    if (active) total = build_list<DIM, LANES>(P, a.cell_start, T, list, tpb);
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
     if (kRec)
         walk_list<DIM, real, KERN, LANES>(term, T, Ca, i, list, tpb, total, lj,
                                           [&](uint32_t k) {
-                                              // 32-bit byte offset from a uniform base (at most
-                                              // 2^28 records): one shift per address
+                                              // 32-bit byte offset from a uniform base
                                               return unpack<DIM, real>(*reinterpret_cast<const uint4*>(
-                                                  reinterpret_cast<const char*>(rec) + (k << 4)));
+                                                  reinterpret_cast<const char*>(rec) + k));
                                           },
                                           acc);
     else
         walk_list<DIM, real, KERN, LANES>(
             term, T, Ca, i, list, tpb, total, lj,
-            [&](uint32_t k) { return Cand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, Cp[k]}; }, acc);
+            [&](uint32_t k) {
+                k /= kRecBytes;
+                return Cand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, Cp[k]};
+            },
+            acc);
 
     // wavefront reduction over the lanes of a target (fixed order: deterministic)
     if (LANES >= 2) acc += __shfl_xor(acc, 1, kWave);
