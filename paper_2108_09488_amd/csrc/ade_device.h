@@ -42,15 +42,15 @@ __device__ __forceinline__ uint32_t cell_key(const PlumeDev& P, uint32_t ux, uin
     return P.cbase + (rz * P.nr + ry) * P.nfx + fx;
 }
 
-// Counting pass: count particle i (an index into the hashed buffer U) in its
-// cell and record it in the cell's bucket, or past kBucket in the overflow list.
-__device__ __forceinline__ void enlist(const CellLists& L, uint32_t key, uint32_t i) {
+// Counting pass: count the particle with this id in its cell and record the
+// id in the cell's bucket, or past kBucket in the overflow list.
+__device__ __forceinline__ void enlist(const CellLists& L, uint32_t key, uint32_t id) {
     const uint32_t t = atomicAdd(&L.count[key], 1u);
     if (t < kBucket) {
-        L.bucket[(size_t)key * kBucket + t] = i;
+        L.bucket[(size_t)key * kBucket + t] = id;
     } else {
         const uint32_t p = atomicAdd(&L.ovf_count[0], 1u);
-        L.ovf[p] = make_uint2(key, i);
+        L.ovf[p] = make_uint2(key, id);
     }
 }
 

@@ -64,14 +64,14 @@ struct StateArrays {
     uint32_t* key;   // cell key (hashed buffer U only)
 };
 
-// Counting pass of the cell build: the number of particles per cell and who
-// they are -- the first kBucket of a cell in its bucket, any further ones in
-// an overflow list of (key, index) pairs.
+// Counting pass of the cell build: the number of particles per cell and
+// their ids -- the first kBucket of a cell in its bucket, any further ones in
+// an overflow list of (key, id) pairs.
 constexpr uint32_t kBucket = 8;
 struct CellLists {
     uint32_t* count;      // per cell (cleared by the scan)
-    uint32_t* bucket;     // kBucket entries per cell: indices into U
-    uint2* ovf;           // overflow pairs (key, index), up to N
+    uint32_t* bucket;     // kBucket entries per cell: particle ids
+    uint2* ovf;           // overflow pairs (key, id), up to N
     uint32_t* ovf_count;  // [0] pairs added since the last scan, [1] pairs of the current build
 };
 

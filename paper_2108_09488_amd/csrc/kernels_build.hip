@@ -32,7 +32,7 @@ __global__ __launch_bounds__(kTile) void k_init(const PlumeDev* __restrict__ plu
     U.id[i] = i;
     const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
     U.key[i] = key;
-    enlist(lists, key, i);
+    enlist(lists, key, i);  // id = index here
 }
 
 // ---------------------------------------------------------------------------
@@ -154,8 +154,8 @@ hipError_t launch_scan64(int64_t* data, uint32_t n, int64_t* partial, hipStream_
 
 // ---------------------------------------------------------------------------
 // placement: every particle of U goes to cell_start[key] + (its rank by id
-// among the particles of its cell), found from the cell's bucket (and, for a
-// cell of more than kBucket particles, the overflow list), so the sorted
+// among the particles of its cell), found from the ids in the cell's bucket
+// (and, for a cell of more than kBucket particles, the overflow list), so the sorted
 // order is a pure function of the positions.  Writes the sorted state S and
 // its candidate records; advances the step counter if asked.
 // ---------------------------------------------------------------------------
@@ -170,16 +170,20 @@ __global__ __launch_bounds__(256) void k_place(StateArrays U, StateArrays S, Cel
     const uint32_t my = U.id[i];
     const uint32_t s = cell_start[key];
     const uint32_t n = cell_start[key + 1] - s;
-    const uint32_t* __restrict__ bk = L.bucket + (size_t)key * kBucket;
     uint32_t rank = 0;
+    if (n > 1) {  // alone in its cell: rank 0
+        const uint4* __restrict__ bq = reinterpret_cast<const uint4*>(L.bucket + (size_t)key * kBucket);
+        const uint4 b0 = bq[0];
+        const uint4 b1 = (n > 4) ? bq[1] : make_uint4(0u, 0u, 0u, 0u);
+        const uint32_t m[kBucket] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
 #pragma unroll
-    for (uint32_t t = 0; t < kBucket; ++t)
-        if (t < n) rank += (U.id[bk[t]] < my) ? 1u : 0u;
-    if (n > kBucket) {  // crowded cell: the rest of it is in the overflow list
-        const uint32_t no = L.ovf_count[1];
-        for (uint32_t p = 0; p < no; ++p) {
-            const uint2 e = L.ovf[p];
-            if (e.x == key) rank += (U.id[e.y] < my) ? 1u : 0u;
+        for (uint32_t t = 0; t < kBucket; ++t) rank += (t < n && m[t] < my) ? 1u : 0u;
+        if (n > kBucket) {  // crowded cell: the rest of it is in the overflow list
+            const uint32_t no = L.ovf_count[1];
+            for (uint32_t p = 0; p < no; ++p) {
+                const uint2 e = L.ovf[p];
+                if (e.x == key) rank += (e.y < my) ? 1u : 0u;
+            }
         }
     }
     const uint32_t d = s + rank;

@@ -333,10 +333,11 @@ __device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* _
         a.upos[c][i] = u[c];
     }
     static_cast<real*>(a.uC)[i] = fmar(sc, acc, Cb);
-    a.uid[i] = a.sid[i];
+    const uint32_t id = a.sid[i];
+    a.uid[i] = id;
     const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
     a.ukey[i] = key;
-    enlist(a.lists, key, i);
+    enlist(a.lists, key, id);
 }
 
 // Eight wavefronts per SIMD for the FP32 kernels: at most 64 VGPRs and 100
