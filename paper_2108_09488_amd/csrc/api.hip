@@ -235,6 +235,24 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
     pl.N = (int64_t)N;
     pl.ncell = cbase;
     pl.ntiles = (uint32_t)pl.tiles.size();
+    // The pair kernel takes the plumes in decreasing order of their expected
+    // neighbours per particle (support volume over particle volume), so that
+    // the cheapest work items come last and fill the end of the launch.
+    {
+        std::vector<std::pair<double, int>> cost;
+        for (int p = 0; p < nplumes; ++p) {
+            const ade_params& q = params[p];
+            const double vol = (pl.dim == 2) ? kPi * q.H * q.H : 4.0 / 3.0 * kPi * q.H * q.H * q.H;
+            cost.emplace_back(-(double)counts[p] * vol / std::pow(q.L, pl.dim), p);
+        }
+        std::stable_sort(cost.begin(), cost.end());
+        pl.pair_tiles.clear();
+        for (const auto& c : cost) {
+            const PlumeDev& d = pl.plumes[c.second];
+            pl.pair_tiles.insert(pl.pair_tiles.end(), pl.tiles.begin() + d.tfirst,
+                                 pl.tiles.begin() + d.tfirst + d.tcount);
+        }
+    }
     pl.nscan = (uint32_t)std::max<uint64_t>(cell_pad(pl.ncell) / kCellChunk,
                                             ((uint64_t)N + 1 + kScanChunk - 1) / kScanChunk);
     return ADE_OK;
@@ -249,6 +267,7 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
     const size_t rb = (size_t)pl.real_bytes;
     c->plumes = b.take<PlumeDev>(pl.P);
     c->tiles = b.take<TileDev>(pl.ntiles);
+    c->pair_tiles = b.take<TileDev>(pl.ntiles);
     StateArrays* bufs[2] = {&c->S, &c->U};
     for (int k = 0; k < 2; ++k) {
         StateArrays& s = *bufs[k];
@@ -321,7 +340,7 @@ PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase,
     PairLaunch a;
     std::memset(&a, 0, sizeof a);
     a.plumes = c->plumes;
-    a.tiles = c->tiles;
+    a.tiles = c->pair_tiles;
     a.ntiles = c->plan.ntiles;
     a.block = c->tuning.block;
     a.lanes = c->tuning.lanes;
@@ -450,6 +469,7 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
     };
     if (hipMemcpyAsync(c->plumes, pl.plumes.data(), sizeof(PlumeDev) * pl.P, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->tiles, pl.tiles.data(), sizeof(TileDev) * pl.ntiles, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+        hipMemcpyAsync(c->pair_tiles, pl.pair_tiles.data(), sizeof(TileDev) * pl.ntiles, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemcpyAsync(c->cell_start + pl.ncell, &c->h_total, sizeof(uint32_t), hipMemcpyHostToDevice, c->stream) != hipSuccess ||
         hipMemsetAsync(c->count, 0, sizeof(uint32_t) * cell_pad(pl.ncell), c->stream) != hipSuccess ||
         hipMemsetAsync(c->step, 0, sizeof(int64_t), c->stream) != hipSuccess ||

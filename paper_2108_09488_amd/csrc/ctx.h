@@ -31,6 +31,7 @@ struct Plan {
     int list_cap = 0;  // candidate-list entries per target (largest plume)
     std::vector<PlumeDev> plumes;
     std::vector<TileDev> tiles;
+    std::vector<TileDev> pair_tiles;  // the tiles in the pair kernel's order (costliest plumes first)
 };
 
 // whether a launch shape fits the plan (LDS of the candidate lists)
@@ -47,6 +48,7 @@ struct ade_ctx {
     ade_tuning tuning{256, 2, 0, 0};
     ade::PlumeDev* plumes = nullptr;
     ade::TileDev* tiles = nullptr;
+    ade::TileDev* pair_tiles = nullptr;
     ade::StateArrays S{}, U{};
     ade::CellLists lists{};
     uint32_t* count = nullptr;
