@@ -90,9 +90,14 @@ typedef struct {
  * wavefronts, so lanes is the waves-per-CU knob.  Each target keeps the list
  * of its candidate ranges in LDS: 8 * (2 * rows + 2) bytes per target, rows =
  * (2R+1)^(dim-1) neighbour rows of the plume with the most, and block / lanes
- * targets per workgroup must fit in 64 KiB (ADE_EINVAL otherwise).  The
- * summation order, and so the last bits of the result, depend on lanes and on
- * nothing else here. */
+ * targets per workgroup must fit in 64 KiB (ADE_EINVAL otherwise).
+ * targets = 2 (with lanes = 1 and block <= 128) gives each lane two
+ * consecutive target particles of the cell order: the lane walks one list
+ * holding the candidates of both, 8 * (P * (S + 3) + 2) bytes per lane with
+ * S = 2R+1 rows and P = 1 (2D) or S + 1 (3D) planes, and evaluates every
+ * candidate it loads for both targets, halving the candidate loads per pair
+ * evaluated.  The summation order, and so the last bits of the result,
+ * depend on lanes and targets and on nothing else here. */
 typedef struct {
     int32_t block;          /* threads per workgroup: 64, 128 or 256          */
     int32_t lanes;          /* lanes per target particle: 1, 2 or 4           */
@@ -102,6 +107,7 @@ typedef struct {
                                of the work evenly; 0 = default (32)          */
     int32_t persistent;     /* 0: one workgroup per work item; > 0: a grid of
                                that many workgroups loops over the items     */
+    int32_t targets;        /* target particles per lane: 1 (0 = 1) or 2      */
 } ade_tuning;
 
 /* Bytes of device workspace needed for nplumes plumes with counts[p]
@@ -180,11 +186,11 @@ int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *
 int ade_kernel_timing(ade_ctx *ctx, int32_t mode, double *h_ms, int64_t *h_count);
 
 /* Autotuner: times the pair kernel (reps launches each, HIP events on the
- * context's stream) over the launch shapes block {64,128,256} x lanes {1,2,4}
- * x persistent {0, 8 workgroups per CU} x xcd_group {8, 32, 128} that fit the
- * LDS limit, keeps the fastest
- * in the context and returns it in *best (may be NULL).  With
- * ADE_TUNE_KEEP_LANES the current lanes value is kept, so results stay
+ * context's stream) over the launch shapes block {64,128,256} x (lanes,
+ * targets) {(1,2), (1,1), (2,1), (4,1)} x persistent {0, 8 workgroups per CU}
+ * x xcd_group {8, 32, 128} that are valid and fit the LDS limit, keeps the
+ * fastest in the context and returns it in *best (may be NULL).  With
+ * ADE_TUNE_KEEP_LANES the current lanes and targets are kept, so results stay
  * bitwise identical to the untuned context.  Needs built cells; does not
  * change the particle state.  Synchronises the stream. */
 enum { ADE_TUNE_KEEP_LANES = 1 };

@@ -40,7 +40,7 @@ class AdeParams(ct.Structure):
 
 class AdeTuning(ct.Structure):
     _fields_ = [("block", ct.c_int32), ("lanes", ct.c_int32), ("xcd_group", ct.c_int32),
-                ("persistent", ct.c_int32)]
+                ("persistent", ct.c_int32), ("targets", ct.c_int32)]
 
 
 class AdeError(RuntimeError):

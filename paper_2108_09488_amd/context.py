@@ -24,6 +24,11 @@ def _ptr(t: torch.Tensor) -> ct.c_void_p:
     return ct.c_void_p(t.data_ptr())
 
 
+def _tuning_dict(t: AdeTuning) -> dict:
+    return {"block": t.block, "lanes": t.lanes, "xcd_group": t.xcd_group, "persistent": t.persistent,
+            "targets": t.targets if t.targets else 1}
+
+
 class Context:
     """One context of nplumes plumes (an ensemble when nplumes > 1).
 
@@ -174,16 +179,16 @@ class Context:
         t = AdeTuning()
         check(lib().ade_autotune(self._h, int(reps), _lib.ADE_TUNE_KEEP_LANES if keep_lanes else 0,
                                  ct.byref(t)))
-        return {"block": t.block, "lanes": t.lanes, "xcd_group": t.xcd_group, "persistent": t.persistent}
+        return _tuning_dict(t)
 
-    def set_tuning(self, block=256, lanes=2, persistent=0, xcd_group=0):
-        t = AdeTuning(block, lanes, xcd_group, persistent)
+    def set_tuning(self, block=256, lanes=2, persistent=0, xcd_group=0, targets=1):
+        t = AdeTuning(block, lanes, xcd_group, persistent, targets)
         check(lib().ade_set_tuning(self._h, ct.byref(t)))
 
     def get_tuning(self) -> dict:
         t = AdeTuning()
         check(lib().ade_get_tuning(self._h, ct.byref(t)))
-        return {"block": t.block, "lanes": t.lanes, "xcd_group": t.xcd_group, "persistent": t.persistent}
+        return _tuning_dict(t)
 
     def adjoint(self, nsteps: int, ckpt_every: int, xs: torch.Tensor, obs: torch.Tensor):
         """J and dJ/d(alpha_L, alpha_T, D_m) of plume 0 after nsteps Euler steps."""

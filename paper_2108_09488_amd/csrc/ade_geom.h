@@ -60,9 +60,10 @@ __device__ __forceinline__ Target make_target(const PlumeDev& P, uint32_t ux, ui
 // seam (k2 > k3 marks it empty).  The bounds are conservative: the float
 // rounding of the distances is covered by relative slack on w^2 and an
 // absolute slack of 64 grid units on w.
+// Half-width w of the x window of a target in its neighbour row (oy, oz);
+// false when the row lies beyond the search radius.
 template <int DIM>
-__device__ __forceinline__ bool row_cells(const PlumeDev& P, const Target& T, int oy, int oz,
-                                          uint32_t& k0, uint32_t& k1, uint32_t& k2, uint32_t& k3) {
+__device__ __forceinline__ bool row_halfwidth(const PlumeDev& P, const Target& T, int oy, int oz, uint32_t& w) {
     float dy = 0.f, dz = 0.f;
     if (oy > 0) dy = (float)oy - T.fy;
     else if (oy < 0) dy = (float)(-oy - 1) + T.fy;
@@ -71,27 +72,37 @@ __device__ __forceinline__ bool row_cells(const PlumeDev& P, const Target& T, in
         else if (oz < 0) dz = (float)(-oz - 1) + T.fz;
     }
     const float d2 = (dy * dy + dz * dz) * P.rowh2f;
-    uint32_t w = P.hx;
+    w = P.hx;
     if (d2 > 0.f) {
         const float w2 = P.Hc2f * 1.000001f - d2 * 0.999999f;
         if (w2 <= 0.f) return false;
         const float wf = __builtin_amdgcn_sqrtf(w2) * 1.000001f + 64.0f;
         w = wf < (float)P.hx ? (uint32_t)wf : P.hx;
     }
+    return true;
+}
+
+// First cell of row (yy, zz) of a plume (row indices already wrapped).
+__device__ __forceinline__ uint32_t row_base(const PlumeDev& P, int yy, int zz) {
+    return P.cbase + ((uint32_t)zz * P.nr + (uint32_t)yy) * P.nfx;
+}
+
+__device__ __forceinline__ int wrap_row(const PlumeDev& P, int y) {
     const int nr = (int)P.nr;
-    int yy = T.ry + oy;
-    yy += (yy < 0) ? nr : 0;
-    yy -= (yy >= nr) ? nr : 0;
-    int zz = 0;
-    if (DIM == 3) {
-        zz = T.rz + oz;
-        zz += (zz < 0) ? nr : 0;
-        zz -= (zz >= nr) ? nr : 0;
-    }
+    y += (y < 0) ? nr : 0;
+    y -= (y >= nr) ? nr : 0;
+    return y;
+}
+
+// Cells of row `row` under the x window [xlo, xhi] (fixed point, inclusive,
+// xhi - xlo < 2^32 - one cell width as an unsigned difference): k0 .. k1,
+// and k2 .. k3 when the window wraps around the periodic seam (k2 > k3
+// marks it empty).
+__device__ __forceinline__ void window_cells(const PlumeDev& P, uint32_t row, uint32_t xlo, uint32_t xhi,
+                                             uint32_t& k0, uint32_t& k1, uint32_t& k2, uint32_t& k3) {
     const uint32_t nfx = P.nfx;
-    const uint32_t row = P.cbase + ((uint32_t)zz * P.nr + (uint32_t)yy) * nfx;
-    const uint32_t clo = __umulhi(T.ux - w, nfx);
-    const uint32_t chi = __umulhi(T.ux + w, nfx);
+    const uint32_t clo = __umulhi(xlo, nfx);
+    const uint32_t chi = __umulhi(xhi, nfx);
     if (clo <= chi) {
         k0 = row + clo;
         k1 = row + chi;
@@ -103,6 +114,16 @@ __device__ __forceinline__ bool row_cells(const PlumeDev& P, const Target& T, in
         k2 = row;
         k3 = row + chi;
     }
+}
+
+template <int DIM>
+__device__ __forceinline__ bool row_cells(const PlumeDev& P, const Target& T, int oy, int oz,
+                                          uint32_t& k0, uint32_t& k1, uint32_t& k2, uint32_t& k3) {
+    uint32_t w;
+    if (!row_halfwidth<DIM>(P, T, oy, oz, w)) return false;
+    const int yy = wrap_row(P, T.ry + oy);
+    const int zz = (DIM == 3) ? wrap_row(P, T.rz + oz) : 0;
+    window_cells(P, row_base(P, yy, zz), T.ux - w, T.ux + w, k0, k1, k2, k3);
     return true;
 }
 

@@ -83,6 +83,7 @@ struct PairLaunch {
     uint32_t ntiles;
     int block;              // threads per workgroup
     int lanes;              // lanes per target particle (1, 2 or 4)
+    int targets;            // target particles per lane: 1, or 2 (one lane, block <= 128)
     int list_cap;           // candidate-list entries per target in LDS (2 * rows + 2)
     int persistent;         // 0: one workgroup per work item; > 0: that many workgroups loop
     uint32_t xcd_group;     // consecutive work items an XCD takes in turn (>= 1)
@@ -109,6 +110,9 @@ struct PairLaunch {
 // rows (each row can be split in two at the periodic seam, plus a sentinel
 // and one entry read past it)
 inline int list_cap_for(int noff) { return 2 * noff + 2; }
+// the same for the merged list of a lane's two targets (span + 1 rows per
+// plane, span + 1 planes in 3D; n + 2 ranges per plane of n rows)
+inline int list_cap_pair_for(int dim, int span) { return (dim == 3 ? span + 1 : 1) * (span + 3) + 2; }
 // LDS bytes of the pair kernel's candidate lists for a workgroup
 inline size_t pair_lds_bytes(int block, int lanes, int list_cap) {
     return (size_t)(block / lanes) * (size_t)list_cap * 8u;

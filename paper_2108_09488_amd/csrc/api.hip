@@ -34,10 +34,19 @@ int fail(int code, const char* fmt, ...) {
     return code;
 }
 
+int targets_of(const ade_tuning& t) { return t.targets == 2 ? 2 : 1; }
+// two targets per lane: the merged list, or the single-target list of the
+// second target of a pair that could not be merged, whichever is longer
+int tuning_list_cap(const Plan& pl, const ade_tuning& t) {
+    return targets_of(t) == 2 ? std::max(pl.list_cap_pair, pl.list_cap) : pl.list_cap;
+}
+
 bool tuning_fits(const Plan& pl, const ade_tuning& t) {
     if (t.block != 64 && t.block != 128 && t.block != 256) return false;
     if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4) return false;
-    return pair_lds_bytes(t.block, t.lanes, pl.list_cap) <= kPairLdsMax;
+    if (t.targets != 0 && t.targets != 1 && t.targets != 2) return false;
+    if (targets_of(t) == 2 && (t.lanes != 1 || 2 * t.block > kTile)) return false;
+    return pair_lds_bytes(t.block, t.lanes, tuning_list_cap(pl, t)) <= kPairLdsMax;
 }
 
 double trace_D(int dim, double aL, double aT, double Dm, const double* v, double D[9]) {
@@ -230,6 +239,7 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         d.tcount = (uint32_t)pl.tiles.size() - d.tfirst;
         const int span = 2 * R + 1;
         pl.list_cap = std::max(pl.list_cap, list_cap_for(pl.dim == 3 ? span * span : span));
+        pl.list_cap_pair = std::max(pl.list_cap_pair, list_cap_pair_for(pl.dim, span));
         pl.plumes.push_back(d);
     }
     pl.N = (int64_t)N;
@@ -344,7 +354,8 @@ PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase,
     a.ntiles = c->plan.ntiles;
     a.block = c->tuning.block;
     a.lanes = c->tuning.lanes;
-    a.list_cap = c->plan.list_cap;
+    a.targets = targets_of(c->tuning);
+    a.list_cap = tuning_list_cap(c->plan, c->tuning);
     a.persistent = c->tuning.persistent;
     a.xcd_group = c->tuning.xcd_group > 0 ? (uint32_t)c->tuning.xcd_group : 32u;
     // candidate records carrying the concentrations the pair sum reads
@@ -442,7 +453,7 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
     // default launch shape: two lanes per target, else four, else smaller
     // workgroups, whichever first fits the LDS of the candidate lists
     {
-        const ade_tuning defaults[4] = {{256, 2, 0, 0}, {256, 4, 0, 0}, {128, 4, 0, 0}, {64, 4, 0, 0}};
+        const ade_tuning defaults[4] = {{256, 2, 0, 0, 1}, {256, 4, 0, 0, 1}, {128, 4, 0, 0, 1}, {64, 4, 0, 0, 1}};
         bool ok = false;
         for (const ade_tuning& t : defaults)
             if (!ok && tuning_fits(c->plan, t)) {
@@ -623,13 +634,16 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     ade_tuning best_t = start;
     bool have = false;
     int rc = ADE_OK;
-    const int blocks[3] = {64, 128, 256}, lanes[3] = {1, 2, 4}, pers[2] = {0, 2048}, groups[3] = {8, 32, 128};
-    for (int lb : lanes) {
-        if ((flags & ADE_TUNE_KEEP_LANES) && lb != start.lanes) continue;
+    const int blocks[3] = {64, 128, 256}, pers[2] = {0, 2048}, groups[3] = {8, 32, 128};
+    // (lanes, targets): one lane per two targets, or 1, 2, 4 lanes per target
+    const int shapes[4][2] = {{1, 2}, {1, 1}, {2, 1}, {4, 1}};
+    for (const auto& sh : shapes) {
+        const int lb = sh[0], tg = sh[1];
+        if ((flags & ADE_TUNE_KEEP_LANES) && (lb != start.lanes || tg != targets_of(start))) continue;
         for (int bb : blocks)
             for (int xg : groups)
                 for (int pp : pers) {
-                    const ade_tuning cand{bb, lb, xg, pp};
+                    const ade_tuning cand{bb, lb, xg, pp, tg};
                     if (!tuning_fits(pl, cand)) continue;
                     c->tuning = cand;
                     PairLaunch a = pair_args(c, kModeRhs, c->S.C, c->S.C, 1.0, c->aux);
@@ -666,10 +680,14 @@ int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
     if (t->block != 64 && t->block != 128 && t->block != 256)
         return fail(ADE_EINVAL, "block must be 64, 128 or 256");
     if (t->lanes != 1 && t->lanes != 2 && t->lanes != 4) return fail(ADE_EINVAL, "lanes must be 1, 2 or 4");
+    if (t->targets < 0 || t->targets > 2) return fail(ADE_EINVAL, "targets must be 0, 1 or 2");
+    if (targets_of(*t) == 2 && (t->lanes != 1 || t->block > 128))
+        return fail(ADE_EINVAL, "two targets per lane need lanes = 1 and block <= 128");
     if (t->xcd_group < 0 || t->xcd_group > 4096) return fail(ADE_EINVAL, "xcd_group in 0..4096");
     if (!tuning_fits(c->plan, *t))
-        return fail(ADE_EINVAL, "candidate lists of block/lanes = %d targets need %zu bytes of LDS (max %zu)",
-                    t->block / t->lanes, pair_lds_bytes(t->block, t->lanes, c->plan.list_cap), kPairLdsMax);
+        return fail(ADE_EINVAL, "candidate lists of %d lists per workgroup need %zu bytes of LDS (max %zu)",
+                    t->block / t->lanes, pair_lds_bytes(t->block, t->lanes, tuning_list_cap(c->plan, *t)),
+                    kPairLdsMax);
     if (t->persistent < 0 || t->persistent > 65536) return fail(ADE_EINVAL, "persistent in 0..65536");
     c->tuning = *t;
     drop_graph(c);

@@ -28,7 +28,8 @@ struct Plan {
     int64_t N = 0;
     uint64_t ncell = 0;
     uint32_t ntiles = 0, nscan = 0;
-    int list_cap = 0;  // candidate-list entries per target (largest plume)
+    int list_cap = 0;       // candidate-list entries per target (largest plume)
+    int list_cap_pair = 0;  // the same for a lane's merged list of two targets
     std::vector<PlumeDev> plumes;
     std::vector<TileDev> tiles;
     std::vector<TileDev> pair_tiles;  // the tiles in the pair kernel's order (costliest plumes first)

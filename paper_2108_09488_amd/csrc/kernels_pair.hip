@@ -48,13 +48,19 @@ struct PairTerm {
     real H2, invHu, invHu5, a0, a1, ex, ey, ez;
     __device__ __forceinline__ void operator()(const Target& T, real Ca, uint32_t bx, uint32_t by,
                                                uint32_t bz, real Cb, real& acc) const {
+        (*this)(T, Ca, bx, by, bz, Cb, true, acc);
+    }
+    // the same, added only if keep (a padding slot of a walk shared by two
+    // targets)
+    __device__ __forceinline__ void operator()(const Target& T, real Ca, uint32_t bx, uint32_t by,
+                                               uint32_t bz, real Cb, bool keep, real& acc) const {
         const real dx = (real)(int32_t)(T.ux - bx);
         const real dy = (real)(int32_t)(T.uy - by);
         const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - bz) : (real)0;
         real r2 = dx * dx;
         r2 = fmar(dy, dy, r2);
         if (DIM == 3) r2 = fmar(dz, dz, r2);
-        const bool inside = r2 > (real)0 && r2 <= H2;
+        const bool inside = keep && r2 > (real)0 && r2 <= H2;
         const real rinv = rsqrt_r(r2);
         const real r = r2 * rinv;
         // 1 - q; inside the support up to the rounding of r (a negative value
@@ -250,6 +256,45 @@ __device__ __forceinline__ void walk_list(const PairTerm<DIM, real, KERN>& term,
     }
 }
 
+// The end of a target's pair sum acc: rhs mode writes the right-hand side
+// (vphi * acc) in id order; half mode the half-step concentration (and its
+// candidate record); step mode updates C and x and hashes the moved particle
+// into the next build's cell counts.
+template <int DIM, typename real, int MODE>
+__device__ __forceinline__ void finish_target(const PairLaunch& a, const PlumeDev& P, const Target& T, uint32_t i,
+                                              real acc) {
+    constexpr bool kRec = Rec<DIM, real>::kStageable;
+    if (MODE == kModeRhs) {
+        static_cast<real*>(a.out)[a.sid[i]] = (real)P.vphi * acc;
+        return;
+    }
+    const real sc = (real)(a.scale * P.dt * P.vphi);
+    const real Cb = static_cast<const real*>(a.Cbase)[i];
+    if (MODE == kModeHalf) {
+        const real Ch = fmar(sc, acc, Cb);
+        static_cast<real*>(a.out)[i] = Ch;
+        if (kRec) a.out_rec[i] = Rec<DIM, real>::pack(T.ux, T.uy, T.uz, Ch);
+        return;
+    }
+    // step: update C and x, hash the moved particle for the next build
+    const int64_t k = *a.step;
+    uint32_t u[3] = {T.ux, T.uy, T.uz};
+#pragma unroll
+    for (int c = 0; c < DIM; ++c) {
+        const double us = P.ushift[c];
+        const int64_t s1 = (int64_t)rint((double)(k + 1) * us);
+        const int64_t s0 = (int64_t)rint((double)k * us);
+        u[c] += (uint32_t)(s1 - s0);
+        a.upos[c][i] = u[c];
+    }
+    static_cast<real*>(a.uC)[i] = fmar(sc, acc, Cb);
+    const uint32_t id = a.sid[i];
+    a.uid[i] = id;
+    const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
+    a.ukey[i] = key;
+    enlist(a.lists, key, id);
+}
+
 // One work item = `block / LANES` consecutive target particles of one tile.
 // The plume and tile tables come in as read-only, non-aliased kernel
 // arguments so that their workgroup-uniform reads go through the scalar unit.
@@ -308,36 +353,250 @@ __device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* _
     if (LANES >= 2) acc += __shfl_xor(acc, 1, kWave);
     if (LANES >= 4) acc += __shfl_xor(acc, 2, kWave);
     if (!active || lj != 0) return;
+    finish_target<DIM, real, MODE>(a, P, T, i, acc);
+}
 
-    if (MODE == kModeRhs) {
-        static_cast<real*>(a.out)[a.sid[i]] = (real)P.vphi * acc;
-        return;
+// ---------------------------------------------------------------------------
+// Two targets per lane.  A lane takes the consecutive sorted targets a and b
+// of a work item (one tile, so one plume).  When their rows are at most one
+// apart along y (and z), it visits each row that can hold a neighbour of
+// either target once (span + 1 rows per axis at most), with the x window of
+// the row widened to the smallest arc that holds the windows of the targets
+// reaching it, and evaluates every record of that one list against both
+// targets.  Each neighbour of a or b is listed exactly once, so the loads of
+// the walk serve two pair sums.
+//
+// List capacity: the arcs shrink away from the pair (the windows of either
+// target do, and the pair's rows are adjacent), so the rows whose arc crosses
+// the periodic x seam are consecutive.  A split row is emitted low part
+// first; its high part ends where the next row's low part begins, and
+// touching ranges are stored as one, so a plane of n rows takes at most n + 2
+// entries (one more than n + 1 for a wrap of the row index among the split
+// rows).  A pair whose rows are further apart (sparse plumes) walks a's own
+// list, then b's.
+// ---------------------------------------------------------------------------
+template <int DIM>
+__device__ __forceinline__ bool pair_rows(const PlumeDev& P, const Target& A, const Target& B, int& dy, int& dz) {
+    const int nr = (int)P.nr, span = 2 * P.R + 1;
+    auto circ = [&](int d) {
+        if (2 * d > nr) d -= nr;
+        if (2 * d < -nr) d += nr;
+        return d;
+    };
+    dy = circ(B.ry - A.ry);
+    dz = (DIM == 3) ? circ(B.rz - A.rz) : 0;
+    return span + 1 <= nr && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+}
+
+// Sorted-index ranges of row number j of a pair's rows: (s1, e1) is the low
+// part of a row cut by the seam (empty otherwise), (s0, e0) the rest.
+template <int DIM>
+__device__ __forceinline__ RowRanges union_row(const PlumeDev& P, const uint32_t* __restrict__ cs, const Target& A,
+                                               const Target& B, int dy, int dz, int j) {
+    RowRanges r{0u, 0u, 0u, 0u};
+    const int R = P.R;
+    const int ny = 2 * R + 1 + (dy != 0 ? 1 : 0);
+    const int oy = j % ny + min(0, dy) - R;
+    const int oz = (DIM == 3) ? j / ny + min(0, dz) - R : 0;
+    uint32_t wa = 0, wb = 0;
+    const bool ra = abs(oy) <= R && abs(oz) <= R && row_halfwidth<DIM>(P, A, oy, oz, wa);
+    const bool rb = abs(oy - dy) <= R && abs(oz - dz) <= R && row_halfwidth<DIM>(P, B, oy - dy, oz - dz, wb);
+    if (!ra && !rb) return r;
+    // the arc in a's frame: [lo, hi] relative to A.ux
+    const int64_t d = (int32_t)(B.ux - A.ux);
+    int64_t lo = ra ? -(int64_t)wa : d - (int64_t)wb;
+    int64_t hi = ra ? (int64_t)wa : d + (int64_t)wb;
+    if (ra && rb) {
+        lo = min(lo, d - (int64_t)wb);
+        hi = max(hi, d + (int64_t)wb);
     }
-    const real sc = (real)(a.scale * P.dt * P.vphi);
-    const real Cb = static_cast<const real*>(a.Cbase)[i];
-    if (MODE == kModeHalf) {
-        const real Ch = fmar(sc, acc, Cb);
-        static_cast<real*>(a.out)[i] = Ch;
-        if (kRec) a.out_rec[i] = Rec<DIM, real>::pack(T.ux, T.uy, T.uz, Ch);
-        return;
+    const uint32_t row = row_base(P, wrap_row(P, A.ry + oy), (DIM == 3) ? wrap_row(P, A.rz + oz) : 0);
+    uint32_t k0, k1, k2, k3;
+    if (hi - lo >= (int64_t)4294967296ll - (int64_t)(4294967296ull / P.nfx) - 2) {  // the whole row
+        k0 = row;
+        k1 = row + P.nfx - 1u;
+        k2 = 1u;
+        k3 = 0u;
+    } else {
+        window_cells(P, row, A.ux + (uint32_t)lo, A.ux + (uint32_t)hi, k0, k1, k2, k3);
     }
-    // step: update C and x, hash the moved particle for the next build
-    const int64_t k = *a.step;
-    uint32_t u[3] = {T.ux, T.uy, T.uz};
+    r.s0 = cs[k0];
+    r.e0 = cs[k1 + 1];
+    if (k2 <= k3) {
+        r.s1 = cs[k2];
+        r.e1 = cs[k3 + 1];
+    }
+    return r;
+}
+
+template <int DIM>
+__device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_t* __restrict__ cs, const Target& A,
+                                                const Target& B, int dy, int dz, uint2* list, uint32_t stride) {
+    const int ny = 2 * P.R + 1 + (dy != 0 ? 1 : 0);
+    const int nz = (DIM == 3) ? 2 * P.R + 1 + (dz != 0 ? 1 : 0) : 1;
+    const int nrows = ny * nz;
+    uint32_t k = 0, total = 0;
+    uint32_t ps = 0, pe = 0;  // pending range (pe == 0: none; ranges are non-empty)
+    auto put = [&](uint32_t s, uint32_t e) {
+        if (pe != 0u && s == pe) {  // touches the pending range
+            pe = e;
+            return;
+        }
+        if (pe != 0u) {
+            list[k * stride] = make_uint2(ps * kRecBytes, pe * kRecBytes);
+            total += pe - ps;
+            ++k;
+        }
+        ps = s;
+        pe = e;
+    };
+    // two rows at a time: their cell-start loads are in flight together
+    for (int j = 0; j < nrows; j += 2) {
+        RowRanges r[2];
 #pragma unroll
-    for (int c = 0; c < DIM; ++c) {
-        const double us = P.ushift[c];
-        const int64_t s1 = (int64_t)rint((double)(k + 1) * us);
-        const int64_t s0 = (int64_t)rint((double)k * us);
-        u[c] += (uint32_t)(s1 - s0);
-        a.upos[c][i] = u[c];
+        for (int q = 0; q < 2; ++q) {
+            r[q] = RowRanges{0u, 0u, 0u, 0u};
+            if (j + q < nrows) r[q] = union_row<DIM>(P, cs, A, B, dy, dz, j + q);
+        }
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            if (r[q].e1 > r[q].s1) put(r[q].s1, r[q].e1);
+            if (r[q].e0 > r[q].s0) put(r[q].s0, r[q].e0);
+        }
     }
-    static_cast<real*>(a.uC)[i] = fmar(sc, acc, Cb);
-    const uint32_t id = a.sid[i];
-    a.uid[i] = id;
-    const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
-    a.ukey[i] = key;
-    enlist(a.lists, key, id);
+    if (pe != 0u) {
+        list[k * stride] = make_uint2(ps * kRecBytes, pe * kRecBytes);
+        total += pe - ps;
+        ++k;
+    }
+    list[k * stride] = make_uint2(kListEndStart, kListEndEnd);
+    return total;
+}
+
+// The walk of walk_list with one lane per list and two targets: every
+// record fetched is evaluated against TA and TB.  Padding slots re-read a's
+// own record, which a's predicate rejects (r2 = 0); b's evaluation keeps only
+// the slots below the lane's total (slot = batch * B + q).  Sums are added
+// to accA and accB.
+template <int DIM, typename real, int KERN, typename Fetch>
+__device__ __forceinline__ void walk_pair(const PairTerm<DIM, real, KERN>& term, const Target& TA, const Target& TB,
+                                          real CA, real CB, uint32_t self, const uint2* list, uint32_t stride,
+                                          uint32_t total, Fetch&& fetch, real& accA, real& accB) {
+    constexpr int B = Batch<1>::value;
+    uint32_t share = total;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
+    const uint32_t nb = __builtin_amdgcn_readfirstlane((share + B - 1) / B);
+    if (nb == 0) return;
+
+    Cursor<1> cur;
+    cur.b = 0;
+    cur.e = 0;
+    cur.lp = list;
+    cur.stride = stride;
+    cur.nx = list[0];
+    cur.settle();
+
+    __builtin_amdgcn_s_waitcnt(0);
+    Cand<real> c0[B], c1[B];
+    auto fill = [&](Cand<real>(&c)[B]) {
+        uint32_t idx[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
+            cur.b += Cursor<1>::kStep;
+            cur.settle();
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) c[q] = fetch(idx[q]);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto eval = [&](const Cand<real>(&c)[B], uint32_t batch) {
+        const uint32_t s0 = batch * B;  // wavefront-uniform
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            term(TA, CA, c[q].x, c[q].y, c[q].z, c[q].C, accA);
+            term(TB, CB, c[q].x, c[q].y, c[q].z, c[q].C, s0 + q < total, accB);
+        }
+    };
+    fill(c0);
+    for (uint32_t it = 1;; it += 2) {
+        if (it >= nb) {
+            eval(c0, it - 1);
+            break;
+        }
+        fill(c1);
+        eval(c0, it - 1);
+        if (it + 1 >= nb) {
+            eval(c1, it);
+            break;
+        }
+        fill(c0);
+        eval(c1, it);
+    }
+}
+
+// One work item = 2 * block consecutive target particles of one tile, two
+// per lane.
+template <int DIM, typename real, int KERN, int MODE>
+__device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* __restrict__ plumes,
+                                           const TileDev* __restrict__ tiles, uint32_t w, uint2* lds_list) {
+    const uint32_t stride = (uint32_t)a.block;
+    const uint32_t tpb = 2u * stride;  // targets per workgroup
+    const uint32_t subs = kTile / tpb;
+    const TileDev t = tiles[w / subs];
+    const uint32_t i0 = t.start + (w % subs) * tpb;
+    if (i0 >= t.end) return;  // whole workgroup: ragged last tile
+    const uint32_t i1 = min(t.end, i0 + tpb);
+    const PlumeDev P = plumes[t.plume];
+    // past the end of a ragged tile a lane keeps a copy of a valid target
+    // (its sums are discarded)
+    const uint32_t ia = i0 + 2u * threadIdx.x, ib = ia + 1u;
+    const bool actA = ia < i1, actB = ib < i1;
+    const uint32_t iA = actA ? ia : i0, iB = actB ? ib : iA;
+
+    const uint32_t* __restrict__ px = a.spos[0];
+    const uint32_t* __restrict__ py = a.spos[1];
+    const uint32_t* __restrict__ pz = a.spos[2];
+    const real* __restrict__ Cp = static_cast<const real*>(a.Cpair);
+    const uint4* __restrict__ rec = a.rec;
+    constexpr bool kRec = Rec<DIM, real>::kStageable;
+    auto fetch = [&](uint32_t k) {
+        if (kRec)  // 32-bit byte offset from a uniform base
+            return unpack<DIM, real>(*reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(rec) + k));
+        k /= kRecBytes;
+        return Cand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, Cp[k]};
+    };
+
+    const Target TA = make_target<DIM>(P, px[iA], py[iA], (DIM == 3) ? pz[iA] : 0u);
+    const Target TB = make_target<DIM>(P, px[iB], py[iB], (DIM == 3) ? pz[iB] : 0u);
+    const real CA = Cp[iA], CB = Cp[iB];
+    const PairTerm<DIM, real, KERN> term = make_term<DIM, real, KERN>(P);
+    real accA = (real)0, accB = (real)0;
+
+    uint2* list = lds_list + threadIdx.x;
+    int dy = 0, dz = 0;
+    const bool merged = actB && pair_rows<DIM>(P, TA, TB, dy, dz);
+    uint32_t total = 0;
+    if (merged) total = build_union<DIM>(P, a.cell_start, TA, TB, dy, dz, list, stride);
+    else if (actA) total = build_list<DIM, 1>(P, a.cell_start, TA, list, stride);
+    else list[0] = make_uint2(kListEndStart, kListEndEnd);
+    walk_pair<DIM, real, KERN>(term, TA, TB, CA, CB, iA, list, stride, total, fetch, accA, accB);
+    if (actA) finish_target<DIM, real, MODE>(a, P, TA, iA, accA);
+    if (merged) finish_target<DIM, real, MODE>(a, P, TB, iB, accB);
+
+    // b of a pair that could not be merged walks its own list (a second walk
+    // that only wavefronts holding such a pair enter)
+    const bool alone = actB && !merged;
+    if (__builtin_amdgcn_ballot_w64(alone) == 0ull) return;
+    const Target T2 = make_target<DIM>(P, px[iB], py[iB], (DIM == 3) ? pz[iB] : 0u);
+    const real C2 = Cp[iB];
+    uint32_t total2 = 0;
+    if (alone) total2 = build_list<DIM, 1>(P, a.cell_start, T2, list, stride);
+    else list[0] = make_uint2(kListEndStart, kListEndEnd);
+    real acc2 = (real)0;
+    walk_list<DIM, real, KERN, 1>(term, T2, C2, iB, list, stride, total2, 0u, fetch, acc2);
+    if (alone) finish_target<DIM, real, MODE>(a, P, T2, iB, acc2);
 }
 
 // Eight wavefronts per SIMD for the FP32 kernels: at most 64 VGPRs and 100
@@ -363,6 +622,26 @@ void k_pair(PairLaunch a, const PlumeDev* __restrict__ plumes,
         const uint32_t w = xcd_item(x, m, nwork, a.xcd_group);
         if (w >= nwork) break;
         pair_item<DIM, real, KERN, MODE, LANES>(a, plumes, tiles, w, lds_list);
+    }
+}
+
+// Two targets per lane: at most 128 threads (a work item holds 2 * block
+// targets of a 256-particle tile); six wavefronts per SIMD for 2D FP32 (the
+// lane carries both targets through the walk).
+template <int DIM, typename real, int KERN, int MODE>
+__global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 && DIM == 2 ? 6 : 1)))
+void k_pair2(PairLaunch a, const PlumeDev* __restrict__ plumes, const TileDev* __restrict__ tiles, uint32_t nwork) {
+    extern __shared__ uint2 lds_list[];
+    if (a.persistent == 0) {
+        pair_item2<DIM, real, KERN, MODE>(a, plumes, tiles, xcd_remap(blockIdx.x, gridDim.x, a.xcd_group), lds_list);
+        return;
+    }
+    const uint32_t nx = 8, x = blockIdx.x % nx, k = blockIdx.x / nx;
+    const uint32_t per_x = (gridDim.x + nx - 1 - x) / nx;
+    for (uint32_t m = k;; m += per_x) {
+        const uint32_t w = xcd_item(x, m, nwork, a.xcd_group);
+        if (w >= nwork) break;
+        pair_item2<DIM, real, KERN, MODE>(a, plumes, tiles, w, lds_list);
     }
 }
 
@@ -428,8 +707,27 @@ static void launch_pair_l(int mode, const PairLaunch& a, hipStream_t s) {
 }
 
 template <int DIM, typename real, int KERN>
+static void launch_pair_2(int mode, const PairLaunch& a, hipStream_t s) {
+    const uint32_t tpb = 2u * (uint32_t)a.block;
+    const uint32_t nwork = a.ntiles * (kTile / tpb);
+    PairLaunch c = a;
+    if (nwork < 8) c.persistent = 0;
+    const uint32_t grid = (c.persistent > 0) ? max(8u, min(nwork, (uint32_t)c.persistent)) : nwork;
+    dim3 g(grid), b(a.block);
+    const size_t shm = pair_lds_bytes(a.block, 1, a.list_cap);
+    auto kern = (mode == kModeStep)   ? k_pair2<DIM, real, KERN, kModeStep>
+                : (mode == kModeHalf) ? k_pair2<DIM, real, KERN, kModeHalf>
+                                      : k_pair2<DIM, real, KERN, kModeRhs>;
+    if (c.ev0)
+        hipExtLaunchKernelGGL(kern, g, b, (uint32_t)shm, s, c.ev0, c.ev1, 0u, c, c.plumes, c.tiles, nwork);
+    else
+        hipLaunchKernelGGL(kern, g, b, shm, s, c, c.plumes, c.tiles, nwork);
+}
+
+template <int DIM, typename real, int KERN>
 static void launch_pair_t(int mode, const PairLaunch& a, hipStream_t s) {
-    if (a.lanes == 4) launch_pair_l<DIM, real, KERN, 4>(mode, a, s);
+    if (a.targets == 2) launch_pair_2<DIM, real, KERN>(mode, a, s);
+    else if (a.lanes == 4) launch_pair_l<DIM, real, KERN, 4>(mode, a, s);
     else if (a.lanes == 2) launch_pair_l<DIM, real, KERN, 2>(mode, a, s);
     else launch_pair_l<DIM, real, KERN, 1>(mode, a, s);
 }
@@ -439,6 +737,7 @@ hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const Pair
     (void)block;
     if (a.block <= 0 || a.block > kTile || kTile % a.block != 0) return hipErrorInvalidValue;
     if (a.lanes != 1 && a.lanes != 2 && a.lanes != 4) return hipErrorInvalidValue;
+    if (a.targets != 1 && (a.targets != 2 || a.lanes != 1 || 2 * a.block > kTile)) return hipErrorInvalidValue;
     if (a.list_cap < 3 || pair_lds_bytes(a.block, a.lanes, a.list_cap) > kPairLdsMax) return hipErrorInvalidValue;
     if (dim == 2) {
         if (real_bytes == 4) {

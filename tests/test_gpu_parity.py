@@ -208,10 +208,11 @@ def test_determinism_and_graph_replay():
     assert np.array_equal(outs[0], outs[2])
 
 
-TUNINGS = [  # (block, lanes, persistent, xcd_group)
-    (256, 1, 0, 0), (128, 1, 0, 1), (64, 1, 0, 8), (256, 1, 64, 0), (128, 1, 7, 3),
-    (256, 2, 0, 0), (64, 2, 0, 128), (128, 2, 40, 5), (256, 2, 8, 1),
-    (256, 4, 0, 0), (128, 4, 13, 2), (64, 4, 0, 7), (256, 4, 300, 4096),
+TUNINGS = [  # (block, lanes, persistent, xcd_group, targets per lane)
+    (256, 1, 0, 0, 1), (128, 1, 0, 1, 1), (64, 1, 0, 8, 1), (256, 1, 64, 0, 1), (128, 1, 7, 3, 1),
+    (256, 2, 0, 0, 1), (64, 2, 0, 128, 1), (128, 2, 40, 5, 1), (256, 2, 8, 1, 1),
+    (256, 4, 0, 0, 1), (128, 4, 13, 2, 1), (64, 4, 0, 7, 1), (256, 4, 300, 4096, 1),
+    (128, 1, 0, 0, 2), (64, 1, 0, 8, 2), (128, 1, 40, 3, 2), (64, 1, 7, 1, 2), (128, 1, 0, 4096, 2),
 ]
 
 
@@ -221,24 +222,25 @@ TUNINGS = [  # (block, lanes, persistent, xcd_group)
 def test_launch_shapes_are_bitwise_equal(name, over):
     """Workgroup size, the persistent grid and the dealing of work items to
     the XCDs change which workgroup runs a target, not the order of its sums:
-    for a given number of lanes per particle every launch shape gives the same
-    bits, and all match the oracle."""
+    for a given number of lanes per particle (or of particles per lane) every
+    launch shape gives the same bits, and all match the oracle."""
     spec = I.config(name, **over)
     ctx, x, C = _ctx(spec)
     r = O.rhs(O.model_from_spec(spec), x, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
-    by_lanes = {}
-    for block, lanes, pers, xg in TUNINGS:
+    by_shape = {}
+    for block, lanes, pers, xg, tg in TUNINGS:
         try:
-            ctx.set_tuning(block=block, lanes=lanes, persistent=pers, xcd_group=xg)
+            ctx.set_tuning(block=block, lanes=lanes, persistent=pers, xcd_group=xg, targets=tg)
         except RuntimeError:
-            # 3D candidate lists of 256 targets exceed the LDS limit
-            assert spec.dim == 3 and block // lanes == 256
+            # 3D candidate lists of 256 targets (or of 128 lanes with two
+            # targets each) exceed the LDS limit
+            assert spec.dim == 3 and (block // lanes == 256 or (tg == 2 and block == 128))
             continue
         out = ctx.rhs().cpu().numpy().copy()
-        if lanes in by_lanes:
-            assert np.array_equal(out, by_lanes[lanes]), (block, lanes, pers, xg)
+        if (lanes, tg) in by_shape:
+            assert np.array_equal(out, by_shape[(lanes, tg)]), (block, lanes, pers, xg, tg)
         else:
-            by_lanes[lanes] = out
+            by_shape[(lanes, tg)] = out
         assert _rel(out.astype(np.float64), r) < (1e-12 if spec.real_bytes == 8 else 1e-5)
     ctx.set_tuning()
     ctx.close()
@@ -287,3 +289,163 @@ def test_autotune_keep_lanes_is_bitwise_neutral():
     assert t2 == ctx.get_tuning()
     ctx.step(3)
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# Two target particles per lane: one merged candidate list serves both
+# ---------------------------------------------------------------------------
+PAIRED = dict(block=128, lanes=1, targets=2)
+
+
+@pytest.mark.parametrize("name,over,integrator,steps", [
+    ("cfg2_h20_r10", {"n_side": 128}, 1, 100),
+    ("cfg2_h13_r100", {"n_side": 101}, 2, 60),                      # odd N: a lane with one target
+    ("cfg2_h30_r10", {"n_side": 96}, 1, 60),
+    ("cfg1", {"n_side": 45}, 2, 100),                                # FP64, predictor-corrector
+    ("cfg3", {"n_side": 20}, 1, 30),
+    ("cfg3", {"n_side": 14, "real_bytes": 8}, 2, 20),
+])
+def test_two_targets_per_lane_trajectory(name, over, integrator, steps):
+    """Steps with two targets per lane (merged lists, both integrators, 2D and
+    3D, FP32 and FP64) against the oracle, and the right-hand side first."""
+    spec = I.config(name, **over)
+    ctx, x, C0 = _ctx(spec, integrator=integrator)
+    ctx.set_tuning(**PAIRED, xcd_group=8)
+    tol = 1e-12 if spec.real_bytes == 8 else 1e-5
+    g = ctx.rhs().double().cpu().numpy()
+    r = O.rhs(O.model_from_spec(spec), x, C0, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+    assert _rel(g, r) < tol
+    ctx.step(steps)
+    C = ctx.read_C().double().cpu().numpy()
+    _, Co, _ = O.run(O.model_from_spec(spec), x, C0, spec.dt, steps, v_uniform=spec.velocity(),
+                     mass=spec.mass, rho=spec.rho0, integrator=integrator)
+    assert _rel(C, Co) < tol
+    ctx.close()
+
+
+def _banded(dim, rows_apart, per_row, L, H, seed):
+    """Particles only in every rows_apart-th row of the default cell grid
+    (rows of height L / nr, nr = floor(2 L / H') as the planner sizes them),
+    per_row of them spread along x in each: consecutive particles of the cell
+    order then sit in rows that far apart wherever a row's count is odd."""
+    rng = np.random.default_rng(seed)
+    hu = H / L * TWO32
+    hc = hu * (1 + 2.0 ** -16) + 2
+    nr = int(np.floor(TWO32 * 2 / hc))
+    h = L / nr
+    pts = []
+    rows = range(0, nr, rows_apart)
+    planes = range(0, nr, rows_apart) if dim == 3 else [0]
+    for z in planes:
+        for y in rows:
+            for k in range(per_row):
+                p = [rng.uniform(0, L), (y + rng.uniform(0.2, 0.8)) * h]
+                if dim == 3:
+                    p.append((z + rng.uniform(0.2, 0.8)) * h)
+                pts.append(p)
+    # on the fixed-point grid the library stores positions on, so that FP64
+    # results compare at 1e-12
+    return O.to_fixed(np.array(pts).T.copy(), L).astype(np.float64) / TWO32 * L
+
+
+@pytest.mark.parametrize("dim,real_bytes,rows_apart,per_row", [(2, 4, 2, 7), (2, 8, 3, 5), (2, 4, 1, 1),
+                                                               (3, 4, 2, 3)])
+def test_two_targets_unmerged_pairs(dim, real_bytes, rows_apart, per_row):
+    """Sparse rows make the two targets of many lanes sit rows apart, so their
+    candidates cannot share one list: the second target walks its own.  The
+    right-hand side and a few steps match the oracle, and the bits match
+    between two runs."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = I.config("cfg1" if dim == 2 else "cfg3", n_side=16 if dim == 2 else 12, real_bytes=real_bytes,
+                    h_over_dp=1.5)
+    x = _banded(dim, rows_apart, per_row, spec.L, spec.H, seed=rows_apart * 10 + per_row)
+    n = x.shape[1]
+    C = spec.concentration(x)
+    if real_bytes == 4:
+        C = C.astype(np.float32).astype(np.float64)
+    tol = 1e-12 if real_bytes == 8 else 1e-5
+    outs = []
+    for rep in range(2):
+        print(f"[case] banded dim={dim} rb={real_bytes} apart={rows_apart} per_row={per_row} n={n} rep={rep}",
+              flush=True)
+        ctx = Context([params_from_spec(spec)], [n])
+        ctx.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+        ctx.set_tuning(block=64, lanes=1, targets=2)
+        g = ctx.rhs().double().cpu().numpy()
+        r = O.rhs(O.model_from_spec(spec), x, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+        assert np.linalg.norm(r) > 0
+        assert _rel(g, r) < tol
+        ctx.step(4)
+        outs.append(ctx.read_C().cpu().numpy().copy())
+        if rep == 0:
+            _, Co, _ = O.run(O.model_from_spec(spec), x, C, spec.dt, 4, v_uniform=spec.velocity(),
+                             mass=spec.mass, rho=spec.rho0)
+            assert _rel(outs[0].astype(np.float64), Co) < tol
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_two_targets_crowded_cells_and_ensemble():
+    """Crowded cells (overflow lists) and a multi-plume context with two
+    targets per lane: bitwise equal to the same plumes run one by one with
+    the same launch shape, and the first plume matches the oracle."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    specs = I.ensemble(6, sides=(16, 24, 40))
+    xs = [s.positions() for s in specs]
+    Cs = [s.concentration(x).astype(np.float32).astype(np.float64) for s, x in zip(specs, xs)]
+    ens = Context([params_from_spec(s) for s in specs], [s.n for s in specs])
+    ens.init(torch.from_numpy(np.concatenate(xs, axis=1)), torch.from_numpy(np.concatenate(Cs))).build()
+    ens.set_tuning(**PAIRED)
+    ens.step(10)
+    Ce = ens.read_C().cpu().numpy()
+    off = 0
+    for p, s in enumerate(specs):
+        one = Context([params_from_spec(s)], [s.n])
+        one.init(torch.from_numpy(xs[p]), torch.from_numpy(Cs[p])).build()
+        one.set_tuning(**PAIRED)
+        one.step(10)
+        assert np.array_equal(Ce[off:off + s.n], one.read_C().cpu().numpy()), p
+        off += s.n
+        one.close()
+    s = specs[0]
+    _, Co, _ = O.run(O.model_from_spec(s), xs[0], Cs[0], s.dt, 10, v_uniform=s.velocity(), mass=s.mass, rho=s.rho0)
+    assert _rel(Ce[:s.n].astype(np.float64), Co) < 1e-5
+    ens.close()
+    spec = I.config("cfg1", n_side=20, real_bytes=4, h_over_dp=1.3)
+    x = I.clustered(spec.n_side, 2, 12, 0.02, spec.L, stream=3)
+    C = spec.concentration(x).astype(np.float32).astype(np.float64)
+    ctx = Context([params_from_spec(spec)], [x.shape[1]])
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+    ctx.set_tuning(**PAIRED)
+    g = ctx.rhs().double().cpu().numpy()
+    r = O.rhs(O.model_from_spec(spec), x, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+    assert _rel(g, r) < 1e-5
+    ctx.close()
+
+
+def test_two_targets_graph_replay_and_validation():
+    """Graph replay equals eager launches with two targets per lane, and the
+    launch shapes it cannot take are refused."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = I.config("cfg2_h20_r10", n_side=96)
+    outs = []
+    for mode in ("eager", "graph"):
+        stream = torch.cuda.Stream()
+        ctx = Context([params_from_spec(spec)], [spec.n], stream=stream)
+        x = spec.positions()
+        ctx.init(torch.from_numpy(x), torch.from_numpy(spec.concentration(x))).build()
+        ctx.set_tuning(block=64, lanes=1, targets=2, persistent=2048)
+        if mode == "eager":
+            ctx.step(20)
+        else:
+            for _ in range(2):
+                ctx.step_graph(10)
+                torch.cuda.synchronize()
+        outs.append(ctx.read_C().cpu().numpy().copy())
+        for bad in (dict(block=256, lanes=1, targets=2), dict(block=128, lanes=2, targets=2),
+                    dict(block=128, lanes=1, targets=3)):
+            with pytest.raises(RuntimeError):
+                ctx.set_tuning(**bad)
+        stream.synchronize()
+        ctx.close()
+    assert np.array_equal(outs[0], outs[1])
