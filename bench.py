@@ -38,15 +38,26 @@ PAIR_SOURCES = ["kernels_pair.hip", "ade_geom.h", "ade_device.h", "ade_internal.
 PEAK_FP32_NONPACKED_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA)
 
 
-def pair_traffic():
+def step_kernel_name(tuning):
+    """The update-mode pair kernel a launch shape runs (2D, FP32, Wendland C4)."""
+    if tuning.get("targets", 1) == 2:
+        return "k_pair2<2, float, 4, 0>"
+    return f"k_pair<2, float, 4, 0, {tuning['lanes']}>"
+
+
+def pair_traffic(kernel):
     """HBM bytes per pair-kernel launch from the committed FETCH_SIZE/WRITE_SIZE
-    profile, or None when the kernel sources changed since it was taken."""
+    profile, or None when the kernel sources changed since it was taken or the
+    profile covers another launch shape's kernel."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
-    vals = dict(l.split(":", 1) for l in text.splitlines() if l.startswith(("traffic_bytes_per_launch:", "source_sha256:")))
+    vals = dict(l.split(":", 1) for l in text.splitlines()
+                if l.startswith(("traffic_bytes_per_launch:", "source_sha256:", "kernel:")))
+    if vals.get("kernel", "").strip() != kernel:
+        return None
     h = hashlib.sha256()
     for f in PAIR_SOURCES:
         with open(os.path.join(ROOT, "paper_2108_09488_amd", "csrc", f), "rb") as fh:
@@ -313,8 +324,9 @@ def main():
                    "plumes": cells, "interactions_per_step": inter_step, "per_plume": per_cell,
                    "tuning": sweep["tuning"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS, "traffic": pair_traffic(),
-                     "kernel": "k_pair (step mode)", "avg_launch_ms": avg_ms,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "traffic": pair_traffic(step_kernel_name(sweep["tuning"])),
+                     "kernel": step_kernel_name(sweep["tuning"]) + " (update mode)", "avg_launch_ms": avg_ms,
                      "launches": pair["launches"],
                      "flops_per_interaction": FLOPS_PER_INTERACTION[2],
                      "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS},

@@ -97,7 +97,9 @@ typedef struct {
  * S = 2R+1 rows and P = 1 (2D) or S + 1 (3D) planes, and evaluates every
  * candidate it loads for both targets, halving the candidate loads per pair
  * evaluated.  The summation order, and so the last bits of the result,
- * depend on lanes and targets and on nothing else here. */
+ * depend on lanes and targets and on nothing else here.  A new context starts
+ * with block 64, lanes 1, targets 2 (else the first of {256,2}, {256,4},
+ * {128,4}, {64,4} lanes per target that fits). */
 typedef struct {
     int32_t block;          /* threads per workgroup: 64, 128 or 256          */
     int32_t lanes;          /* lanes per target particle: 1, 2 or 4           */
@@ -185,8 +187,11 @@ int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *
  * *h_count (either may be NULL). */
 int ade_kernel_timing(ade_ctx *ctx, int32_t mode, double *h_ms, int64_t *h_count);
 
-/* Autotuner: times the pair kernel (reps launches each, HIP events on the
- * context's stream) over the launch shapes block {64,128,256} x (lanes,
+/* Autotuner: times the pair kernel as a step launches it (update mode; reps
+ * launches each plus one warm-up, each timed by HIP events stamped with the
+ * kernel's own start and end on the context's stream; the kernel's outputs
+ * go to the step's scratch buffers and the next build's cell counts, which
+ * are cleared after every launch) over the launch shapes block {64,128,256} x (lanes,
  * targets) {(1,2), (1,1), (2,1), (4,1)} x persistent {0, 8 workgroups per CU}
  * x xcd_group {8, 32, 128} that are valid and fit the LDS limit, keeps the
  * fastest in the context and returns it in *best (may be NULL).  With

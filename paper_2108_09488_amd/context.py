@@ -181,7 +181,7 @@ class Context:
                                  ct.byref(t)))
         return _tuning_dict(t)
 
-    def set_tuning(self, block=256, lanes=2, persistent=0, xcd_group=0, targets=1):
+    def set_tuning(self, block=64, lanes=1, persistent=0, xcd_group=0, targets=2):
         t = AdeTuning(block, lanes, xcd_group, persistent, targets)
         check(lib().ade_set_tuning(self._h, ct.byref(t)))
 

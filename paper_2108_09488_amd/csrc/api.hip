@@ -450,10 +450,12 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
         delete c;
         return rc;
     }
-    // default launch shape: two lanes per target, else four, else smaller
-    // workgroups, whichever first fits the LDS of the candidate lists
+    // default launch shape: two targets per lane in workgroups of 64 (the
+    // fastest shape on the 2D sweep), else two lanes per target, else four,
+    // else smaller workgroups, whichever first fits the LDS of the lists
     {
-        const ade_tuning defaults[4] = {{256, 2, 0, 0, 1}, {256, 4, 0, 0, 1}, {128, 4, 0, 0, 1}, {64, 4, 0, 0, 1}};
+        const ade_tuning defaults[5] = {
+            {64, 1, 0, 0, 2}, {256, 2, 0, 0, 1}, {256, 4, 0, 0, 1}, {128, 4, 0, 0, 1}, {64, 4, 0, 0, 1}};
         bool ok = false;
         for (const ade_tuning& t : defaults)
             if (!ok && tuning_fits(c->plan, t)) {
@@ -621,6 +623,14 @@ int ade_kernel_timing(ade_ctx* c, int32_t mode, double* h_ms, int64_t* h_count) 
     return ADE_OK;
 }
 
+// cell counts and overflow count of the next build back to zero (as every
+// build leaves them)
+static int clear_counts(ade_ctx* c) {
+    HIPCHK(hipMemsetAsync(c->count, 0, sizeof(uint32_t) * cell_pad(c->plan.ncell), c->stream));
+    HIPCHK(hipMemsetAsync(c->lists.ovf_count, 0, 2 * sizeof(uint32_t), c->stream));
+    return ADE_OK;
+}
+
 int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     if (!c) return fail(ADE_EINVAL, "null ctx");
     if (reps < 1) return fail(ADE_EINVAL, "reps must be positive");
@@ -646,17 +656,29 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
                     const ade_tuning cand{bb, lb, xg, pp, tg};
                     if (!tuning_fits(pl, cand)) continue;
                     c->tuning = cand;
-                    PairLaunch a = pair_args(c, kModeRhs, c->S.C, c->S.C, 1.0, c->aux);
-                    if ((rc = run_pair(c, kModeRhs, a))) break;  // warm-up
-                    if (hipEventRecord(e0, c->stream) != hipSuccess) { rc = fail(ADE_EHIP, "event record"); break; }
-                    for (int r = 0; r < reps && !rc; ++r) rc = run_pair(c, kModeRhs, a);
-                    if (rc) break;
-                    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) {
-                        rc = fail(ADE_EHIP, "event synchronise");
-                        break;
-                    }
+                    // the step-mode kernel, as a step runs it; its outputs go to
+                    // the hashed buffer U and the cell counts of the next build,
+                    // which are cleared again after every launch
+                    PairLaunch a = pair_args(c, kModeStep, c->S.C, c->S.C, 1.0, nullptr);
                     float ms = 0.f;
-                    hipEventElapsedTime(&ms, e0, e1);
+                    for (int r = 0; r <= reps && !rc; ++r) {  // r = 0: warm-up
+                        PairLaunch t = a;
+                        t.ev0 = e0;
+                        t.ev1 = e1;
+                        if (launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeStep, t, cand.block, c->stream) !=
+                                hipSuccess ||
+                            (rc = clear_counts(c)) != ADE_OK) {
+                            if (!rc) rc = fail(ADE_EHIP, "autotune launch");
+                            break;
+                        }
+                        float one = 0.f;
+                        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&one, e0, e1) != hipSuccess) {
+                            rc = fail(ADE_EHIP, "event synchronise");
+                            break;
+                        }
+                        if (r > 0) ms += one;
+                    }
+                    if (rc) break;
                     if (!have || ms < best_ms) {
                         best_ms = ms;
                         best_t = c->tuning;
@@ -665,6 +687,8 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
                 }
         if (rc) break;
     }
+    const int rc_clear = clear_counts(c);  // also after a failed launch
+    if (!rc) rc = rc_clear;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     (void)pl;
