@@ -57,6 +57,10 @@ struct PairTerm {
         const real dx = (real)(int32_t)(T.ux - bx);
         const real dy = (real)(int32_t)(T.uy - by);
         const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - bz) : (real)0;
+        sep(dx, dy, dz, Ca, Cb, keep, acc);
+    }
+    // the same from the separation (dx, dy, dz) = x_a - x_b in grid units
+    __device__ __forceinline__ void sep(real dx, real dy, real dz, real Ca, real Cb, bool keep, real& acc) const {
         real r2 = dx * dx;
         r2 = fmar(dy, dy, r2);
         if (DIM == 3) r2 = fmar(dz, dz, r2);
@@ -385,7 +389,15 @@ __device__ __forceinline__ bool pair_rows(const PlumeDev& P, const Target& A, co
     };
     dy = circ(B.ry - A.ry);
     dz = (DIM == 3) ? circ(B.rz - A.rz) : 0;
-    return span + 1 <= nr && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
+    // |x_b - x_a| + H_u < 2^31 per axis: then for every neighbour c of b the
+    // integer sum (x_b - x_a) + (x_a - x_c) does not wrap, and walk_pair's
+    // separations of b are those of the minimum image
+    auto near = [&](uint32_t ub, uint32_t ua) {
+        const int32_t d = (int32_t)(ub - ua);
+        return (uint32_t)(d < 0 ? -(int64_t)d : (int64_t)d) + P.hx < 0x80000000u;
+    };
+    const bool close = near(B.ux, A.ux) && near(B.uy, A.uy) && (DIM != 3 || near(B.uz, A.uz));
+    return close && span + 1 <= nr && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
 }
 
 // Sorted-index ranges of row number j of a pair's rows: (s1, e1) is the low
@@ -477,7 +489,15 @@ __device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_
 // record fetched is evaluated against TA and TB.  Padding slots re-read a's
 // own record, which a's predicate rejects (r2 = 0); b's evaluation keeps only
 // the slots below the lane's total (slot = batch * B + q).  Sums are added
-// to accA and accB.
+// to accA and accB.  b's separation from a record is taken as (x_b - x_a) +
+// (x_a - x_c) in the working precision, which saves its integer differences
+// and conversions.  pair_rows merges only pairs with |x_b - x_a| + H_u < 2^31
+// per axis, so for every neighbour of b the integer sum is its minimum-image
+// separation; a record whose sum leaves [-2^31, 2^31) is then no neighbour
+// of b, and the sum, at least 2^31 in magnitude, rejects it.  Exact in FP64; in FP32 one more rounding, which can move a
+// candidate across r = H only within a rounding of it, where its term is
+// below 1e-35 of a typical one (the neighbour-set export keeps the exact
+// predicate).
 template <int DIM, typename real, int KERN, typename Fetch>
 __device__ __forceinline__ void walk_pair(const PairTerm<DIM, real, KERN>& term, const Target& TA, const Target& TB,
                                           real CA, real CB, uint32_t self, const uint2* list, uint32_t stride,
@@ -511,12 +531,18 @@ __device__ __forceinline__ void walk_pair(const PairTerm<DIM, real, KERN>& term,
         for (int q = 0; q < B; ++q) c[q] = fetch(idx[q]);
         __builtin_amdgcn_sched_barrier(0);
     };
+    const real bx = (real)(int32_t)(TB.ux - TA.ux);
+    const real by = (real)(int32_t)(TB.uy - TA.uy);
+    const real bz = (DIM == 3) ? (real)(int32_t)(TB.uz - TA.uz) : (real)0;
     auto eval = [&](const Cand<real>(&c)[B], uint32_t batch) {
         const uint32_t s0 = batch * B;  // wavefront-uniform
 #pragma unroll
         for (int q = 0; q < B; ++q) {
-            term(TA, CA, c[q].x, c[q].y, c[q].z, c[q].C, accA);
-            term(TB, CB, c[q].x, c[q].y, c[q].z, c[q].C, s0 + q < total, accB);
+            const real dx = (real)(int32_t)(TA.ux - c[q].x);
+            const real dy = (real)(int32_t)(TA.uy - c[q].y);
+            const real dz = (DIM == 3) ? (real)(int32_t)(TA.uz - c[q].z) : (real)0;
+            term.sep(dx, dy, dz, CA, c[q].C, true, accA);
+            term.sep(dx + bx, dy + by, dz + bz, CB, c[q].C, s0 + q < total, accB);
         }
     };
     fill(c0);
