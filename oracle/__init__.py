@@ -71,9 +71,9 @@ def lib():
         L.or_analytic.argtypes = [mp, p, p, d, d, d, i64, p, p]
         L.or_sensor_interp.argtypes = [mp, i64, p, p, i64, p, p, p]
         L.or_apply_LT.argtypes = [mp, i64, p, p, p, p, p, p]
-        L.or_adjoint.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, p, p, p]
+        L.or_adjoint.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, i32, p, p, p]
         L.or_misfit.restype = d
-        L.or_misfit.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, p]
+        L.or_misfit.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, i32, p]
         L.or_num_threads.restype = ct.c_int
         _lib = L
     return _lib
@@ -259,8 +259,9 @@ def apply_LT(m: Model, x, lam, v_uniform, mass=1.0, rho=1.0):
     return y
 
 
-def adjoint(m: Model, x0, C0, v_uniform, dt, nsteps, xs, obs, mass=1.0, rho=1.0):
-    """Discrete adjoint of the Euler run: returns (J, grad[alpha_L, alpha_T, D_m], C^N)."""
+def adjoint(m: Model, x0, C0, v_uniform, dt, nsteps, xs, obs, mass=1.0, rho=1.0, integrator=1):
+    """Discrete adjoint of the Euler (1) or predictor-corrector (2, Eqs. 8-9)
+    run: returns (J, grad[alpha_L, alpha_T, D_m], C^N)."""
     x0, C0, xs, obs = _f64(x0), _f64(C0), _f64(xs), _f64(obs)
     n = x0.shape[1]
     vu = _f64(np.pad(np.asarray(v_uniform, float), (0, 3 - len(v_uniform))))
@@ -269,12 +270,13 @@ def adjoint(m: Model, x0, C0, v_uniform, dt, nsteps, xs, obs, mass=1.0, rho=1.0)
     g = np.zeros(3)
     CN = np.zeros(n)
     lib().or_adjoint(ct.byref(m), n, _ptr(x0), _ptr(C0), _ptr(vu), _ptr(m_arr), _ptr(r_arr), dt,
-                     nsteps, xs.shape[1], _ptr(xs), _ptr(obs), _ptr(J), _ptr(g), _ptr(CN))
+                     nsteps, xs.shape[1], _ptr(xs), _ptr(obs), int(integrator), _ptr(J), _ptr(g), _ptr(CN))
     return float(J[0]), g, CN
 
 
-def misfit(m: Model, x0, C0, v_uniform, dt, nsteps, xs, obs=None, mass=1.0, rho=1.0):
-    """Forward Euler run and J = sum_s (C_s - d_s)^2; returns (J, C_s)."""
+def misfit(m: Model, x0, C0, v_uniform, dt, nsteps, xs, obs=None, mass=1.0, rho=1.0, integrator=1):
+    """Forward run (Euler 1, predictor-corrector 2) and J = sum_s (C_s - d_s)^2;
+    returns (J, C_s)."""
     x0, C0, xs = _f64(x0), _f64(C0), _f64(xs)
     ob = None if obs is None else _f64(obs)
     n = x0.shape[1]
@@ -282,7 +284,7 @@ def misfit(m: Model, x0, C0, v_uniform, dt, nsteps, xs, obs=None, mass=1.0, rho=
     m_arr, r_arr = _particle_arrays(n, mass, rho)
     pred = np.zeros(xs.shape[1])
     J = lib().or_misfit(ct.byref(m), n, _ptr(x0), _ptr(C0), _ptr(vu), _ptr(m_arr), _ptr(r_arr), dt,
-                        nsteps, xs.shape[1], _ptr(xs), _ptr(ob), _ptr(pred))
+                        nsteps, xs.shape[1], _ptr(xs), _ptr(ob), int(integrator), _ptr(pred))
     return J, pred
 
 

@@ -773,19 +773,27 @@ void or_apply_LT(const or_model *m, int64_t n, const double *x, const double *vu
 }
 
 /* ------------------------------------------------------------------------- */
-/* Discrete adjoint of the explicit Euler run (uniform velocity):              */
-/*   C^{n+1} = C^n + dt L^n C^n,   J = sum_s (P C^N - d)_s^2                    */
-/*   lam^N = P^T 2 (P C^N - d),   lam^n = lam^{n+1} + dt (L^n)^T lam^{n+1}      */
-/*   dJ/dtheta_k = sum_n dt lam^{n+1} . (dL^n/dtheta_k) C^n                     */
-/* theta = (alpha_L, alpha_T, D_m).  For a uniform tensor the harmonic mean of */
-/* Eq. (5) is h = 2 D (entries with D_ij = 0 stay 0), so dh/dtheta_k =        */
-/* 2 dD/dtheta_k with dD/dalpha_L = v v^T/|v|, dD/dalpha_T = |v| I - v v^T/|v|, */
-/* dD/dD_m = I.  All states are kept in memory (plain reverse sweep).          */
+/* Discrete adjoint of the explicit run (uniform velocity), J = sum_s         */
+/* (P C^N - d)_s^2 with P the sensor interpolation at the final positions:    */
+/*   lam^N = P^T 2 (P C^N - d).                                                */
+/* Euler (integrator 1): C^{n+1} = C^n + dt L1 C^n, L1 = L(x^n):               */
+/*   lam^n = lam^{n+1} + dt L1^T lam^{n+1},                                    */
+/*   dJ/dtheta_k += dt lam^{n+1} . L1_k C^n.                                   */
+/* Predictor-corrector (integrator 2, Eqs. 8-9): C^h = C^n + dt/2 L1 C^n and   */
+/* C^{n+1} = C^n + dt L2 C^h with L2 = L(x^n + dt/2 v), i.e. C^{n+1} =        */
+/* (I + dt L2 + dt^2/2 L2 L1) C^n, so with y = L2^T lam^{n+1}:                 */
+/*   lam^n = lam^{n+1} + dt y + dt^2/2 L1^T y,                                 */
+/*   dJ/dtheta_k += dt lam^{n+1} . L2_k C^h + dt^2/2 y . L1_k C^n.             */
+/* L_k is the operator with the tensor replaced by its derivative: theta =    */
+/* (alpha_L, alpha_T, D_m); for a uniform tensor the harmonic mean of Eq. (5) */
+/* is h = 2 D (entries with D_ij = 0 stay 0), so dh/dtheta_k = 2 dD/dtheta_k  */
+/* with dD/dalpha_L = v v^T/|v|, dD/dalpha_T = |v| I - v v^T/|v|, dD/dD_m = I. */
+/* All states are kept in memory (plain reverse sweep).                        */
 /* ------------------------------------------------------------------------- */
 void or_adjoint(const or_model *m, int64_t n, const double *x0, const double *C0,
                 const double *vu, const double *mass, const double *rho, double dt,
                 int64_t nsteps, int64_t ns, const double *xs, const double *obs,
-                double *J_out, double *grad_out, double *Cfinal_out)
+                int integrator, double *J_out, double *grad_out, double *Cfinal_out)
 {
     int dim = m->dim;
     double *X = (double *)malloc(sizeof(double) * dim * n * (nsteps + 1));
@@ -793,10 +801,24 @@ void or_adjoint(const or_model *m, int64_t n, const double *x0, const double *C0
     double *rhs = (double *)malloc(sizeof(double) * n);
     memcpy(X, x0, sizeof(double) * dim * n);
     memcpy(Cs, C0, sizeof(double) * n);
+    double *Ch = (double *)malloc(sizeof(double) * n);
+    double *xh = (double *)malloc(sizeof(double) * n * dim);
+    /* C^h and x^h of step s: the predictor stage */
+    #define HALF_STAGE(xs_n, C_n)                                                   \
+        do {                                                                        \
+            or_rhs(m, n, xs_n, C_n, NULL, vu, mass, rho, NULL, n, NULL, rhs);       \
+            for (int64_t a = 0; a < n; ++a) Ch[a] = (C_n)[a] + 0.5 * dt * rhs[a];   \
+            advect(m, n, xs_n, NULL, vu, 0.5 * dt, xh);                             \
+        } while (0)
     for (int64_t s = 0; s < nsteps; ++s) {
         const double *xs_n = X + (size_t)s * dim * n;
         const double *C_n = Cs + (size_t)s * n;
-        or_rhs(m, n, xs_n, C_n, NULL, vu, mass, rho, NULL, n, NULL, rhs);
+        if (integrator == 2) {
+            HALF_STAGE(xs_n, C_n);
+            or_rhs(m, n, xh, Ch, NULL, vu, mass, rho, NULL, n, NULL, rhs);
+        } else {
+            or_rhs(m, n, xs_n, C_n, NULL, vu, mass, rho, NULL, n, NULL, rhs);
+        }
         for (int64_t a = 0; a < n; ++a) Cs[(size_t)(s + 1) * n + a] = C_n[a] + dt * rhs[a];
         advect(m, n, xs_n, NULL, vu, dt, X + (size_t)(s + 1) * dim * n);
     }
@@ -829,35 +851,54 @@ void or_adjoint(const or_model *m, int64_t n, const double *x0, const double *C0
     or_dispersion(dim, m->alpha_L, m->alpha_T, m->D_m, vu, D);
     or_harmonic(dim, D, D, h);
     double grad[3] = {0.0, 0.0, 0.0};
+    double *z = (double *)malloc(sizeof(double) * n);
     for (int64_t s = nsteps - 1; s >= 0; --s) {
         const double *xs_n = X + (size_t)s * dim * n;
         const double *C_n = Cs + (size_t)s * n;
-        for (int k = 0; k < 3; ++k) {
-            or_rhs(m, n, xs_n, C_n, NULL, vu, mass, rho, dD[k], n, NULL, rhs);
-            double acc = 0.0;
-            for (int64_t a = 0; a < n; ++a) acc += lam[a] * rhs[a];
-            grad[k] += dt * acc;
+        if (integrator == 2) {
+            HALF_STAGE(xs_n, C_n);
+            apply_LT(m, n, xh, mass, rho, h, lam, y);  /* y = L2^T lam */
+            for (int k = 0; k < 3; ++k) {
+                double acc = 0.0;
+                or_rhs(m, n, xh, Ch, NULL, vu, mass, rho, dD[k], n, NULL, rhs);
+                for (int64_t a = 0; a < n; ++a) acc += dt * lam[a] * rhs[a];
+                or_rhs(m, n, xs_n, C_n, NULL, vu, mass, rho, dD[k], n, NULL, rhs);
+                for (int64_t a = 0; a < n; ++a) acc += 0.5 * dt * dt * y[a] * rhs[a];
+                grad[k] += acc;
+            }
+            apply_LT(m, n, xs_n, mass, rho, h, y, z);   /* z = L1^T y */
+            for (int64_t a = 0; a < n; ++a) lam[a] += dt * y[a] + 0.5 * dt * dt * z[a];
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                or_rhs(m, n, xs_n, C_n, NULL, vu, mass, rho, dD[k], n, NULL, rhs);
+                double acc = 0.0;
+                for (int64_t a = 0; a < n; ++a) acc += lam[a] * rhs[a];
+                grad[k] += dt * acc;
+            }
+            apply_LT(m, n, xs_n, mass, rho, h, lam, y);
+            for (int64_t a = 0; a < n; ++a) lam[a] += dt * y[a];
         }
-        apply_LT(m, n, xs_n, mass, rho, h, lam, y);
-        for (int64_t a = 0; a < n; ++a) lam[a] += dt * y[a];
     }
+    #undef HALF_STAGE
     *J_out = J;
     for (int k = 0; k < 3; ++k) grad_out[k] = grad[k];
     if (Cfinal_out) memcpy(Cfinal_out, CN, sizeof(double) * n);
-    free(X); free(Cs); free(rhs); free(pred); free(g); free(lam); free(y);
+    free(X); free(Cs); free(rhs); free(pred); free(g); free(lam); free(y); free(z); free(Ch); free(xh);
 }
 
-/* Forward run followed by the misfit J only (for finite differences). */
+/* Forward run (Euler or predictor-corrector) followed by the misfit J only
+ * (for finite differences). */
 double or_misfit(const or_model *m, int64_t n, const double *x0, const double *C0,
                  const double *vu, const double *mass, const double *rho, double dt,
-                 int64_t nsteps, int64_t ns, const double *xs, const double *obs, double *pred_out)
+                 int64_t nsteps, int64_t ns, const double *xs, const double *obs, int integrator,
+                 double *pred_out)
 {
     int dim = m->dim;
     double *x = (double *)malloc(sizeof(double) * dim * n);
     double *C = (double *)malloc(sizeof(double) * n);
     memcpy(x, x0, sizeof(double) * dim * n);
     memcpy(C, C0, sizeof(double) * n);
-    or_run(m, n, x, C, NULL, vu, mass, rho, dt, nsteps, 1, NULL);
+    or_run(m, n, x, C, NULL, vu, mass, rho, dt, nsteps, integrator, NULL);
     double *pred = (double *)malloc(sizeof(double) * (ns > 0 ? ns : 1));
     or_sensor_interp(m, n, x, C, ns, xs, pred, NULL);
     double J = 0.0;
