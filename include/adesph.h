@@ -171,9 +171,12 @@ int ade_sensor_interp(ade_ctx *ctx, const double *d_xs, int32_t n_sensors, void 
 int ade_adjoint_workspace_bytes(const ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every,
                                 int32_t n_sensors, size_t *bytes);
 
-/* Misfit and gradient of J = sum_s (C_s(T) - d_s)^2 after nsteps Euler steps
- * from the current state, w.r.t. (alpha_L, alpha_T, D_m) of plume 0, by a
- * discrete adjoint with a checkpoint every ckpt_every steps and recompute.
+/* Misfit and gradient of J = sum_s (C_s(T) - d_s)^2 after nsteps steps of the
+ * context's integrator (explicit Euler, or the predictor-corrector of Eqs.
+ * 8-9: its step is C <- (I + dt L + dt^2/2 L^2) C for a uniform flow, and the
+ * adjoint applies the same two stages to lambda) from the current state,
+ * w.r.t. (alpha_L, alpha_T, D_m) of plume 0, by a discrete adjoint with a
+ * checkpoint every ckpt_every steps and recompute.
  * d_obs holds S reals.  On return the context holds the state at step
  * nsteps.  h_grad receives 3 doubles; synchronises the stream. */
 int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *d_xs,

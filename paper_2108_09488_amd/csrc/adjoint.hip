@@ -7,7 +7,17 @@
 //     dJ/dtheta_k = sum_n dt lambda^{n+1} . (dL^n/dtheta_k) C^n.
 // For equal particle volumes and a uniform tensor the pair weights are
 // symmetric (w_ab = w_ba), so (L^n)^T = L^n: the adjoint kernel applies the
-// same pair sum to lambda.  L depends on theta only through D (Eq. 3), which
+// same pair sum to lambda.
+// The predictor-corrector step (Eqs. 8-9) is C^{n+1} = (I + dt L + dt^2/2 L^2)
+// C^n: a uniform flow moves every particle by the same displacement, so the
+// operator of the corrector stage is that of the predictor.  Its adjoint is
+// the same two stages applied to lambda,
+//     mu = lambda + dt/2 L lambda,  lambda^n = lambda + dt L mu,
+// and with C^h = C^n + dt/2 L C^n the gradient gains
+//     dt [lambda . L_k C^h + (mu - lambda) . L_k C^n]
+// (= dt lambda . L_k C^n + dt^2/2 (lambda . L_k L C^n + L lambda . L_k C^n)).
+// kAdjHalf forms mu, C^h and the second term; kAdjFull forms lambda^n and
+// the first.  L depends on theta only through D (Eq. 3), which
 // is linear in theta: dD/dalpha_L = v v^T/|v|, dD/dalpha_T = |v| I - v v^T/|v|,
 // dD/dD_m = I.  With p = (x_ab . v)^2 / (|v|^2 r^2) the factor
 // A = Gamma x^T M x / r^2 - tr M of the pair term becomes
@@ -161,13 +171,22 @@ struct AdjConst {
     double speed;    // |v|
 };
 
-template <int DIM, typename real, int KERN>
+// kAdjEuler: out = lambda^n (id order) = lam + dt L lam, gradient dt lam . L_k X.
+// kAdjHalf:  out = mu (sorted) = lam + dt/2 L lam, xh_out = C^h (sorted) = X +
+//            dt/2 L X, gradient dt (mu - lam) . L_k X.
+// kAdjFull:  out = lambda^n (id order) = lam + dt L u (u = mu), gradient
+//            dt lam . L_k X (X = C^h).
+enum AdjMode { kAdjEuler = 0, kAdjHalf = 1, kAdjFull = 2 };
+
+template <int DIM, typename real, int KERN, int AMODE>
 __global__ __launch_bounds__(kTile) void k_adjoint(const PlumeDev* __restrict__ plumes,
                                                   const TileDev* __restrict__ tiles, StateArrays S,
                                                   const uint32_t* __restrict__ cs,
+                                                  const real* __restrict__ u_s,
                                                   const real* __restrict__ lam_s,
-                                                  real* __restrict__ lam_out, AdjConst ac,
-                                                  double* __restrict__ gpart) {
+                                                  const real* __restrict__ X,
+                                                  real* __restrict__ lam_out, real* __restrict__ xh_out,
+                                                  AdjConst ac, double* __restrict__ gpart) {
     __shared__ double lds[kTile / kWave];
     const TileDev t = tiles[blockIdx.x];
     const PlumeDev P = plumes[t.plume];
@@ -176,16 +195,18 @@ __global__ __launch_bounds__(kTile) void k_adjoint(const PlumeDev* __restrict__ 
     const uint32_t* px = S.pos[0];
     const uint32_t* py = S.pos[1];
     const uint32_t* pz = S.pos[2];
-    const real* C = static_cast<const real*>(S.C);
+    const real* C = X;
     const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
     const real a0 = (real)P.a0, a1 = (real)P.a1;
     const real gam = (real)(DIM + 2), spd = (real)ac.speed;
     const real vx = (real)P.ehat[0], vy = (real)P.ehat[1], vz = (real)P.ehat[2];
-    real al = 0, g1 = 0, g2 = 0, g3 = 0, li = 0;
+    real al = 0, cl = 0, g1 = 0, g2 = 0, g3 = 0, li = 0;
+    double mult = 0.0;  // the gradient's multiplier of this particle
     if (active) {
         const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
         const real Ci = C[i];
         li = lam_s[i];
+        const real ui = u_s[i];
         const int span = 2 * P.R + 1, noff = (DIM == 3) ? span * span : span;
         for (int j = 0; j < noff; ++j) {
             const RowRanges r = row_ranges<DIM>(P, cs, T, j, span);
@@ -216,7 +237,8 @@ __global__ __launch_bounds__(kTile) void k_adjoint(const PlumeDev* __restrict__ 
                         const real p = xv * xv * ir2;
                         const real A = fmar(a1, p, a0);
                         const real dCf = (Ci - C[b]) * f;
-                        al = fmar(A * f, li - lam_s[b], al);
+                        al = fmar(A * f, ui - u_s[b], al);
+                        if (AMODE == kAdjHalf) cl = fmar(A, dCf, cl);
                         g1 = fmar(spd * (gam * p - (real)1), dCf, g1);
                         g2 = fmar(spd * (gam * ((real)1 - p) - (real)(DIM - 1)), dCf, g2);
                         g3 += (gam - (real)DIM) * dCf;
@@ -224,14 +246,22 @@ __global__ __launch_bounds__(kTile) void k_adjoint(const PlumeDev* __restrict__ 
                 }
             }
         }
-        const real s = (real)(P.dt * P.vphi);
-        lam_out[S.id[i]] = fmar(s, al, li);
+        const double sd = P.dt * P.vphi;
+        if (AMODE == kAdjHalf) {
+            const real h = (real)(0.5 * sd);
+            lam_out[i] = fmar(h, al, li);
+            xh_out[i] = fmar(h, cl, Ci);
+            mult = 0.5 * sd * (double)al;  // mu - lambda
+        } else {
+            lam_out[S.id[i]] = fmar((real)sd, al, li);
+            mult = (double)li;
+        }
     }
     // per-workgroup gradient partials, accumulated over the steps in FP64
     const double s = P.dt * P.vphi;
-    const double c1 = block_sum(active ? s * (double)li * (double)g1 : 0.0, lds);
-    const double c2 = block_sum(active ? s * (double)li * (double)g2 : 0.0, lds);
-    const double c3 = block_sum(active ? s * (double)li * (double)g3 : 0.0, lds);
+    const double c1 = block_sum(active ? s * mult * (double)g1 : 0.0, lds);
+    const double c2 = block_sum(active ? s * mult * (double)g2 : 0.0, lds);
+    const double c3 = block_sum(active ? s * mult * (double)g3 : 0.0, lds);
     if (threadIdx.x == 0) {
         gpart[3 * blockIdx.x + 0] += c1;
         gpart[3 * blockIdx.x + 1] += c2;
@@ -280,6 +310,8 @@ struct AdjLayout {
     std::vector<Snap> seg;  // states of one segment
     void* lam[2];
     void* lam_s;
+    void* mu_s;  // predictor-corrector: mu and C^h of the step (cell order)
+    void* ch_s;
     void* pred;
     void* den;
     void* rw;
@@ -323,6 +355,9 @@ void adj_layout(const ade_ctx* c, int64_t nsteps, int32_t K, int32_t ns, char* b
     L.lam[0] = take(N * rb);
     L.lam[1] = take(N * rb);
     L.lam_s = take(N * rb);
+    const bool pc = pl.integrator == ADE_PC;
+    L.mu_s = pc ? take(N * rb) : nullptr;
+    L.ch_s = pc ? take(N * rb) : nullptr;
     L.pred = take((size_t)ns * rb);
     L.den = take((size_t)ns * rb);
     L.rw = take((size_t)ns * rb);
@@ -418,7 +453,6 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     if (rc) return rc;
     if (!d_obs || !d_ws || !h_J || !h_grad) return fail(ADE_EINVAL, "null argument");
     if (nsteps < 1 || K < 1) return fail(ADE_EINVAL, "nsteps and ckpt_every must be positive");
-    if (c->plan.integrator != ADE_EULER) return fail(ADE_EINVAL, "the adjoint is implemented for ADE_EULER");
     if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
     AdjLayout L;
     adj_layout(c, nsteps, K, ns, nullptr, L);
@@ -486,11 +520,22 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
             else
                 hipLaunchKernelGGL((k_gather_sorted<double>), g, b, 0, st, sn.id, (const double*)L.lam[li], N,
                                    (double*)L.lam_s);
-#define CALL(D, R, KK)                                                                            \
-    hipLaunchKernelGGL((k_adjoint<D, R, KK>), dim3(pl.ntiles), dim3(kTile), 0, st, c->plumes, c->tiles, \
-                       Sa, sn.cs, (const R*)L.lam_s, (R*)L.lam[1 - li], ac, L.gpart)
-            ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, CALL);
+#define LAUNCH(D, R, KK, MODE, U, X, OUT, XH)                                                          \
+    hipLaunchKernelGGL((k_adjoint<D, R, KK, MODE>), dim3(pl.ntiles), dim3(kTile), 0, st, c->plumes, c->tiles, \
+                       Sa, sn.cs, (const R*)(U), (const R*)L.lam_s, (const R*)(X), (R*)(OUT), (R*)(XH), ac,     \
+                       L.gpart)
+            if (pl.integrator == ADE_PC) {
+#define CALL(D, R, KK)                                                               \
+    LAUNCH(D, R, KK, kAdjHalf, L.lam_s, sn.C, L.mu_s, L.ch_s);                        \
+    LAUNCH(D, R, KK, kAdjFull, L.mu_s, L.ch_s, L.lam[1 - li], nullptr)
+                ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, CALL);
 #undef CALL
+            } else {
+#define CALL(D, R, KK) LAUNCH(D, R, KK, kAdjEuler, L.lam_s, sn.C, L.lam[1 - li], nullptr)
+                ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, CALL);
+#undef CALL
+            }
+#undef LAUNCH
             HIPCHK(hipGetLastError());
             li = 1 - li;
         }

@@ -16,11 +16,11 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "adjoint_256.json")
 
 
-def _ctx(spec):
+def _ctx(spec, integrator=1):
     from paper_2108_09488_amd.context import Context, params_from_spec
-    print(f"[case] {spec.name} n_side={spec.n_side} rb={spec.real_bytes} aL={spec.alpha_L} aT={spec.alpha_T}",
-          flush=True)
-    c = Context([params_from_spec(spec)], [spec.n])
+    print(f"[case] {spec.name} n_side={spec.n_side} rb={spec.real_bytes} aL={spec.alpha_L} aT={spec.alpha_T} "
+          f"integ={integrator}", flush=True)
+    c = Context([params_from_spec(spec, integrator=integrator)], [spec.n])
     x = spec.positions()
     C = spec.concentration(x)
     if spec.real_bytes == 4:
@@ -41,7 +41,7 @@ def test_sensor_interpolation(rb):
     c.close()
 
 
-def _small(rb=4, n_side=64, steps=60, ns=64):
+def _small(rb=4, n_side=64, steps=60, ns=64, integrator=1):
     # dt v is a multiple of 2^-32 (dt = 2^-12, v = (0.75, 0.5)): the library's
     # fixed-point displacement per step is then exact, so positions relative to
     # the fixed sensors agree with the oracle's to the last bit
@@ -53,19 +53,25 @@ def _small(rb=4, n_side=64, steps=60, ns=64):
         C0 = C0.astype(np.float32).astype(np.float64)
     xs = I.sensors(ns, [0.05, 0.25], [0.55, 0.75])
     truth = O.model(2, 4, spec.H, alpha_L=2e-2, alpha_T=2e-3, D_m=1e-6)
-    _, obs = O.misfit(truth, x, C0, spec.velocity(), spec.dt, steps, xs, None, mass=spec.mass, rho=spec.rho0)
+    _, obs = O.misfit(truth, x, C0, spec.velocity(), spec.dt, steps, xs, None, mass=spec.mass, rho=spec.rho0,
+                      integrator=integrator)
     if rb == 4:
         obs = obs.astype(np.float32).astype(np.float64)
     return spec, x, C0, xs, obs
 
 
-@pytest.mark.parametrize("rb", [4, 8])
-def test_adjoint_matches_oracle(rb):
-    spec, x, C0, xs, obs = _small(rb)
-    c, _, _ = _ctx(spec)
+@pytest.mark.parametrize("rb,integrator", [(4, 1), (8, 1), (4, 2), (8, 2)])
+def test_adjoint_matches_oracle(rb, integrator):
+    """J and the gradient of the explicit Euler run, and of the
+    predictor-corrector run (Eqs. 8-9), against the oracle's discrete adjoint."""
+    spec, x, C0, xs, obs = _small(rb, integrator=integrator)
+    c, _, _ = _ctx(spec, integrator=integrator)
     J, g = c.adjoint(spec.steps, 7, torch.from_numpy(xs), torch.from_numpy(obs))
-    Jo, go, _ = O.adjoint(O.model_from_spec(spec), x, C0, spec.velocity(), spec.dt, spec.steps, xs, obs,
-                          mass=spec.mass, rho=spec.rho0)
+    Jo, go, Co = O.adjoint(O.model_from_spec(spec), x, C0, spec.velocity(), spec.dt, spec.steps, xs, obs,
+                           mass=spec.mass, rho=spec.rho0, integrator=integrator)
+    # the context is left at step nsteps of its own integrator
+    Cg = c.read_C().double().cpu().numpy()
+    assert np.linalg.norm(Cg - Co) / np.linalg.norm(Co) < (1e-12 if rb == 8 else 1e-5)
     tol = 1e-10 if rb == 8 else 1e-4
     assert J == pytest.approx(Jo, rel=tol)
     assert np.allclose(g, go, rtol=tol, atol=tol * np.abs(go).max())
