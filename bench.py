@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 FLOPS_PER_INTERACTION = {2: 29, 3: 39}
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published vector FP32 (packed FMA)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.md")
-PAIR_SOURCES = ["kernels_pair.hip", "ade_geom.h", "ade_device.h", "ade_internal.h"]
+PAIR_SOURCES = ["kernels_pair.hip", "ade_walk.h", "ade_geom.h", "ade_device.h", "ade_internal.h"]
 PEAK_FP32_NONPACKED_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA)
 
 
@@ -167,6 +167,7 @@ def fwd_adjoint(device):
     c.close()
     c = Context([params_from_spec(guess)], [guess.n], device=device)
     c.init(torch.from_numpy(x), C0).build()
+    tuning = c.autotune(reps=3)
     off, _ = c.neighbours()
     inter = int(off[-1].item())
     c.adjoint(guess.steps, 50, xs, obs)  # warm-up
@@ -183,7 +184,7 @@ def fwd_adjoint(device):
     _sync()
     wall_fwd = time.perf_counter() - t0
     c.close()
-    return {"particles": guess.n, "steps": guess.steps, "interactions_per_step": inter,
+    return {"particles": guess.n, "steps": guess.steps, "interactions_per_step": inter, "tuning": tuning,
             "ms_fwd_adjoint": 1e3 * wall_adj, "ms_fwd": 1e3 * wall_fwd,
             "interactions_per_s": inter * guess.steps / wall_adj,
             "fwd_interactions_per_s": inter * guess.steps / wall_fwd,

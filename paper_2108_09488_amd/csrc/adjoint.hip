@@ -34,7 +34,7 @@
 #include <algorithm>
 #include <cmath>
 
-#include "ade_geom.h"
+#include "ade_walk.h"
 #include "ctx.h"
 
 namespace ade {
@@ -159,12 +159,36 @@ __global__ __launch_bounds__(256) void k_sensor_seed(const PlumeDev* __restrict_
 // ---------------------------------------------------------------------------
 // adjoint step
 // ---------------------------------------------------------------------------
+// The adjoint passes walk the candidate lists of the forward kernels (cell
+// rows in LDS, one lane per target, batches of records in flight).  A
+// candidate carries its position and the pass's two values: X (the state in
+// the gradient terms) and u (the vector the operator is applied to).  In 2D
+// FP32 they travel as one 16-byte record (x, y, X, u) written just before
+// the pass; otherwise they are read from the arrays.
 template <typename real>
-__global__ __launch_bounds__(256) void k_gather_sorted(const uint32_t* __restrict__ id,
-                                                      const real* __restrict__ src, uint32_t N,
-                                                      real* __restrict__ dst) {
+struct ACand {
+    uint32_t x, y, z;
+    real X, u;
+};
+
+template <int DIM, typename real>
+struct ARec {
+    static constexpr bool kPacked = DIM == 2 && sizeof(real) == 4;
+};
+
+__device__ __forceinline__ uint32_t fbits(float v) { return __builtin_bit_cast(uint32_t, v); }
+__device__ __forceinline__ float bitsf(uint32_t v) { return __builtin_bit_cast(float, v); }
+
+// lambda from id order into cell order (and the records (x, y, X, lambda))
+template <int DIM, typename real>
+__global__ __launch_bounds__(256) void k_adj_gather(StateArrays S, const real* __restrict__ lam_id,
+                                                   const real* __restrict__ X, uint32_t N,
+                                                   real* __restrict__ lam_s, uint4* __restrict__ arec) {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < N) dst[i] = src[id[i]];
+    if (i >= N) return;
+    const real l = lam_id[S.id[i]];
+    lam_s[i] = l;
+    if constexpr (ARec<DIM, real>::kPacked) arec[i] = make_uint4(S.pos[0][i], S.pos[1][i], fbits(X[i]), fbits(l));
 }
 
 struct AdjConst {
@@ -172,85 +196,107 @@ struct AdjConst {
 };
 
 // kAdjEuler: out = lambda^n (id order) = lam + dt L lam, gradient dt lam . L_k X.
-// kAdjHalf:  out = mu (sorted) = lam + dt/2 L lam, xh_out = C^h (sorted) = X +
-//            dt/2 L X, gradient dt (mu - lam) . L_k X.
+// kAdjHalf:  out = mu (cell order) = lam + dt/2 L lam, xh_out = C^h (cell
+//            order) = X + dt/2 L X, arec_out = their records, gradient
+//            dt (mu - lam) . L_k X.
 // kAdjFull:  out = lambda^n (id order) = lam + dt L u (u = mu), gradient
 //            dt lam . L_k X (X = C^h).
+// A workgroup takes blockDim.x consecutive targets of a tile; its gradient
+// partials go to gpart[3 * blockIdx.x ..].
 enum AdjMode { kAdjEuler = 0, kAdjHalf = 1, kAdjFull = 2 };
 
 template <int DIM, typename real, int KERN, int AMODE>
-__global__ __launch_bounds__(kTile) void k_adjoint(const PlumeDev* __restrict__ plumes,
-                                                  const TileDev* __restrict__ tiles, StateArrays S,
-                                                  const uint32_t* __restrict__ cs,
-                                                  const real* __restrict__ u_s,
-                                                  const real* __restrict__ lam_s,
-                                                  const real* __restrict__ X,
-                                                  real* __restrict__ lam_out, real* __restrict__ xh_out,
-                                                  AdjConst ac, double* __restrict__ gpart) {
+__global__ __launch_bounds__(256) void k_adjoint(const PlumeDev* __restrict__ plumes,
+                                                const TileDev* __restrict__ tiles, StateArrays S,
+                                                const uint32_t* __restrict__ cs,
+                                                const real* __restrict__ u_s,
+                                                const real* __restrict__ lam_s,
+                                                const real* __restrict__ X,
+                                                const uint4* __restrict__ arec,
+                                                real* __restrict__ lam_out, real* __restrict__ xh_out,
+                                                uint4* __restrict__ arec_out, AdjConst ac,
+                                                double* __restrict__ gpart) {
+    extern __shared__ uint2 lds_list[];
     __shared__ double lds[kTile / kWave];
-    const TileDev t = tiles[blockIdx.x];
+    constexpr bool kPacked = ARec<DIM, real>::kPacked;
+    const uint32_t tpb = blockDim.x, subs = kTile / tpb;
+    const TileDev t = tiles[blockIdx.x / subs];
+    const uint32_t i0 = t.start + (blockIdx.x % subs) * tpb;
+    if (i0 >= t.end) return;  // whole workgroup: ragged last tile
+    const uint32_t i1 = min(t.end, i0 + tpb);
     const PlumeDev P = plumes[t.plume];
-    const uint32_t i = t.start + threadIdx.x;
-    const bool active = i < t.end;
-    const uint32_t* px = S.pos[0];
-    const uint32_t* py = S.pos[1];
-    const uint32_t* pz = S.pos[2];
-    const real* C = X;
+    const bool active = i0 + threadIdx.x < i1;
+    const uint32_t i = active ? i0 + threadIdx.x : i0;
+    const uint32_t* __restrict__ px = S.pos[0];
+    const uint32_t* __restrict__ py = S.pos[1];
+    const uint32_t* __restrict__ pz = S.pos[2];
+    const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
+    const real Xi = X[i], ui = u_s[i], li = lam_s[i];
     const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
     const real a0 = (real)P.a0, a1 = (real)P.a1;
     const real gam = (real)(DIM + 2), spd = (real)ac.speed;
     const real vx = (real)P.ehat[0], vy = (real)P.ehat[1], vz = (real)P.ehat[2];
-    real al = 0, cl = 0, g1 = 0, g2 = 0, g3 = 0, li = 0;
+
+    uint2* list = lds_list + threadIdx.x;
+    uint32_t total = 0;
+    if (active) total = build_list<DIM, 1>(P, cs, T, list, tpb);
+    else list[0] = make_uint2(kListEndStart, kListEndEnd);
+
+    real al = 0, cl = 0, g1 = 0, g2 = 0, g3 = 0;
+    auto fetch = [&](uint32_t k) {
+        if constexpr (kPacked) {
+            const uint4 r = *reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(arec) + k);
+            return ACand<real>{r.x, r.y, 0u, (real)bitsf(r.z), (real)bitsf(r.w)};
+        } else {
+            k /= kRecBytes;
+            return ACand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, X[k], u_s[k]};
+        }
+    };
+    // branch-free: outside the support (and at r2 = 0, where 1/r is infinite)
+    // f and p are replaced by 0, so every term is exactly 0
+    auto eval = [&](const ACand<real>& c, bool keep) {
+        const real dx = (real)(int32_t)(T.ux - c.x);
+        const real dy = (real)(int32_t)(T.uy - c.y);
+        const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - c.z) : (real)0;
+        real r2 = dx * dx;
+        r2 = fmar(dy, dy, r2);
+        if (DIM == 3) r2 = fmar(dz, dz, r2);
+        const bool in = keep && r2 > (real)0 && r2 <= H2;
+        const real rinv = rsqrt_r(r2);
+        const real q = r2 * rinv * invHu;
+        real omq = (real)1 - q;
+        omq = omq > (real)0 ? omq : (real)0;
+        real f;
+        if (KERN == 4) {
+            const real o2 = omq * omq;
+            f = o2 * o2 * omq * fmar((real)5, q, (real)1);
+        } else {
+            f = omq * omq * omq;
+        }
+        // Gamma x^T D x / r^2 - tr D = a0 + a1 p, p = (e . x / r)^2
+        const real xv = fmar(dz, vz, fmar(dy, vy, dx * vx));
+        real p = xv * xv * (rinv * rinv);
+        f = in ? f : (real)0;
+        p = in ? p : (real)0;
+        const real A = fmar(a1, p, a0);
+        const real dCf = (Xi - c.X) * f;
+        al = fmar(A * f, ui - c.u, al);
+        if (AMODE == kAdjHalf) cl = fmar(A, dCf, cl);
+        g1 = fmar(spd * fmar(gam, p, (real)-1), dCf, g1);
+        g2 = fmar(spd * fmar(-gam, p, gam - (real)(DIM - 1)), dCf, g2);
+        g3 = fmar(gam - (real)DIM, dCf, g3);
+    };
+    walk_stream<4>(list, tpb, total, i, fetch, eval);
+
     double mult = 0.0;  // the gradient's multiplier of this particle
     if (active) {
-        const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
-        const real Ci = C[i];
-        li = lam_s[i];
-        const real ui = u_s[i];
-        const int span = 2 * P.R + 1, noff = (DIM == 3) ? span * span : span;
-        for (int j = 0; j < noff; ++j) {
-            const RowRanges r = row_ranges<DIM>(P, cs, T, j, span);
-            for (int part = 0; part < 2; ++part) {
-                const uint32_t b0 = part ? r.s1 : r.s0, b1 = part ? r.e1 : r.e0;
-                for (uint32_t b = b0; b < b1; ++b) {
-                    const real dx = (real)(int32_t)(T.ux - px[b]);
-                    const real dy = (real)(int32_t)(T.uy - py[b]);
-                    const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - pz[b]) : (real)0;
-                    real r2 = dx * dx;
-                    r2 = fmar(dy, dy, r2);
-                    if (DIM == 3) r2 = fmar(dz, dz, r2);
-                    if (r2 > (real)0 && r2 <= H2) {
-                        const real rinv = (real)1 / sqrt(r2);
-                        const real q = r2 * rinv * invHu;
-                        real omq = (real)1 - q;
-                        omq = omq > (real)0 ? omq : (real)0;
-                        real f;
-                        if (KERN == 4) {
-                            const real o2 = omq * omq;
-                            f = o2 * o2 * omq * fmar((real)5, q, (real)1);
-                        } else {
-                            f = omq * omq * omq;
-                        }
-                        // Gamma x^T D x / r^2 - tr D = a0 + a1 p, p = (e . x / r)^2
-                        const real ir2 = rinv * rinv;
-                        const real xv = dx * vx + dy * vy + dz * vz;
-                        const real p = xv * xv * ir2;
-                        const real A = fmar(a1, p, a0);
-                        const real dCf = (Ci - C[b]) * f;
-                        al = fmar(A * f, ui - u_s[b], al);
-                        if (AMODE == kAdjHalf) cl = fmar(A, dCf, cl);
-                        g1 = fmar(spd * (gam * p - (real)1), dCf, g1);
-                        g2 = fmar(spd * (gam * ((real)1 - p) - (real)(DIM - 1)), dCf, g2);
-                        g3 += (gam - (real)DIM) * dCf;
-                    }
-                }
-            }
-        }
         const double sd = P.dt * P.vphi;
         if (AMODE == kAdjHalf) {
             const real h = (real)(0.5 * sd);
-            lam_out[i] = fmar(h, al, li);
-            xh_out[i] = fmar(h, cl, Ci);
+            const real mu = fmar(h, al, li), xh = fmar(h, cl, Xi);
+            lam_out[i] = mu;
+            xh_out[i] = xh;
+            if constexpr (kPacked) arec_out[i] = make_uint4(T.ux, T.uy, fbits(xh), fbits(mu));
             mult = 0.5 * sd * (double)al;  // mu - lambda
         } else {
             lam_out[S.id[i]] = fmar((real)sd, al, li);
@@ -280,6 +326,37 @@ __global__ __launch_bounds__(256) void k_grad_reduce(const double* __restrict__ 
     }
 }
 
+// copy of a state snapshot: positions, C (as 32-bit words), ids, records,
+// the cell table and the step counter
+struct SnapCopy {
+    uint32_t* dpos[3];
+    const uint32_t* spos[3];
+    uint32_t* dC;
+    const uint32_t* sC;
+    uint32_t* did;
+    const uint32_t* sid;
+    uint4* drec;
+    const uint4* srec;
+    uint32_t* dcs;
+    const uint32_t* scs;
+    int64_t* dstep;
+    const int64_t* sstep;
+    uint32_t n, ncs, cwords;
+};
+
+__global__ __launch_bounds__(256) void k_copy_snap(SnapCopy a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *a.dstep = *a.sstep;
+    if (i < a.n * a.cwords) a.dC[i] = a.sC[i];
+    if (i < a.ncs) a.dcs[i] = a.scs[i];
+    if (i >= a.n) return;
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+        if (a.dpos[d]) a.dpos[d][i] = a.spos[d][i];
+    a.did[i] = a.sid[i];
+    if (a.drec) a.drec[i] = a.srec[i];
+}
+
 namespace {
 
 #define ADE_DISPATCH3(dim, rb, kern, CALL)                              \
@@ -304,6 +381,16 @@ struct Snap {
     int64_t* step;
 };
 
+constexpr uint32_t kAdjMaxSubs = 4;  // workgroups per tile of the adjoint passes (64 threads)
+
+// threads per workgroup of the adjoint passes: the largest of 256, 128, 64
+// whose candidate lists fit in 64 KiB of LDS
+uint32_t adj_block(const Plan& pl) {
+    for (uint32_t b = 256; b > 64; b /= 2)
+        if ((size_t)b * (size_t)pl.list_cap * 8u <= kPairLdsMax) return b;
+    return 64;
+}
+
 struct AdjLayout {
     size_t bytes = 0;
     std::vector<Snap> ck;   // checkpoints (every K steps, plus the final state)
@@ -312,6 +399,8 @@ struct AdjLayout {
     void* lam_s;
     void* mu_s;  // predictor-corrector: mu and C^h of the step (cell order)
     void* ch_s;
+    uint4* arec;   // 2D FP32: candidate records of the pass (x, y, X, u)
+    uint4* arec2;  // predictor-corrector: those of the second pass
     void* pred;
     void* den;
     void* rw;
@@ -356,28 +445,47 @@ void adj_layout(const ade_ctx* c, int64_t nsteps, int32_t K, int32_t ns, char* b
     L.lam[1] = take(N * rb);
     L.lam_s = take(N * rb);
     const bool pc = pl.integrator == ADE_PC;
+    const bool packed = pl.dim == 2 && pl.real_bytes == 4;
     L.mu_s = pc ? take(N * rb) : nullptr;
     L.ch_s = pc ? take(N * rb) : nullptr;
+    L.arec = packed ? (uint4*)take(N * 16) : nullptr;
+    L.arec2 = (packed && pc) ? (uint4*)take(N * 16) : nullptr;
     L.pred = take((size_t)ns * rb);
     L.den = take((size_t)ns * rb);
     L.rw = take((size_t)ns * rb);
     L.J = (double*)take(8);
-    L.gpart = (double*)take((size_t)pl.ntiles * 3 * 8);
+    L.gpart = (double*)take((size_t)pl.ntiles * kAdjMaxSubs * 3 * 8);
     L.grad = (double*)take(3 * 8);
     L.bytes = off + 256;
 }
 
+// one launch per snapshot (the arrays are small for the adjoint's problem
+// sizes, so separate copies would be launch-bound)
 int copy_state(const ade_ctx* c, const Snap& dst, const Snap& src) {
     const Plan& pl = c->plan;
-    const size_t N = (size_t)pl.N;
-    hipStream_t st = c->stream;
-    for (int d = 0; d < pl.dim; ++d)
-        HIPCHK(hipMemcpyAsync(dst.pos[d], src.pos[d], N * 4, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(dst.C, src.C, N * pl.real_bytes, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(dst.id, src.id, N * 4, hipMemcpyDeviceToDevice, st));
-    if (dst.rec && src.rec) HIPCHK(hipMemcpyAsync(dst.rec, src.rec, N * 16, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(dst.cs, src.cs, (pl.ncell + 1) * 4, hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(dst.step, src.step, 8, hipMemcpyDeviceToDevice, st));
+    const uint32_t N = (uint32_t)pl.N, nc = (uint32_t)pl.ncell + 1;
+    const uint32_t words = (uint32_t)pl.real_bytes / 4;
+    SnapCopy a;
+    for (int d = 0; d < 3; ++d) {
+        a.dpos[d] = (d < pl.dim) ? dst.pos[d] : nullptr;
+        a.spos[d] = (d < pl.dim) ? src.pos[d] : nullptr;
+    }
+    a.dC = static_cast<uint32_t*>(dst.C);
+    a.sC = static_cast<const uint32_t*>(src.C);
+    a.did = dst.id;
+    a.sid = src.id;
+    a.drec = (dst.rec && src.rec) ? dst.rec : nullptr;
+    a.srec = src.rec;
+    a.dcs = dst.cs;
+    a.scs = src.cs;
+    a.dstep = dst.step;
+    a.sstep = src.step;
+    a.n = N;
+    a.ncs = nc;
+    a.cwords = words;
+    const uint32_t items = std::max(N * words, nc);
+    hipLaunchKernelGGL(k_copy_snap, dim3((items + 255) / 256), dim3(256), 0, c->stream, a);
+    HIPCHK(hipGetLastError());
     return ADE_OK;
 }
 
@@ -490,7 +598,10 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
 #undef CALL
         HIPCHK(hipGetLastError());
     }
-    HIPCHK(hipMemsetAsync(L.gpart, 0, (size_t)pl.ntiles * 3 * 8, st));
+    HIPCHK(hipMemsetAsync(L.gpart, 0, (size_t)pl.ntiles * kAdjMaxSubs * 3 * 8, st));
+    const uint32_t ab = adj_block(pl), asubs = kTile / ab;
+    const size_t ashm = (size_t)ab * (size_t)pl.list_cap * 8u;
+    if (ashm > kPairLdsMax) return fail(ADE_EINVAL, "candidate lists of the adjoint do not fit in LDS");
 
     AdjConst ac{};
     {
@@ -514,24 +625,24 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
             const Snap& sn = L.seg[(size_t)(n - n0)];
             const StateArrays Sa = snap_arrays(c, sn);
             dim3 g((N + 255) / 256), b(256);
-            if (pl.real_bytes == 4)
-                hipLaunchKernelGGL((k_gather_sorted<float>), g, b, 0, st, sn.id, (const float*)L.lam[li], N,
-                                   (float*)L.lam_s);
-            else
-                hipLaunchKernelGGL((k_gather_sorted<double>), g, b, 0, st, sn.id, (const double*)L.lam[li], N,
-                                   (double*)L.lam_s);
-#define LAUNCH(D, R, KK, MODE, U, X, OUT, XH)                                                          \
-    hipLaunchKernelGGL((k_adjoint<D, R, KK, MODE>), dim3(pl.ntiles), dim3(kTile), 0, st, c->plumes, c->tiles, \
-                       Sa, sn.cs, (const R*)(U), (const R*)L.lam_s, (const R*)(X), (R*)(OUT), (R*)(XH), ac,     \
-                       L.gpart)
+            const dim3 ag(pl.ntiles * asubs), abk(ab);
+#define GATHER(D, R, KK)                                                                                   \
+    hipLaunchKernelGGL((k_adj_gather<D, R>), g, b, 0, st, Sa, (const R*)L.lam[li], (const R*)sn.C, N,       \
+                       (R*)L.lam_s, L.arec)
+            ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, GATHER);
+#undef GATHER
+#define LAUNCH(D, R, KK, MODE, U, X, REC, OUT, XH, RECOUT)                                                   \
+    hipLaunchKernelGGL((k_adjoint<D, R, KK, MODE>), ag, abk, (uint32_t)ashm, st, c->plumes, c->tiles, Sa,     \
+                       sn.cs, (const R*)(U), (const R*)L.lam_s, (const R*)(X), (const uint4*)(REC), (R*)(OUT), \
+                       (R*)(XH), (uint4*)(RECOUT), ac, L.gpart)
             if (pl.integrator == ADE_PC) {
-#define CALL(D, R, KK)                                                               \
-    LAUNCH(D, R, KK, kAdjHalf, L.lam_s, sn.C, L.mu_s, L.ch_s);                        \
-    LAUNCH(D, R, KK, kAdjFull, L.mu_s, L.ch_s, L.lam[1 - li], nullptr)
+#define CALL(D, R, KK)                                                                                    \
+    LAUNCH(D, R, KK, kAdjHalf, L.lam_s, sn.C, L.arec, L.mu_s, L.ch_s, L.arec2);                              \
+    LAUNCH(D, R, KK, kAdjFull, L.mu_s, L.ch_s, L.arec2, L.lam[1 - li], nullptr, nullptr)
                 ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, CALL);
 #undef CALL
             } else {
-#define CALL(D, R, KK) LAUNCH(D, R, KK, kAdjEuler, L.lam_s, sn.C, L.lam[1 - li], nullptr)
+#define CALL(D, R, KK) LAUNCH(D, R, KK, kAdjEuler, L.lam_s, sn.C, L.arec, L.lam[1 - li], nullptr, nullptr)
                 ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, CALL);
 #undef CALL
             }
@@ -542,7 +653,7 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     }
     // leave the context at step nsteps
     if ((rc = copy_state(c, cur, L.ck[(size_t)nck]))) return rc;
-    hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, L.gpart, pl.ntiles, L.grad);
+    hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, L.gpart, pl.ntiles * asubs, L.grad);
     HIPCHK(hipGetLastError());
     double hostv[4];
     HIPCHK(hipMemcpyAsync(hostv, L.grad, 3 * 8, hipMemcpyDeviceToHost, st));

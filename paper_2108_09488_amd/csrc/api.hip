@@ -450,12 +450,19 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
         delete c;
         return rc;
     }
-    // default launch shape: two targets per lane in workgroups of 64 (the
-    // fastest shape on the 2D sweep), else two lanes per target, else four,
-    // else smaller workgroups, whichever first fits the LDS of the lists
+    // default launch shape: the fewest lanes per particle that still give
+    // the chip about 4 wavefronts per SIMD (4096 wavefronts of 64 lanes, i.e.
+    // 2^18 lanes): two targets per lane from 2^19 particles on (the fastest
+    // shape on the 2D sweep), one lane per target from 2^18, two lanes from
+    // 2^17, else four; then the next shapes whose candidate lists fit in LDS
     {
-        const ade_tuning defaults[5] = {
-            {64, 1, 0, 0, 2}, {256, 2, 0, 0, 1}, {256, 4, 0, 0, 1}, {128, 4, 0, 0, 1}, {64, 4, 0, 0, 1}};
+        const int64_t N = c->plan.N;
+        const ade_tuning first = N >= (1 << 19)   ? ade_tuning{64, 1, 0, 0, 2}
+                                 : N >= (1 << 18) ? ade_tuning{256, 1, 0, 0, 1}
+                                 : N >= (1 << 17) ? ade_tuning{256, 2, 0, 0, 1}
+                                                  : ade_tuning{256, 4, 0, 0, 1};
+        const ade_tuning defaults[6] = {first, {256, 2, 0, 0, 1}, {256, 4, 0, 0, 1}, {128, 4, 0, 0, 1},
+                                        {64, 4, 0, 0, 1}, {64, 1, 0, 0, 2}};
         bool ok = false;
         for (const ade_tuning& t : defaults)
             if (!ok && tuning_fits(c->plan, t)) {
