@@ -12,7 +12,7 @@ constexpr int kTile = 256;          // particles per tile (a tile never spans tw
 constexpr int kScanPerThread = 16;  // counting-sort scan: elements per thread
 constexpr int kScanBlock = 256;
 constexpr int kScanChunk = kScanPerThread * kScanBlock;
-constexpr int kCellChunk = 4096;    // cell-count scan: 256 threads x 16 counts per workgroup
+constexpr int kCellChunk = 1024;    // cell-count scan: 256 threads x 4 counts per workgroup
 
 // cell tables are padded to a whole number of scan chunks (plus the sentinel)
 inline uint64_t cell_pad(uint64_t ncell) { return (ncell + 1 + kCellChunk - 1) / kCellChunk * kCellChunk; }

@@ -37,10 +37,10 @@ __global__ __launch_bounds__(kTile) void k_init(const PlumeDev* __restrict__ plu
 
 // ---------------------------------------------------------------------------
 // exclusive scan of the per-cell counts -> cell_start; counts are cleared.
-// The tables are padded to whole 4096-cell chunks with zero counts, so the
+// The tables are padded to whole 1024-cell chunks with zero counts, so the
 // entry after the last cell receives the particle total (the sentinel).
 // Two launches: the chunk totals, then every workgroup sums the totals of
-// the chunks before its own (a few hundred numbers, read by all of its
+// the chunks before its own (up to a few thousand numbers, read by all its
 // threads at once) and scans its chunk.
 // ---------------------------------------------------------------------------
 constexpr int kCellVec = kCellChunk / (256 * 4);  // uint4 of counts per thread, contiguous
