@@ -407,81 +407,33 @@ __device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_
     return total;
 }
 
-// The walk of walk_list with one lane per list and two targets: every
-// record fetched is evaluated against TA and TB.  Padding slots re-read a's
-// own record, which a's predicate rejects (r2 = 0); b's evaluation keeps only
-// the slots below the lane's total (slot = batch * B + q).  Sums are added
-// to accA and accB.  b's separation from a record is taken as (x_b - x_a) +
-// (x_a - x_c) in the working precision, which saves its integer differences
-// and conversions.  pair_rows merges only pairs with |x_b - x_a| + H_u < 2^31
-// per axis, so for every neighbour of b the integer sum is its minimum-image
-// separation; a record whose sum leaves [-2^31, 2^31) is then no neighbour
-// of b, and the sum, at least 2^31 in magnitude, rejects it.  Exact in FP64; in FP32 one more rounding, which can move a
-// candidate across r = H only within a rounding of it, where its term is
-// below 1e-35 of a typical one (the neighbour-set export keeps the exact
-// predicate).
+// The walk of one lane's list (walk_stream) for two targets: every record
+// fetched is evaluated against TA and TB.  Padding slots re-read a's own
+// record, which a's predicate rejects (r2 = 0); b's evaluation keeps only the
+// slots below the lane's total.  Sums are added to accA and accB.  b's
+// separation from a record is taken as (x_b - x_a) + (x_a - x_c) in the
+// working precision, which saves its integer differences and conversions.
+// pair_rows merges only pairs with |x_b - x_a| + H_u < 2^31 per axis, so for
+// every neighbour of b the integer sum is its minimum-image separation; a
+// record whose sum leaves [-2^31, 2^31) is then no neighbour of b, and the
+// sum, at least 2^31 in magnitude, rejects it.  Exact in FP64; in FP32 one
+// more rounding, which can move a candidate across r = H only within a
+// rounding of it, where its term is below 1e-35 of a typical one (the
+// neighbour-set export keeps the exact predicate).
 template <int DIM, typename real, int KERN, typename Fetch>
 __device__ __forceinline__ void walk_pair(const PairTerm<DIM, real, KERN>& term, const Target& TA, const Target& TB,
                                           real CA, real CB, uint32_t self, const uint2* list, uint32_t stride,
                                           uint32_t total, Fetch&& fetch, real& accA, real& accB) {
-    constexpr int B = Batch<1>::value;
-    uint32_t share = total;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
-    const uint32_t nb = __builtin_amdgcn_readfirstlane((share + B - 1) / B);
-    if (nb == 0) return;
-
-    Cursor<1> cur;
-    cur.b = 0;
-    cur.e = 0;
-    cur.lp = list;
-    cur.stride = stride;
-    cur.nx = list[0];
-    cur.settle();
-
-    __builtin_amdgcn_s_waitcnt(0);
-    Cand<real> c0[B], c1[B];
-    auto fill = [&](Cand<real>(&c)[B]) {
-        uint32_t idx[B];
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-            idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
-            cur.b += Cursor<1>::kStep;
-            cur.settle();
-        }
-#pragma unroll
-        for (int q = 0; q < B; ++q) c[q] = fetch(idx[q]);
-        __builtin_amdgcn_sched_barrier(0);
-    };
     const real bx = (real)(int32_t)(TB.ux - TA.ux);
     const real by = (real)(int32_t)(TB.uy - TA.uy);
     const real bz = (DIM == 3) ? (real)(int32_t)(TB.uz - TA.uz) : (real)0;
-    auto eval = [&](const Cand<real>(&c)[B], uint32_t batch) {
-        const uint32_t s0 = batch * B;  // wavefront-uniform
-#pragma unroll
-        for (int q = 0; q < B; ++q) {
-            const real dx = (real)(int32_t)(TA.ux - c[q].x);
-            const real dy = (real)(int32_t)(TA.uy - c[q].y);
-            const real dz = (DIM == 3) ? (real)(int32_t)(TA.uz - c[q].z) : (real)0;
-            term.sep(dx, dy, dz, CA, c[q].C, true, accA);
-            term.sep(dx + bx, dy + by, dz + bz, CB, c[q].C, s0 + q < total, accB);
-        }
-    };
-    fill(c0);
-    for (uint32_t it = 1;; it += 2) {
-        if (it >= nb) {
-            eval(c0, it - 1);
-            break;
-        }
-        fill(c1);
-        eval(c0, it - 1);
-        if (it + 1 >= nb) {
-            eval(c1, it);
-            break;
-        }
-        fill(c0);
-        eval(c1, it);
-    }
+    walk_stream<Batch<1>::value>(list, stride, total, self, fetch, [&](const Cand<real>& c, bool keep) {
+        const real dx = (real)(int32_t)(TA.ux - c.x);
+        const real dy = (real)(int32_t)(TA.uy - c.y);
+        const real dz = (DIM == 3) ? (real)(int32_t)(TA.uz - c.z) : (real)0;
+        term.sep(dx, dy, dz, CA, c.C, true, accA);
+        term.sep(dx + bx, dy + by, dz + bz, CB, c.C, keep, accB);
+    });
 }
 
 // One work item = 2 * block consecutive target particles of one tile, two
