@@ -32,6 +32,10 @@ sys.path.insert(0, ROOT)
 # quadratic form x^T (Gamma D) x (7 in 2D, 14 in 3D), A = Q / r^2 - tr D (3),
 # C_a - C_b (1), accumulation (3).
 FLOPS_PER_INTERACTION = {2: 29, 3: 39}
+# the velocity-field pair term in 2D: the uniform term's separation, kernel and
+# sum, plus three harmonic means (a division each), the tensor quadratic form
+# and the convective dot product
+FLOPS_PER_INTERACTION_FIELD = {2: 57}
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published vector FP32 (packed FMA)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.md")
 PAIR_SOURCES = ["kernels_pair.hip", "ade_walk.h", "ade_geom.h", "ade_device.h", "ade_internal.h"]
@@ -216,6 +220,57 @@ def single_3d(device, steps=10):
             "ms_per_step": 1e3 * wall / steps, "interactions_per_s": inter * steps / wall}
 
 
+def velocity_field(device, steps=50, warmup=3):
+    """One 512^2 sweep plume (h = 2 dp, FP32) with a velocity per particle (the
+    smooth periodic field of inputs.velocity_field: harmonic means of the
+    per-particle tensors and the convective term active), beside the same plume
+    in the uniform flow; eager steps with the pair kernel timed by HIP events."""
+    import numpy as np
+    import torch
+    from paper_2108_09488_amd import _lib
+    from paper_2108_09488_amd import inputs as I
+    from paper_2108_09488_amd.context import Context, params_from_spec
+
+    s = I.config("cfg2_h20_r10")
+    x = s.positions()
+    C = s.concentration(x).astype(np.float32)
+    v = I.velocity_field(x, s.L)
+    out = {}
+    for kind in ("uniform", "field"):
+        stream = torch.cuda.Stream(device=device)
+        flags = _lib.ADE_VELOCITY_FIELD if kind == "field" else 0
+        c = Context([params_from_spec(s, flags=flags)], [s.n], device=device, stream=stream)
+        c.init(torch.from_numpy(x), torch.from_numpy(C))
+        if kind == "field":
+            c.set_velocities(torch.from_numpy(v))
+        c.build()
+        off, _ = c.neighbours()
+        inter = int(off[-1].item())
+        if kind == "uniform":
+            c.autotune(reps=2)
+        c.step(warmup)
+        _sync()
+        c.timing_start()
+        t0 = time.perf_counter()
+        c.step(steps)
+        _sync()
+        wall = time.perf_counter() - t0
+        ms, n = c.timing_stop()
+        c.close()
+        out[kind] = {"ms_per_step": 1e3 * wall / steps, "pair_kernel_ms": ms / n,
+                     "interactions_per_step": inter, "interactions_per_s": inter * steps / wall}
+    f = out["field"]
+    f["vs_uniform"] = f["interactions_per_s"] / out["uniform"]["interactions_per_s"]
+    achieved = FLOPS_PER_INTERACTION_FIELD[2] * f["interactions_per_step"] / (f["pair_kernel_ms"] * 1e-3) / 1e12
+    f["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                     "flops_per_interaction": FLOPS_PER_INTERACTION_FIELD[2],
+                     "kernel": "k_pair_gen<2, float, 4, 0> (update mode)"}
+    out["workload"] = ("cfg2 plume h/dp 2, alpha_L/alpha_T 10, 512^2 FP32, explicit Euler; "
+                       "interactions counted at the initial positions")
+    return out
+
+
 def cpu_baseline(cells, budget_s=20.0):
     """The FP64 oracle on the host cores: one explicit step of each plume of
     the sweep (full 512^2 size), repeated while within the time budget."""
@@ -253,6 +308,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip graph replay and batched runs")
+    ap.add_argument("--extras", default="batched,fwd_adjoint,single_3d,velocity_field",
+                    help="comma-separated extras to run (unless --no-extras)")
     ap.add_argument("--cells", default="", help="comma-separated subset of the sweep plumes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size "
@@ -293,15 +350,24 @@ def main():
     extras = {"eager": {"ms_per_step": 1e3 * ewall / args.steps,
                         "interactions_per_s": inter_step * args.steps / ewall,
                         "pair_kernel_ms_per_step": pair["ms_total"] / args.steps}}
-    if not args.no_extras:
+    want = set() if args.no_extras else set(args.extras.split(","))
+    if "batched" in want:
         b = batched(device, steps=min(args.steps, 200), warmup=args.warmup)
         b["vs_plain"] = b["interactions_per_s"] / value
         extras["batched"] = b
         print(f"[bench] batched: {b['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    if "fwd_adjoint" in want:
         extras["fwd_adjoint"] = fwd_adjoint(device)
         print(f"[bench] fwd+adjoint: {extras['fwd_adjoint']['ms_fwd_adjoint']:.1f} ms", file=sys.stderr, flush=True)
+    if "single_3d" in want:
         extras["single_3d"] = single_3d(device)
         print(f"[bench] 3D: {extras['single_3d']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    if "velocity_field" in want:
+        vf = velocity_field(device, steps=min(args.steps, 100))
+        extras["velocity_field"] = vf
+        print(f"[bench] velocity field: {vf['field']['ms_per_step']:.3f} ms/step "
+              f"(pair kernel {1e3 * vf['field']['pair_kernel_ms']:.1f} us), uniform "
+              f"{vf['uniform']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     per_cell = {n: {"interactions_per_step": i, "neighbours_mean": i / s.n}
                 for n, i, s in zip(sweep["names"], sweep["interactions"], sweep["specs"])}
     sweep["ctx"].close()

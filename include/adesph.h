@@ -13,6 +13,12 @@
  * convective term of Eq. 4 vanishes and D is the same for every particle),
  * all particles of a plume having equal mass and density.  Time stepping is
  * explicit Euler, or the predictor-corrector of Eqs. (8)-(9).
+ * A context created with ADE_VELOCITY_FIELD takes a velocity per particle
+ * instead (ade_set_velocities): each particle then has its own tensor D_a,
+ * the pair term takes the harmonic mean of Eq. (5) per component, and the
+ * convective term of Eq. (4),
+ *     + C_a sum_b (m_b / rhobar_ab) (v_a - v_b) . grad_a W_ab,
+ * is added; particles move with their own velocities (explicit Euler).
  * Reference: Klapp, Sigalotti, Alvarado-Rodriguez & Rendon, "Consistent SPH
  * simulations of the anisotropic dispersion of a contaminant plume",
  * arXiv:2108.09488, Sections 2.1-2.4.
@@ -57,7 +63,7 @@ enum {
 
 enum { ADE_WENDLAND_C2 = 2, ADE_WENDLAND_C4 = 4 };
 enum { ADE_EULER = 1, ADE_PC = 2 };
-enum { ADE_STRICT_DT = 1u, ADE_CHECK_FINITE = 2u };
+enum { ADE_STRICT_DT = 1u, ADE_CHECK_FINITE = 2u, ADE_VELOCITY_FIELD = 4u };
 
 /* One plume: kernel, box, dispersion parameters (Eq. 3), flow and time step.
  * All plumes of a context must share dim, real_bytes, kernel and integrator. */
@@ -71,11 +77,15 @@ typedef struct {
     double alpha_L;     /* longitudinal dispersivity (>= 0)                  */
     double alpha_T;     /* transverse dispersivity (>= 0)                    */
     double D_m;         /* molecular diffusion coefficient (>= 0)            */
-    double v[3];        /* uniform flow velocity (v[2] ignored in 2D)        */
+    double v[3];        /* uniform flow velocity (v[2] ignored in 2D; ignored
+                           with ADE_VELOCITY_FIELD)                         */
     double dt;          /* time step; <= 0 selects Eq. (10): 0.1 (H/2)^2 / tr D */
     double rho0;        /* density of every particle (> 0)                   */
     double mass;        /* mass of every particle (> 0)                      */
-    uint32_t flags;     /* ADE_STRICT_DT | ADE_CHECK_FINITE                  */
+    uint32_t flags;     /* ADE_STRICT_DT | ADE_CHECK_FINITE |
+                           ADE_VELOCITY_FIELD (per-particle velocities; the
+                           same on every plume of a context, ADE_EULER and
+                           dt > 0 only)                                      */
     int32_t cell_rows;  /* cell grid: rows per support radius in y (and z),
                            1..4; 0 = default                                */
     int32_t cell_xsub;  /* cell grid: cells per support radius along x,
@@ -133,6 +143,20 @@ int ade_create(const ade_params *params, const int64_t *counts, int32_t nplumes,
  * concatenated) and concentrations d_C (N reals of real_bytes) and resets
  * the step counter.  The ids of the particles are their indices in d_x. */
 int ade_init_particles(ade_ctx *ctx, const double *d_x, const void *d_C);
+
+/* Velocity field (contexts created with ADE_VELOCITY_FIELD): d_v holds the
+ * velocity of every particle (double, SoA dim x N in id order, the layout of
+ * d_x).  Call after ade_init_particles and before ade_build_cells (ADE_ESTATE
+ * otherwise; ADE_EINVAL for a context without the flag); init clears it.
+ * Each particle keeps its velocity, stored in the working precision, for
+ * the whole run; its tensor D_a (Eq. 3) is formed from the stored value.
+ * Every step, particle a moves by rint((k + 1) u_a) - rint(k u_a) grid
+ * units (u_a = dt v_a / L * 2^32, k the step index), so the displacement
+ * after k steps is rint(k u_a): exact when u_a is an integer.  The pair sum
+ * runs one lane per target with a fixed launch shape; ade_set_tuning,
+ * ade_autotune and the adjoint entry points return ADE_EINVAL for such a
+ * context. */
+int ade_set_velocities(ade_ctx *ctx, const double *d_v);
 
 /* Cell-linked list: cell hash, counting sort by cell (stable, ordered by
  * particle id within a cell) and the cell-start table, then the particle

@@ -15,14 +15,14 @@ LIB_PATH = os.path.join(HERE, "libadesph.so")
 ADE_OK, ADE_EINVAL, ADE_EWORKSPACE, ADE_EHIP, ADE_EUNSTABLE, ADE_ENONFINITE, ADE_ESTATE = 0, -1, -2, -3, -4, -5, -6
 ADE_WENDLAND_C2, ADE_WENDLAND_C4 = 2, 4
 ADE_EULER, ADE_PC = 1, 2
-ADE_STRICT_DT, ADE_CHECK_FINITE = 1, 2
+ADE_STRICT_DT, ADE_CHECK_FINITE, ADE_VELOCITY_FIELD = 1, 2, 4
 ADE_TUNE_KEEP_LANES = 1
 
 ERROR_NAMES = {0: "ADE_OK", -1: "ADE_EINVAL", -2: "ADE_EWORKSPACE", -3: "ADE_EHIP",
                -4: "ADE_EUNSTABLE", -5: "ADE_ENONFINITE", -6: "ADE_ESTATE"}
 
 # every entry point declared in include/adesph.h
-EXPORTS = ["ade_workspace_bytes", "ade_create", "ade_init_particles", "ade_build_cells",
+EXPORTS = ["ade_workspace_bytes", "ade_create", "ade_init_particles", "ade_set_velocities", "ade_build_cells",
            "ade_step", "ade_step_graph", "ade_rhs", "ade_read_C", "ade_read_x", "ade_mass",
            "ade_neighbours", "ade_sensor_interp", "ade_adjoint_workspace_bytes", "ade_adjoint",
            "ade_kernel_timing", "ade_autotune", "ade_set_tuning", "ade_get_tuning", "ade_info", "ade_destroy", "ade_last_error",
@@ -69,6 +69,7 @@ def lib() -> ct.CDLL:
         "ade_workspace_bytes": [P, p, i32, psz],
         "ade_create": [P, p, i32, p, sz, p, ct.POINTER(p)],
         "ade_init_particles": [p, p, p],
+        "ade_set_velocities": [p, p],
         "ade_build_cells": [p],
         "ade_step": [p, i64],
         "ade_step_graph": [p, i64],

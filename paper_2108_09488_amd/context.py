@@ -109,6 +109,16 @@ class Context:
         check(lib().ade_init_particles(self._h, _ptr(x), _ptr(C)))
         return self
 
+    def set_velocities(self, v: torch.Tensor):
+        """v: float64 (dim, N) per-particle velocities in id order (contexts made
+        with ADE_VELOCITY_FIELD; after init, before build)."""
+        v = v.to(self.device, torch.float64).contiguous()
+        assert v.shape == (self.dim, self.N)
+        self._inputs_ready(v)
+        self._v_in = v  # keep alive until the kernel ran
+        check(lib().ade_set_velocities(self._h, _ptr(v)))
+        return self
+
     def build(self):
         check(lib().ade_build_cells(self._h))
         return self
@@ -181,7 +191,7 @@ class Context:
                                  ct.byref(t)))
         return _tuning_dict(t)
 
-    def set_tuning(self, block=64, lanes=1, persistent=0, xcd_group=0, targets=2):
+    def set_tuning(self, block=256, lanes=2, persistent=0, xcd_group=0, targets=1):
         t = AdeTuning(block, lanes, xcd_group, persistent, targets)
         check(lib().ade_set_tuning(self._h, ct.byref(t)))
 

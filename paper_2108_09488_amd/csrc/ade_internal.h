@@ -49,6 +49,7 @@ struct PlumeDev {
     double vel[3];          // flow velocity (physical units)
     double mass;            // particle mass
     double L;
+    double aL, aT, Dm;      // alpha_L, alpha_T, D_m (per-particle tensors of a velocity field)
 };
 
 struct TileDev {
@@ -62,6 +63,11 @@ struct StateArrays {
     void* C;
     uint32_t* id;
     uint32_t* key;   // cell key (hashed buffer U only)
+    // velocity field only (null otherwise): per-particle velocity (DIM
+    // components) and the dispersion tensor of Eq. (3) it gives (2D: xx, xy,
+    // yy; 3D: xx, xy, xz, yy, yz, zz), in the working precision
+    void* vel[3];
+    void* Dt[6];
 };
 
 // Counting pass of the cell build: the number of particles per cell and
@@ -128,6 +134,23 @@ hipError_t launch_scan(CellLists lists, uint32_t* cell_start, uint32_t* partial,
 hipError_t launch_place(int dim, int real_bytes, StateArrays U, StateArrays S, CellLists lists,
                         const uint32_t* cell_start, uint32_t N, int64_t* step, int inc_step,
                         hipStream_t s);
+// Velocity field (per-particle velocities, general Eq. 4): the pair sum with
+// per-pair harmonic means and the convective term, one lane per target.
+struct GenLaunch {
+    const PlumeDev* plumes;
+    const TileDev* tiles;
+    uint32_t ntiles;
+    int list_cap;
+    StateArrays S, U;
+    const uint32_t* cell_start;
+    CellLists lists;
+    const int64_t* step;
+    void* out;              // rhs mode: id-order output
+    hipEvent_t ev0, ev1;    // if set: events stamped at the kernel's start and end
+};
+hipError_t launch_setvel(int dim, int real_bytes, const PlumeDev* plumes, const TileDev* tiles, uint32_t ntiles,
+                         const double* v, uint32_t N, StateArrays U, hipStream_t s);
+hipError_t launch_pair_gen(int dim, int real_bytes, int kernel, int mode, const GenLaunch& g, hipStream_t s);
 hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const PairLaunch& a,
                        int block, hipStream_t s);
 hipError_t launch_read_C(int real_bytes, StateArrays S, uint32_t N, void* out, hipStream_t s);

@@ -549,6 +549,7 @@ int ade_adjoint_workspace_bytes(const ade_ctx* c, int64_t nsteps, int32_t ckpt_e
     if (!c || !bytes) return fail(ADE_EINVAL, "null argument");
     if (nsteps < 1 || ckpt_every < 1 || n_sensors < 1)
         return fail(ADE_EINVAL, "nsteps, ckpt_every and n_sensors must be positive");
+    if (c->plan.general) return fail(ADE_EINVAL, "the adjoint takes a uniform flow");
     AdjLayout L;
     adj_layout(c, nsteps, ckpt_every, n_sensors, nullptr, L);
     *bytes = L.bytes;
@@ -561,6 +562,7 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     if (rc) return rc;
     if (!d_obs || !d_ws || !h_J || !h_grad) return fail(ADE_EINVAL, "null argument");
     if (nsteps < 1 || K < 1) return fail(ADE_EINVAL, "nsteps and ckpt_every must be positive");
+    if (c->plan.general) return fail(ADE_EINVAL, "the adjoint takes a uniform flow");
     if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
     AdjLayout L;
     adj_layout(c, nsteps, K, ns, nullptr, L);

@@ -108,6 +108,7 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
     pl.real_bytes = p0.real_bytes;
     pl.kernel = p0.kernel;
     pl.integrator = p0.integrator;
+    pl.general = (p0.flags & ADE_VELOCITY_FIELD) != 0;
     pl.P = nplumes;
     if (pl.dim != 2 && pl.dim != 3) return fail(ADE_EINVAL, "dim must be 2 or 3 (got %d)", pl.dim);
     if (pl.real_bytes != 4 && pl.real_bytes != 8) return fail(ADE_EINVAL, "real_bytes must be 4 or 8");
@@ -124,6 +125,14 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
             q.integrator != pl.integrator)
             return fail(ADE_EINVAL, "plume %d: dim, real_bytes, kernel and integrator must match plume 0", p);
         if (q.reserved != 0) return fail(ADE_EINVAL, "plume %d: reserved must be 0", p);
+        if (((q.flags & ADE_VELOCITY_FIELD) != 0) != pl.general)
+            return fail(ADE_EINVAL, "plume %d: ADE_VELOCITY_FIELD must match plume 0", p);
+        if (q.flags & ~(uint32_t)(ADE_STRICT_DT | ADE_CHECK_FINITE | ADE_VELOCITY_FIELD))
+            return fail(ADE_EINVAL, "plume %d: unknown flags", p);
+        if (pl.general && q.integrator != ADE_EULER)
+            return fail(ADE_EINVAL, "plume %d: a velocity field steps with ADE_EULER only", p);
+        if (pl.general && !(q.dt > 0))
+            return fail(ADE_EINVAL, "plume %d: a velocity field needs dt > 0", p);
         if (counts[p] <= 0) return fail(ADE_EINVAL, "plume %d: count must be positive", p);
         const double vals[] = {q.H, q.L, q.alpha_L, q.alpha_T, q.D_m, q.v[0], q.v[1], q.v[2], q.dt, q.rho0, q.mass};
         for (double v : vals)
@@ -227,6 +236,9 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         }
         d.mass = q.mass;
         d.L = q.L;
+        d.aL = q.alpha_L;
+        d.aT = q.alpha_T;
+        d.Dm = q.D_m;
         d.tfirst = (uint32_t)pl.tiles.size();
         for (uint32_t s = 0; s < d.n; s += kTile) {
             TileDev t;
@@ -286,6 +298,8 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
         s.C = b.take_bytes(N * rb);
         s.id = b.take<uint32_t>(N);
         s.key = (k == 1) ? b.take<uint32_t>(N) : nullptr;
+        for (int d = 0; d < 3; ++d) s.vel[d] = (pl.general && d < pl.dim) ? b.take_bytes(N * rb) : nullptr;
+        for (int d = 0; d < 6; ++d) s.Dt[d] = (pl.general && d < (pl.dim == 2 ? 3 : 6)) ? b.take_bytes(N * rb) : nullptr;
     }
     if (pl.dim == 2) {  // never read in 2D, but keep the pointers valid
         c->S.pos[2] = c->S.pos[0];
@@ -322,27 +336,48 @@ int flush_events(ade_ctx* c) {
 
 namespace ade {
 
+// a pair of timing events from the context's pool, or false when timing is
+// off (or a graph is being captured)
+static int take_events(ade_ctx* c, hipEvent_t& e0, hipEvent_t& e1, bool& took) {
+    took = false;
+    if (!c->timing || c->capturing) return ADE_OK;
+    if (c->ev_used + 2 > c->events.size()) {
+        if (c->events.size() < 4096) {
+            size_t old = c->events.size();
+            c->events.resize(old + 512);
+            for (size_t k = old; k < c->events.size(); ++k) HIPCHK(hipEventCreate(&c->events[k]));
+        } else {
+            int rc = flush_events(c);
+            if (rc) return rc;
+        }
+    }
+    e0 = c->events[c->ev_used++];
+    e1 = c->events[c->ev_used++];
+    took = true;
+    return ADE_OK;
+}
+
 // launch a pair kernel; when timing is on, events stamped with the kernel's
 // own start and end times are attached to the launch
 int run_pair(ade_ctx* c, int mode, const PairLaunch& a) {
     const Plan& pl = c->plan;
     PairLaunch b = a;
     b.ev0 = b.ev1 = nullptr;
-    if (c->timing && !c->capturing) {
-        if (c->ev_used + 2 > c->events.size()) {
-            if (c->events.size() < 4096) {
-                size_t old = c->events.size();
-                c->events.resize(old + 512);
-                for (size_t k = old; k < c->events.size(); ++k) HIPCHK(hipEventCreate(&c->events[k]));
-            } else {
-                int rc = flush_events(c);
-                if (rc) return rc;
-            }
-        }
-        b.ev0 = c->events[c->ev_used++];
-        b.ev1 = c->events[c->ev_used++];
-    }
+    bool took = false;
+    int rc = take_events(c, b.ev0, b.ev1, took);
+    if (rc) return rc;
     HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, mode, b, c->tuning.block, c->stream));
+    return ADE_OK;
+}
+
+// the same for the velocity-field pair kernel
+int run_gen(ade_ctx* c, int mode, void* out) {
+    const Plan& pl = c->plan;
+    GenLaunch g = gen_args(c, out);
+    bool took = false;
+    int rc = take_events(c, g.ev0, g.ev1, took);
+    if (rc) return rc;
+    HIPCHK(launch_pair_gen(pl.dim, pl.real_bytes, pl.kernel, mode, g, c->stream));
     return ADE_OK;
 }
 
@@ -389,10 +424,28 @@ int enqueue_build(ade_ctx* c, int inc_step) {
     return ADE_OK;
 }
 
+GenLaunch gen_args(ade_ctx* c, void* out) {
+    GenLaunch g;
+    std::memset(&g, 0, sizeof g);
+    g.plumes = c->plumes;
+    g.tiles = c->pair_tiles;
+    g.ntiles = c->plan.ntiles;
+    g.list_cap = c->plan.list_cap;
+    g.S = c->S;
+    g.U = c->U;
+    g.cell_start = c->cell_start;
+    g.lists = c->lists;
+    g.step = c->step;
+    g.out = out;
+    return g;
+}
+
 int enqueue_step(ade_ctx* c) {
     const Plan& pl = c->plan;
     int rc;
-    if (pl.integrator == ADE_PC) {
+    if (pl.general) {  // velocity field: explicit Euler
+        if ((rc = run_gen(c, kModeStep, nullptr))) return rc;
+    } else if (pl.integrator == ADE_PC) {
         PairLaunch h = pair_args(c, kModeHalf, c->S.C, c->S.C, 0.5, c->aux);
         if ((rc = run_pair(c, kModeHalf, h))) return rc;
         PairLaunch f = pair_args(c, kModeStep, c->aux, c->S.C, 1.0, nullptr);
@@ -455,6 +508,10 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
     // 2^18 lanes): two targets per lane from 2^19 particles on (the fastest
     // shape on the 2D sweep), one lane per target from 2^18, two lanes from
     // 2^17, else four; then the next shapes whose candidate lists fit in LDS
+    if (c->plan.general && (size_t)64 * (size_t)c->plan.list_cap * 8u > kPairLdsMax) {
+        delete c;
+        return fail(ADE_EINVAL, "too many neighbour rows: the candidate lists do not fit in LDS");
+    }
     {
         const int64_t N = c->plan.N;
         const ade_tuning first = N >= (1 << 19)   ? ade_tuning{64, 1, 0, 0, 2}
@@ -510,12 +567,27 @@ int ade_init_particles(ade_ctx* c, const double* d_x, const void* d_C) {
                        c->U, c->lists, c->stream));
     c->initialized = true;
     c->built = false;
+    c->vel_set = false;
+    return ADE_OK;
+}
+
+int ade_set_velocities(ade_ctx* c, const double* d_v) {
+    if (!c || !d_v) return fail(ADE_EINVAL, "null argument");
+    const Plan& pl = c->plan;
+    if (!pl.general) return fail(ADE_EINVAL, "context created without ADE_VELOCITY_FIELD");
+    if (!c->initialized || c->built)
+        return fail(ADE_ESTATE, "ade_set_velocities belongs between ade_init_particles and ade_build_cells");
+    HIPCHK(launch_setvel(pl.dim, pl.real_bytes, c->plumes, c->tiles, pl.ntiles, d_v, (uint32_t)pl.N, c->U,
+                         c->stream));
+    c->vel_set = true;
     return ADE_OK;
 }
 
 int ade_build_cells(ade_ctx* c) {
     if (!c) return fail(ADE_EINVAL, "null ctx");
     if (!c->initialized) return fail(ADE_ESTATE, "ade_build_cells before ade_init_particles");
+    if (c->plan.general && !c->vel_set && !c->built)
+        return fail(ADE_ESTATE, "ade_build_cells before ade_set_velocities (ADE_VELOCITY_FIELD)");
     if (c->built) return ADE_OK;  // every step already leaves the cells built
     int rc = enqueue_build(c, 0);
     if (rc) return rc;
@@ -566,7 +638,7 @@ int ade_rhs(ade_ctx* c, void* d_rhs) {
     if (!c || !d_rhs) return fail(ADE_EINVAL, "null argument");
     if (!c->built) return fail(ADE_ESTATE, "ade_rhs before ade_build_cells");
     const Plan& pl = c->plan;
-    (void)pl;
+    if (pl.general) return run_gen(c, kModeRhs, d_rhs);
     PairLaunch a = pair_args(c, kModeRhs, c->S.C, c->S.C, 1.0, d_rhs);
     return run_pair(c, kModeRhs, a);
 }
@@ -642,6 +714,7 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     if (!c) return fail(ADE_EINVAL, "null ctx");
     if (reps < 1) return fail(ADE_EINVAL, "reps must be positive");
     if (!c->built) return fail(ADE_ESTATE, "ade_autotune before ade_build_cells");
+    if (c->plan.general) return fail(ADE_EINVAL, "a velocity-field context has a fixed launch shape");
     const Plan& pl = c->plan;
     const ade_tuning start = c->tuning;
     hipEvent_t e0, e1;
@@ -708,6 +781,7 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
 
 int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
     if (!c || !t) return fail(ADE_EINVAL, "null argument");
+    if (c->plan.general) return fail(ADE_EINVAL, "a velocity-field context has a fixed launch shape");
     if (t->block != 64 && t->block != 128 && t->block != 256)
         return fail(ADE_EINVAL, "block must be 64, 128 or 256");
     if (t->lanes != 1 && t->lanes != 2 && t->lanes != 4) return fail(ADE_EINVAL, "lanes must be 1, 2 or 4");

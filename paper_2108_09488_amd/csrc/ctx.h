@@ -30,6 +30,7 @@ struct Plan {
     uint32_t ntiles = 0, nscan = 0;
     int list_cap = 0;       // candidate-list entries per target (largest plume)
     int list_cap_pair = 0;  // the same for a lane's merged list of two targets
+    bool general = false;   // velocity field: per-particle velocities (ADE_VELOCITY_FIELD)
     std::vector<PlumeDev> plumes;
     std::vector<TileDev> tiles;
     std::vector<TileDev> pair_tiles;  // the tiles in the pair kernel's order (costliest plumes first)
@@ -61,6 +62,7 @@ struct ade_ctx {
     int64_t* step = nullptr;
     uint32_t h_total = 0;  // host copy of N for the cell-start sentinel
     bool initialized = false, built = false;
+    bool vel_set = false;  // velocity field: ade_set_velocities called since init
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
     bool capturing = false;
@@ -82,5 +84,9 @@ PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase,
 int enqueue_build(ade_ctx* c, int inc_step);
 // one explicit step (pair sum, update, rebuild)
 int enqueue_step(ade_ctx* c);
+// launch arguments of the velocity-field pair kernel over the sorted state of c
+GenLaunch gen_args(ade_ctx* c, void* out);
+// enqueue the velocity-field pair kernel (timed when timing is on)
+int run_gen(ade_ctx* c, int mode, void* out);
 
 }  // namespace ade

@@ -157,7 +157,8 @@ hipError_t launch_scan64(int64_t* data, uint32_t n, int64_t* partial, hipStream_
 // among the particles of its cell), found from the ids in the cell's bucket
 // (and, for a cell of more than kBucket particles, the overflow list), so the sorted
 // order is a pure function of the positions.  Writes the sorted state S and
-// its candidate records; advances the step counter if asked.
+// its candidate records (and, for a velocity field, its velocity and
+// tensor); advances the step counter if asked.
 // ---------------------------------------------------------------------------
 template <int DIM, typename real>
 __global__ __launch_bounds__(256) void k_place(StateArrays U, StateArrays S, CellLists L,
@@ -197,6 +198,13 @@ __global__ __launch_bounds__(256) void k_place(StateArrays U, StateArrays S, Cel
     static_cast<real*>(S.C)[d] = C;
     S.id[d] = my;
     if (Rec<DIM, real>::kStageable) S.rec[d] = Rec<DIM, real>::pack(u[0], u[1], u[2], C);
+    if (U.vel[0]) {  // velocity field: the particle's velocity and tensor travel with it
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) static_cast<real*>(S.vel[c])[d] = static_cast<const real*>(U.vel[c])[i];
+#pragma unroll
+        for (int q = 0; q < (DIM == 2 ? 3 : 6); ++q)
+            static_cast<real*>(S.Dt[q])[d] = static_cast<const real*>(U.Dt[q])[i];
+    }
 }
 
 // ---------------------------------------------------------------------------

@@ -129,6 +129,27 @@ def sensors(n_sensors: int, lo, hi, seed: int = BASE_SEED, stream: int = 7777,
     return out
 
 
+def velocity_field(x: np.ndarray, L: float = 1.0, U: float = 1.0, amp: float = 0.3,
+                   quantum: float = 0.0) -> np.ndarray:
+    """A smooth periodic flow for the per-particle velocity path, evaluated at
+    positions x (dim, n): a drift U along x with a shear and a compressive part,
+        v_x = U (1 + amp sin(2 pi y / L) + amp sin(2 pi x / L)),
+        v_y = U amp cos(2 pi x / L)           [, v_z = U amp sin(2 pi (x + y) / L)].
+    quantum > 0 rounds every component to a multiple of it (so that dt v / L
+    can be a whole number of fixed-point units per step)."""
+    x = np.asarray(x, dtype=np.float64)
+    dim = x.shape[0]
+    k = 2.0 * math.pi / L
+    v = np.zeros_like(x)
+    v[0] = U * (1.0 + amp * np.sin(k * x[1]) + amp * np.sin(k * x[0]))
+    v[1] = U * amp * np.cos(k * x[0])
+    if dim == 3:
+        v[2] = U * amp * np.sin(k * (x[0] + x[1]))
+    if quantum > 0:
+        v = np.rint(v / quantum) * quantum
+    return v
+
+
 @dataclass
 class PlumeSpec:
     """One plume problem: particles on a lattice in a periodic box with uniform flow."""

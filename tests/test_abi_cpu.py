@@ -73,6 +73,27 @@ def test_strict_dt_flags_unstable_step():
     assert _wsbytes([p], [s.n])[0] == _lib.ADE_EUNSTABLE
 
 
+def test_velocity_field_flag_validation():
+    """ADE_VELOCITY_FIELD: explicit Euler with a given dt, the same on every
+    plume; its workspace holds the per-particle velocities and tensors."""
+    s = I.config("cfg1")
+    base = params_from_spec(s)
+    p = params_from_spec(s, flags=_lib.ADE_VELOCITY_FIELD)
+    rc0, nb0 = _wsbytes([base], [s.n])
+    rc, nb = _wsbytes([p], [s.n])
+    assert rc0 == 0 and rc == 0
+    # two buffers (sorted and hashed) of 2 velocity and 3 tensor components, FP64
+    assert nb - nb0 >= 2 * 5 * 8 * s.n
+    pc = params_from_spec(s, integrator=_lib.ADE_PC, flags=_lib.ADE_VELOCITY_FIELD)
+    assert _wsbytes([pc], [s.n])[0] == _lib.ADE_EINVAL
+    p0 = params_from_spec(s, flags=_lib.ADE_VELOCITY_FIELD)
+    p0.dt = 0.0
+    assert _wsbytes([p0], [s.n])[0] == _lib.ADE_EINVAL
+    assert _wsbytes([p, base], [s.n, s.n])[0] == _lib.ADE_EINVAL
+    bad = params_from_spec(s, flags=64)
+    assert _wsbytes([bad], [s.n])[0] == _lib.ADE_EINVAL
+
+
 def test_create_rejects_null_and_small_workspace():
     p = params_from_spec(I.config("cfg1"))
     arr = (_lib.AdeParams * 1)(p)

@@ -1,0 +1,210 @@
+"""Velocity-field path (per-particle velocities, the general Eqs. 4-5: the
+elementwise harmonic mean of the two particles' tensors and the convective
+term) against the FP64 CPU oracle, through the C ABI.
+
+Tolerances as for the uniform flow: neighbour sets and positions bit-exact
+(velocities quantised so that every step moves a particle by a whole number
+of fixed-point units, as the oracle's FP64 positions then do exactly); FP64
+within 1e-12 relative L2, FP32 within 1e-5.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2108_09488_amd import _lib
+from paper_2108_09488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TWO32 = 4294967296.0
+DT_EXACT = 2.0 ** -12   # with v a multiple of 2^-20 and L = 1: dt v 2^32 / L is an integer
+V_QUANTUM = 2.0 ** -20
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _spec(dim, real_bytes, n_side, kernel=4, hod=1.5, jitter=0.1, dt=DT_EXACT):
+    base = "cfg1" if dim == 2 else "cfg3"
+    return I.config(base, n_side=n_side, real_bytes=real_bytes, kernel=kernel, h_over_dp=hod,
+                    jitter=jitter, dt=dt)
+
+
+def _ctx(spec, v, C=None, stream=None):
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    print(f"[case] velocity field dim={spec.dim} n={spec.n} rb={spec.real_bytes} k={spec.kernel} "
+          f"h/dp={spec.h_over_dp}", flush=True)
+    ctx = Context([params_from_spec(spec, flags=_lib.ADE_VELOCITY_FIELD)], [spec.n], stream=stream)
+    x = spec.positions()
+    if C is None:
+        C = spec.concentration(x)
+    if spec.real_bytes == 4:
+        C = C.astype(np.float32).astype(np.float64)
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C)).set_velocities(torch.from_numpy(v)).build()
+    return ctx, x, C
+
+
+def _field(spec, quantise=True):
+    x = spec.positions()
+    v = I.velocity_field(x, spec.L, quantum=V_QUANTUM if quantise else 0.0)
+    if spec.real_bytes == 4:  # what the context stores
+        v = v.astype(np.float32).astype(np.float64)
+    return v
+
+
+RHS_CASES = [(2, 8, 40, 2, 1.3), (2, 8, 50, 4, 2.0), (2, 4, 96, 4, 1.5), (2, 4, 70, 4, 3.0),
+             (3, 4, 16, 4, 2.0), (3, 8, 12, 2, 1.3), (3, 8, 13, 4, 1.5)]
+
+
+@pytest.mark.parametrize("dim,rb,n_side,kernel,hod", RHS_CASES)
+def test_velocity_field_rhs_parity(dim, rb, n_side, kernel, hod):
+    spec = _spec(dim, rb, n_side, kernel, hod)
+    v = _field(spec, quantise=False)
+    ctx, x, C = _ctx(spec, v)
+    g = ctx.rhs().double().cpu().numpy()
+    r = O.rhs(O.model_from_spec(spec), x, C, v=v, mass=spec.mass, rho=spec.rho0)
+    assert _rel(g, r) < (1e-12 if rb == 8 else 1e-5)
+    # the convective term carries weight in this comparison
+    r_disp = O.rhs(O.model_from_spec(spec), x, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+    assert _rel(r_disp, r) > 1e-2
+    ctx.close()
+
+
+def test_velocity_field_full_size_sampled():
+    """The 512^2 FP32 plume of the benchmark (h = 2 dp) with the velocity field:
+    the right-hand side at a seeded sample of particles against the oracle,
+    then one step: every particle on its exact schedule and the sampled C."""
+    spec = I.config("cfg2_h20_r10")
+    x = spec.positions()
+    v = I.velocity_field(x, spec.L).astype(np.float32).astype(np.float64)
+    ctx, x, C = _ctx(spec, v)
+    g = ctx.rhs().double().cpu().numpy()
+    rng = np.random.default_rng(11)
+    inside = np.flatnonzero(C > 1e-3)
+    idx = np.sort(rng.choice(inside, size=1500, replace=False))
+    r = O.rhs(O.model_from_spec(spec), x, C, v=v, mass=spec.mass, rho=spec.rho0, idx=idx)
+    assert _rel(g[idx], r) < 1e-5
+    ctx.step(1)
+    C1 = ctx.read_C().double().cpu().numpy()
+    assert _rel(C1[idx], C[idx] + spec.dt * r) < 1e-5
+    xg = ctx.read_x().cpu().numpy()
+    u0 = O.to_fixed(x, spec.L).astype(np.int64)
+    u1 = np.mod(u0 + np.rint(spec.dt * v / spec.L * TWO32).astype(np.int64), 1 << 32)
+    assert np.array_equal(xg, u1.astype(np.float64) / TWO32 * spec.L)
+    ctx.close()
+
+
+def test_uniform_field_matches_uniform_flow():
+    """The same velocity for every particle gives the uniform-flow operator
+    (the harmonic mean of two equal tensors is twice the tensor, and the
+    convective term vanishes)."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = _spec(2, 8, 48, 4, 1.5)
+    v = np.tile(spec.velocity()[:, None], (1, spec.n))
+    ctx, x, C = _ctx(spec, v)
+    g = ctx.rhs().cpu().numpy()
+    u = Context([params_from_spec(spec)], [spec.n])
+    u.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+    gu = u.rhs().cpu().numpy()
+    assert _rel(g, gu) < 1e-12
+    ctx.close()
+    u.close()
+
+
+@pytest.mark.parametrize("dim,rb,n_side,steps", [(2, 8, 48, 40), (2, 4, 64, 40), (3, 4, 14, 12), (3, 8, 14, 6)])
+def test_velocity_field_trajectory(dim, rb, n_side, steps):
+    """Explicit Euler with per-particle moves: positions bit-exact (whole
+    fixed-point units per step), C within the tolerance, and the neighbour
+    sets of the moved particles bit-exact."""
+    spec = _spec(dim, rb, n_side, 4, 1.5 if dim == 2 else 2.0)
+    v = _field(spec)
+    ctx, x, C0 = _ctx(spec, v)
+    ctx.step(steps)
+    C = ctx.read_C().double().cpu().numpy()
+    xg = ctx.read_x().cpu().numpy()
+    xo, Co, _ = O.run(O.model_from_spec(spec), x, C0, spec.dt, steps, v=v, mass=spec.mass, rho=spec.rho0)
+    assert np.array_equal(xg, xo)
+    assert _rel(C, Co) < (1e-12 if rb == 8 else 1e-5)
+    off, ids = ctx.neighbours()
+    off, ids = off.cpu().numpy(), ids.cpu().numpy()
+    seg = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    ids = ids[np.lexsort((ids, seg))]
+    o_off, o_ids = O.neighbours_fixed(dim, xo, spec.L, spec.H, rb)
+    assert np.array_equal(off, o_off) and np.array_equal(ids, o_ids)
+    ctx.close()
+
+
+def test_velocity_field_moves_on_the_exact_schedule():
+    """Velocities that are not whole fixed-point units per step: after k steps
+    a particle has moved by rint(k u) units, u = dt v / L 2^32 (FP64 state)."""
+    spec = _spec(2, 8, 32, 4, 1.5, dt=1.7e-4)
+    v = _field(spec, quantise=False)
+    ctx, x, _ = _ctx(spec, v)
+    k = 9
+    ctx.step(k)
+    xg = ctx.read_x().cpu().numpy()
+    u0 = O.to_fixed(x, spec.L).astype(np.int64)
+    us = spec.dt * v / spec.L * TWO32
+    uk = np.mod(u0 + np.rint(k * us).astype(np.int64), 1 << 32)
+    assert np.array_equal(xg, uk.astype(np.float64) / TWO32 * spec.L)
+    ctx.close()
+
+
+def test_velocity_field_graph_replay_and_determinism():
+    spec = _spec(2, 4, 64, 4, 2.0)
+    v = _field(spec)
+    outs = []
+    for graph in (False, False, True):
+        stream = torch.cuda.Stream()
+        ctx, _, _ = _ctx(spec, v, stream=stream)
+        if graph:
+            for _ in range(3):  # several graph launches with host work between them
+                ctx.step_graph(3)
+                torch.cuda.synchronize()
+        else:
+            ctx.step(9)
+        outs.append((ctx.read_C().cpu().numpy().copy(), ctx.read_x().cpu().numpy().copy()))
+        assert ctx.info()["step"] == 9
+        stream.synchronize()
+        ctx.close()
+    for C, xx in outs[1:]:
+        assert np.array_equal(C, outs[0][0]) and np.array_equal(xx, outs[0][1])
+
+
+def test_velocity_field_validation():
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = _spec(2, 4, 32, 4, 1.5)
+    x = spec.positions()
+    C = spec.concentration(x).astype(np.float32).astype(np.float64)
+    v = torch.from_numpy(_field(spec))
+    # a uniform-flow context takes no velocities
+    u = Context([params_from_spec(spec)], [spec.n])
+    u.init(torch.from_numpy(x), torch.from_numpy(C))
+    with pytest.raises(_lib.AdeError) as e:
+        u.set_velocities(v)
+    assert e.value.code == _lib.ADE_EINVAL
+    u.close()
+    ctx = Context([params_from_spec(spec, flags=_lib.ADE_VELOCITY_FIELD)], [spec.n])
+    with pytest.raises(_lib.AdeError) as e:  # before init
+        ctx.set_velocities(v)
+    assert e.value.code == _lib.ADE_ESTATE
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C))
+    with pytest.raises(_lib.AdeError) as e:  # build before the velocities
+        ctx.build()
+    assert e.value.code == _lib.ADE_ESTATE
+    ctx.set_velocities(v).build()
+    with pytest.raises(_lib.AdeError) as e:  # after build
+        ctx.set_velocities(v)
+    assert e.value.code == _lib.ADE_ESTATE
+    for call in (lambda: ctx.set_tuning(), lambda: ctx.autotune()):
+        with pytest.raises(_lib.AdeError) as e:
+            call()
+        assert e.value.code == _lib.ADE_EINVAL
+    # init clears the velocities: build needs them again
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C))
+    with pytest.raises(_lib.AdeError) as e:
+        ctx.build()
+    assert e.value.code == _lib.ADE_ESTATE
+    ctx.close()

@@ -197,6 +197,70 @@ def test_isotropic_limit_is_brookshaw(dim):
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.max(np.abs(ref))
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_isotropic_field_is_cleary_monaghan_harmonic(dim):
+    """alpha_L = alpha_T with a per-particle speed makes every tensor isotropic,
+    D_a = kappa_a I, but different per particle.  On a regular lattice with the
+    shear flow v = (s(y), 0[, 0]) the convective term cancels pair by pair
+    (mirror neighbours across x have equal velocity and opposite x_ab), and the
+    operator reduces to the Cleary-Monaghan conduction sum with the harmonic
+    mean of the conductivities, sum_b V_b 4 kappa_a kappa_b / (kappa_a +
+    kappa_b) (C_a - C_b) W'(r)/r (kernel derivative from numpy's polynomial)."""
+    n_side = 32 if dim == 2 else 16  # powers of 2: the lattice is exact, so is its mirror symmetry
+    dp = 1.0 / n_side
+    H = 2 * 1.5 * dp
+    x = I.lattice(n_side, dim)
+    n = x.shape[1]
+    s = 1.0 + 0.5 * np.sin(2 * np.pi * x[1])
+    v = np.zeros((dim, n))
+    v[0] = s
+    aL = aT = 0.01
+    Dm = 1e-5
+    C = np.sin(2 * np.pi * x[0]) + np.cos(2 * np.pi * x[1])
+    m = O.model(dim, 4, H, alpha_L=aL, alpha_T=aT, D_m=Dm)
+    rho = 1000.0
+    mass = rho * dp ** dim
+    got = O.rhs(m, x, C, v=v, mass=mass, rho=rho)
+    kap = aT * np.abs(s) + Dm
+    q = P([0.0, 1.0])
+    df = ((1 - q) ** 6 * (1 + 6 * q + (35.0 / 3.0) * q ** 2)).deriv()
+    B = O.kernel_B(4, dim, H)
+    ref = np.zeros(n)
+    for a in range(n):
+        d = (x[:, a:a + 1] - x + 0.5) % 1.0 - 0.5
+        r = np.sqrt((d * d).sum(0))
+        sel = (r > 0) & (r <= H)
+        dW = B / H * df(r[sel] / H)
+        kh = 4 * kap[a] * kap[sel] / (kap[a] + kap[sel])
+        ref[a] = np.sum((mass / rho) * kh * (C[a] - C[sel]) * dW / r[sel])
+    assert np.max(np.abs(got - ref)) <= 1e-11 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("dim,n_side,tol", [(2, 64, 1e-2), (3, 24, 4e-2)])
+def test_convective_term_is_minus_c_div_v(dim, n_side, tol):
+    """With C constant the dispersive part vanishes and Eq. (4) keeps
+    C_a sum_b V_b (v_a - v_b) . grad_a W_ab, the SPH estimate of -C div v
+    (Eq. 1).  For a smooth periodic field on a regular lattice it matches the
+    analytic -C div v to the discretisation error, which falls with dp."""
+    def err(ns):
+        dp = 1.0 / ns
+        H = 2 * 2.0 * dp
+        x = I.lattice(ns, dim)
+        a = 0.3
+        v = np.zeros((dim, x.shape[1]))
+        v[0] = 1 + a * np.sin(2 * np.pi * x[0])
+        v[1] = a * np.cos(2 * np.pi * x[1])
+        div = a * 2 * np.pi * np.cos(2 * np.pi * x[0]) - a * 2 * np.pi * np.sin(2 * np.pi * x[1])
+        c0 = 2.5
+        m = O.model(dim, 4, H, alpha_L=0.02, alpha_T=0.004, D_m=1e-6)
+        r = O.rhs(m, x, np.full(x.shape[1], c0), v=v, mass=1000.0 * dp ** dim, rho=1000.0)
+        return np.max(np.abs(r + c0 * div)) / np.max(np.abs(c0 * div))
+    e = err(n_side)
+    assert e < tol
+    if dim == 2:
+        assert err(2 * n_side) < 0.6 * e
+
+
 def _stencil_moment(dim, n_side, hod, kernel, aL, aT, v):
     dp = 1.0 / n_side
     H = 2 * hod * dp
