@@ -64,10 +64,14 @@ struct StateArrays {
     uint32_t* id;
     uint32_t* key;   // cell key (hashed buffer U only)
     // velocity field only (null otherwise): per-particle velocity (DIM
-    // components) and the dispersion tensor of Eq. (3) it gives (2D: xx, xy,
-    // yy; 3D: xx, xy, xz, yy, yz, zz), in the working precision
+    // components) and the reciprocals of the components of the dispersion
+    // tensor of Eq. (3) it gives (2D: xx, xy, yy; 3D: xx, xy, xz, yy, yz, zz;
+    // 1/0 = inf), in the working precision
     void* vel[3];
-    void* Dt[6];
+    void* rD[6];
+    // velocity field in 2D FP32, sorted buffer S only (null otherwise): a
+    // 32-byte record per particle, {x, y, C, v_x} {v_y, 1/D_xx, 1/D_xy, 1/D_yy}
+    uint4* grec;
 };
 
 // Counting pass of the cell build: the number of particles per cell and

@@ -299,7 +299,8 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
         s.id = b.take<uint32_t>(N);
         s.key = (k == 1) ? b.take<uint32_t>(N) : nullptr;
         for (int d = 0; d < 3; ++d) s.vel[d] = (pl.general && d < pl.dim) ? b.take_bytes(N * rb) : nullptr;
-        for (int d = 0; d < 6; ++d) s.Dt[d] = (pl.general && d < (pl.dim == 2 ? 3 : 6)) ? b.take_bytes(N * rb) : nullptr;
+        for (int d = 0; d < 6; ++d) s.rD[d] = (pl.general && d < (pl.dim == 2 ? 3 : 6)) ? b.take_bytes(N * rb) : nullptr;
+        s.grec = (k == 0 && pl.general && pl.dim == 2 && pl.real_bytes == 4) ? b.take<uint4>(2 * N) : nullptr;
     }
     if (pl.dim == 2) {  // never read in 2D, but keep the pointers valid
         c->S.pos[2] = c->S.pos[0];

@@ -199,11 +199,20 @@ __global__ __launch_bounds__(256) void k_place(StateArrays U, StateArrays S, Cel
     S.id[d] = my;
     if (Rec<DIM, real>::kStageable) S.rec[d] = Rec<DIM, real>::pack(u[0], u[1], u[2], C);
     if (U.vel[0]) {  // velocity field: the particle's velocity and tensor travel with it
+        real w[DIM + (DIM == 2 ? 3 : 6)];
 #pragma unroll
-        for (int c = 0; c < DIM; ++c) static_cast<real*>(S.vel[c])[d] = static_cast<const real*>(U.vel[c])[i];
+        for (int c = 0; c < DIM; ++c) w[c] = static_cast<const real*>(U.vel[c])[i];
 #pragma unroll
-        for (int q = 0; q < (DIM == 2 ? 3 : 6); ++q)
-            static_cast<real*>(S.Dt[q])[d] = static_cast<const real*>(U.Dt[q])[i];
+        for (int q = 0; q < (DIM == 2 ? 3 : 6); ++q) w[DIM + q] = static_cast<const real*>(U.rD[q])[i];
+#pragma unroll
+        for (int c = 0; c < DIM; ++c) static_cast<real*>(S.vel[c])[d] = w[c];
+#pragma unroll
+        for (int q = 0; q < (DIM == 2 ? 3 : 6); ++q) static_cast<real*>(S.rD[q])[d] = w[DIM + q];
+        if (DIM == 2 && sizeof(real) == 4 && S.grec) {
+            auto bits = [](real f) { return __float_as_uint((float)f); };
+            S.grec[2 * (size_t)d] = make_uint4(u[0], u[1], bits(C), bits(w[0]));
+            S.grec[2 * (size_t)d + 1] = make_uint4(bits(w[1]), bits(w[2]), bits(w[3]), bits(w[4]));
+        }
     }
 }
 

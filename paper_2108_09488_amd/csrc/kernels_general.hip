@@ -11,18 +11,30 @@
 // own velocities, each on the exact fixed-point schedule of the uniform case
 // (displacement rint((k+1) u_a) - rint(k u_a) at step k, u_a = dt v_a / L
 // 2^32), and are hashed and counted into the next build's cells as there.
-// One lane per target walks the target's candidate list (ade_walk.h); the
-// candidates are read from the structure-of-arrays state.
+// One lane per target walks the target's candidate list (ade_walk.h).  Each
+// particle carries the reciprocals of its tensor components, so a harmonic
+// mean costs one add and one reciprocal; in 2D FP32 a candidate is one
+// 32-byte record, elsewhere it is read from the structure-of-arrays state.
 #include <hip/hip_ext.h>
 
 #include "ade_walk.h"
 
 namespace ade {
 
+#ifndef ADE_GEN_BATCH
+#define ADE_GEN_BATCH 2
+#endif
+constexpr int kGenBatch = ADE_GEN_BATCH;  // candidates per lane per batch of the walk
+
 template <int DIM>
 struct GenDims {
     static constexpr int kT = DIM == 2 ? 3 : 6;  // tensor components stored per particle
 };
+// whether stored component k is on the diagonal
+template <int DIM>
+__host__ __device__ constexpr bool is_diag(int k) {
+    return DIM == 2 ? (k == 0 || k == 2) : (k == 0 || k == 3 || k == 5);
+}
 
 // Eq. (3) for velocity v: the stored components (2D: xx, xy, yy; 3D: xx,
 // xy, xz, yy, yz, zz)
@@ -52,7 +64,8 @@ __host__ __device__ inline void tensor_of(double aL, double aT, double Dm, const
 
 // Velocities (double, SoA dim x N in id order) into the hashed buffer U,
 // which after ade_init_particles holds particle a at index a, with the
-// tensors they give.
+// reciprocals of the tensor components they give (the pair term needs only
+// those: see hmean).
 template <int DIM, typename real>
 __global__ __launch_bounds__(kTile) void k_setvel(const PlumeDev* __restrict__ plumes,
                                                  const TileDev* __restrict__ tiles,
@@ -70,25 +83,69 @@ __global__ __launch_bounds__(kTile) void k_setvel(const PlumeDev* __restrict__ p
     // moves and the tensors see the same velocity
     for (int c = 0; c < DIM; ++c) va[c] = (double)(real)va[c];
     tensor_of<DIM>(P.aL, P.aT, P.Dm, va, Dt);
-    for (int k = 0; k < GenDims<DIM>::kT; ++k) static_cast<real*>(U.Dt[k])[a] = (real)Dt[k];
+    for (int k = 0; k < GenDims<DIM>::kT; ++k) {
+        // a diagonal component is at least min(alpha_L, alpha_T) |v| + D_m
+        // >= 0; a rounding below 0 is taken as 0, so its reciprocal is
+        // positive (or +inf)
+        const double d = is_diag<DIM>(k) ? fmax(Dt[k], 0.0) : Dt[k];
+        static_cast<real*>(U.rD[k])[a] = (real)(1.0 / d);
+    }
 }
 
+// One particle as the pair term reads it: position, C, velocity and the
+// reciprocals of its tensor components.
 template <int DIM, typename real>
-struct GCand {
+struct GPart {
     uint32_t x, y, z;
     real C;
     real v[DIM];
-    real D[GenDims<DIM>::kT];
+    real r[GenDims<DIM>::kT];
 };
 
-__device__ __forceinline__ float harm4(float p, float q) {
-    const float pq = p * q;
-    return pq > 0.f ? 4.f * pq / (p + q) : 0.f;
+// 2D FP32 reads the particle's 32-byte record, the other cases the
+// structure-of-arrays state.
+template <int DIM, typename real>
+__device__ __forceinline__ GPart<DIM, real> load_part(const StateArrays& S, uint32_t k) {
+    GPart<DIM, real> p;
+    if constexpr (DIM == 2 && sizeof(real) == 4) {
+        const uint4 a = S.grec[2 * (size_t)k], b = S.grec[2 * (size_t)k + 1];
+        p.x = a.x;
+        p.y = a.y;
+        p.z = 0u;
+        p.C = __uint_as_float(a.z);
+        p.v[0] = __uint_as_float(a.w);
+        p.v[1] = __uint_as_float(b.x);
+        p.r[0] = __uint_as_float(b.y);
+        p.r[1] = __uint_as_float(b.z);
+        p.r[2] = __uint_as_float(b.w);
+    } else {
+        p.x = S.pos[0][k];
+        p.y = S.pos[1][k];
+        p.z = (DIM == 3) ? S.pos[2][k] : 0u;
+        p.C = static_cast<const real*>(S.C)[k];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) p.v[d] = static_cast<const real*>(S.vel[d])[k];
+#pragma unroll
+        for (int q = 0; q < GenDims<DIM>::kT; ++q) p.r[q] = static_cast<const real*>(S.rD[q])[k];
+    }
+    return p;
 }
-__device__ __forceinline__ double harm4(double p, double q) {
-    const double pq = p * q;
-    return pq > 0.0 ? 4.0 * pq / (p + q) : 0.0;
+
+// A quarter of the harmonic mean of Eq. (5) from the reciprocals of the two
+// components: 4 p q / (p + q) = 4 / (1/p + 1/q) when p q > 0, and 0 when
+// p q <= 0 (a product of reciprocals has the sign of p q; a zero component
+// has an infinite reciprocal, whose product is not positive against the other
+// sign and whose sum gives 0 against the same sign).
+__device__ __forceinline__ float hmean(float ra, float rb) {
+    return ra * rb > 0.f ? __builtin_amdgcn_rcpf(ra + rb) : 0.f;
 }
+__device__ __forceinline__ double hmean(double ra, double rb) {
+    return ra * rb > 0.0 ? 1.0 / (ra + rb) : 0.0;
+}
+// the same for diagonal components, whose reciprocals are positive or +inf:
+// the sum is never NaN and 1 / inf = 0 covers a zero component
+__device__ __forceinline__ float hmean_diag(float ra, float rb) { return __builtin_amdgcn_rcpf(ra + rb); }
+__device__ __forceinline__ double hmean_diag(double ra, double rb) { return 1.0 / (ra + rb); }
 
 // A work item = blockDim.x consecutive targets of one tile (blockDim.x a
 // divisor of the tile, chosen so the candidate lists fit in LDS).
@@ -106,17 +163,8 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
     const uint32_t i = active ? i0 + threadIdx.x : i0;
 
     const StateArrays& S = g.S;
-    const uint32_t* __restrict__ px = S.pos[0];
-    const uint32_t* __restrict__ py = S.pos[1];
-    const uint32_t* __restrict__ pz = S.pos[2];
-    const real* __restrict__ C = static_cast<const real*>(S.C);
-    const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
-    const real Ca = C[i];
-    real va[DIM], Da[NT];
-#pragma unroll
-    for (int c = 0; c < DIM; ++c) va[c] = static_cast<const real*>(S.vel[c])[i];
-#pragma unroll
-    for (int k = 0; k < NT; ++k) Da[k] = static_cast<const real*>(S.Dt[k])[i];
+    const GPart<DIM, real> A = load_part<DIM, real>(S, i);
+    const Target T = make_target<DIM>(P, A.x, A.y, A.z);
 
     uint2* list = lds_list + threadIdx.x;
     uint32_t total = 0;
@@ -126,20 +174,8 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
     const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
     const real gam = (real)(DIM + 2);
     real disp = 0, conv = 0;
-    auto fetch = [&](uint32_t k) {
-        k /= kRecBytes;
-        GCand<DIM, real> c;
-        c.x = px[k];
-        c.y = py[k];
-        c.z = (DIM == 3) ? pz[k] : 0u;
-        c.C = C[k];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) c.v[d] = static_cast<const real*>(S.vel[d])[k];
-#pragma unroll
-        for (int q = 0; q < NT; ++q) c.D[q] = static_cast<const real*>(S.Dt[q])[k];
-        return c;
-    };
-    auto eval = [&](const GCand<DIM, real>& c, bool keep) {
+    auto fetch = [&](uint32_t k) { return load_part<DIM, real>(S, k / kRecBytes); };
+    auto eval = [&](const GPart<DIM, real>& c, bool keep) {
         const real dx = (real)(int32_t)(T.ux - c.x);
         const real dy = (real)(int32_t)(T.uy - c.y);
         const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - c.z) : (real)0;
@@ -162,49 +198,54 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
         // and f = 0, so the terms vanish
         f = in ? f : (real)0;
         const real ir2 = in ? rinv * rinv : (real)0;
+        // the pair's harmonic-mean tensor h, divided by 4
         real quad, tr;
         if (DIM == 2) {
-            const real hxx = harm4(Da[0], c.D[0]), hxy = harm4(Da[1], c.D[1]), hyy = harm4(Da[2], c.D[2]);
+            const real hxx = hmean_diag(A.r[0], c.r[0]), hxy = hmean(A.r[1], c.r[1]);
+            const real hyy = hmean_diag(A.r[2], c.r[2]);
             quad = fmar(hxx * dx, dx, fmar((real)2 * hxy * dx, dy, hyy * dy * dy));
             tr = hxx + hyy;
         } else {
-            const real hxx = harm4(Da[0], c.D[0]), hxy = harm4(Da[1], c.D[1]), hxz = harm4(Da[2], c.D[2]);
-            const real hyy = harm4(Da[3], c.D[3]), hyz = harm4(Da[4], c.D[4]), hzz = harm4(Da[5], c.D[5]);
+            const real hxx = hmean_diag(A.r[0], c.r[0]), hxy = hmean(A.r[1], c.r[1]), hxz = hmean(A.r[2], c.r[2]);
+            const real hyy = hmean_diag(A.r[3], c.r[3]), hyz = hmean(A.r[4], c.r[4]);
+            const real hzz = hmean_diag(A.r[5], c.r[5]);
             quad = hxx * dx * dx + hyy * dy * dy + hzz * dz * dz +
                    (real)2 * (hxy * dx * dy + hxz * dx * dz + hyz * dy * dz);
             tr = hxx + hyy + hzz;
         }
-        const real dcal = fmar(gam * quad, ir2, -tr);
-        disp = fmar((real)0.5 * dcal * f, Ca - c.C, disp);
-        real vx = (va[0] - c.v[0]) * dx + (va[1] - c.v[1]) * dy;
-        if (DIM == 3) vx = fmar(va[DIM - 1] - c.v[DIM - 1], dz, vx);
+        const real dcal = fmar(gam * quad, ir2, -tr);  // Dcal / 4
+        disp = fmar(dcal * f, A.C - c.C, disp);
+        real vx = (A.v[0] - c.v[0]) * dx;
+        vx = fmar(A.v[1] - c.v[1], dy, vx);
+        if (DIM == 3) vx = fmar(A.v[DIM - 1] - c.v[DIM - 1], dz, vx);
         conv = fmar(f, vx, conv);
     };
-    walk_stream<4>(list, tpb, total, i, fetch, eval);
+    walk_stream<kGenBatch>(list, tpb, total, i, fetch, eval);
     if (!active) return;
 
-    // x_ab of the convective term in grid units: L / 2^32 per unit
-    const real rhs = (real)P.vphi * fmar(Ca * (real)(P.L * (1.0 / 4294967296.0)), conv, disp);
+    // 1/2 of the sum of Dcal terms = 2 disp (disp sums Dcal / 4); x_ab of the
+    // convective term is in grid units, L / 2^32 each
+    const real rhs = (real)P.vphi * fmar(A.C * (real)(P.L * (1.0 / 4294967296.0)), conv, (real)2 * disp);
     if (MODE == kModeRhs) {
         static_cast<real*>(g.out)[S.id[i]] = rhs;
         return;
     }
     // step: C, the move on the particle's own schedule, hashing and counting
     const StateArrays& U = g.U;
-    static_cast<real*>(U.C)[i] = fmar((real)P.dt, rhs, Ca);
+    static_cast<real*>(U.C)[i] = fmar((real)P.dt, rhs, A.C);
     const int64_t k = *g.step;
     uint32_t u[3] = {T.ux, T.uy, T.uz};
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
-        const double us = (double)va[c] * P.dt / P.L * 4294967296.0;
+        const double us = (double)A.v[c] * P.dt / P.L * 4294967296.0;
         const int64_t s1 = (int64_t)rint((double)(k + 1) * us);
         const int64_t s0 = (int64_t)rint((double)k * us);
         u[c] += (uint32_t)(s1 - s0);
         U.pos[c][i] = u[c];
-        static_cast<real*>(U.vel[c])[i] = va[c];
+        static_cast<real*>(U.vel[c])[i] = A.v[c];
     }
 #pragma unroll
-    for (int q = 0; q < NT; ++q) static_cast<real*>(U.Dt[q])[i] = Da[q];
+    for (int q = 0; q < NT; ++q) static_cast<real*>(U.rD[q])[i] = A.r[q];
     const uint32_t id = S.id[i];
     U.id[i] = id;
     const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
@@ -228,6 +269,7 @@ static hipError_t launch_gen_t(int mode, const GenLaunch& g, hipStream_t s) {
     while (block > 64 && (size_t)block * (size_t)g.list_cap * 8u > kPairLdsMax) block /= 2;
     const size_t shm = (size_t)block * (size_t)g.list_cap * 8u;
     if (shm > kPairLdsMax) return hipErrorInvalidValue;
+    if (DIM == 2 && sizeof(real) == 4 && !g.S.grec) return hipErrorInvalidValue;
     dim3 gr(g.ntiles * (kTile / block)), b(block);
     auto kern = (mode == kModeStep) ? k_pair_gen<DIM, real, KERN, kModeStep> : k_pair_gen<DIM, real, KERN, kModeRhs>;
     if (g.ev0)  // timed launch: the events carry the kernel's own start and end stamps
