@@ -271,6 +271,46 @@ def velocity_field(device, steps=50, warmup=3):
     return out
 
 
+def paper_scale(device, steps=3):
+    """The paper-scale problems of Table 1: 10^6 particles with ~31k neighbours
+    each (autotuned) and 4x10^6 with ~78k (the default launch shape of such
+    plumes), FP32, eager steps with the pair kernel timed by HIP events."""
+    import numpy as np
+    import torch
+    from paper_2108_09488_amd import inputs as I
+    from paper_2108_09488_amd.context import Context, params_from_spec
+
+    out = {}
+    for name, tune in (("paper1m", True), ("paper4m", False)):
+        s = I.config(name)
+        stream = torch.cuda.Stream(device=device)
+        c = Context([params_from_spec(s)], [s.n], device=device, stream=stream)
+        x = s.positions()
+        c.init(torch.from_numpy(x), torch.from_numpy(s.concentration(x).astype(np.float32))).build()
+        inter = int(c.neighbour_counts()[-1].item())
+        tuning = c.autotune(reps=1) if tune else c.get_tuning()
+        c.step(1)
+        _sync()
+        c.timing_start()
+        t0 = time.perf_counter()
+        c.step(steps)
+        _sync()
+        wall = time.perf_counter() - t0
+        ms, n = c.timing_stop()
+        cells = c.info()["cells"]
+        c.close()
+        achieved = FLOPS_PER_INTERACTION[2] * inter / (ms / n * 1e-3) / 1e12
+        out[name] = {"particles": s.n, "neighbours_mean": inter / s.n, "interactions_per_step": inter,
+                     "cells": cells, "steps": steps, "tuning": tuning, "ms_per_step": 1e3 * wall / steps,
+                     "pair_kernel_ms": ms / n, "interactions_per_s": inter * steps / wall,
+                     "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
+                                  "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS}}
+        _sync()
+        print(f"[bench] {name}: {out[name]['ms_per_step']:.1f} ms/step, "
+              f"{out[name]['interactions_per_s']:.3e} interactions/s", file=sys.stderr, flush=True)
+    return out
+
+
 def cpu_baseline(cells, budget_s=20.0):
     """The FP64 oracle on the host cores: one explicit step of each plume of
     the sweep (full 512^2 size), repeated while within the time budget."""
@@ -308,7 +348,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip graph replay and batched runs")
-    ap.add_argument("--extras", default="batched,fwd_adjoint,single_3d,velocity_field",
+    ap.add_argument("--extras", default="batched,fwd_adjoint,single_3d,velocity_field,paper_scale",
                     help="comma-separated extras to run (unless --no-extras)")
     ap.add_argument("--cells", default="", help="comma-separated subset of the sweep plumes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -362,6 +402,8 @@ def main():
     if "single_3d" in want:
         extras["single_3d"] = single_3d(device)
         print(f"[bench] 3D: {extras['single_3d']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+    if "paper_scale" in want:
+        extras["paper_scale"] = paper_scale(device)
     if "velocity_field" in want:
         vf = velocity_field(device, steps=min(args.steps, 100))
         extras["velocity_field"] = vf

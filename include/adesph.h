@@ -110,9 +110,11 @@ typedef struct {
  * depend on lanes and targets and on nothing else here.  A new context starts
  * with the fewest lanes per particle that keep about 4 wavefronts per SIMD:
  * block 64 with two targets per lane from 2^19 particles on, else 256
- * threads with 1 (from 2^18), 2 (from 2^17) or 4 lanes per target; when
- * the lists do not fit, the first of {256,2}, {256,4}, {128,4}, {64,4}
- * lanes per target that does. */
+ * threads with 1 (from 2^18), 2 (from 2^17) or 4 lanes per target; a
+ * context with a plume of more than 2000 expected neighbours per particle
+ * starts with block 128, 4 lanes per target, xcd_group 128; when the lists
+ * do not fit, the first of {256,2}, {256,4}, {128,4}, {64,4} lanes per
+ * target that does. */
 typedef struct {
     int32_t block;          /* threads per workgroup: 64, 128 or 256          */
     int32_t lanes;          /* lanes per target particle: 1, 2 or 4           */

@@ -160,6 +160,13 @@ class Context:
         check(lib().ade_neighbours(self._h, _ptr(offsets), _ptr(ids), need.value, ct.byref(need)))
         return self._out(offsets), self._out(ids)[: need.value]
 
+    def neighbour_counts(self) -> torch.Tensor:
+        """offsets (N+1,) int64 of the neighbour lists (id order), without the ids."""
+        offsets = self._empty(self.N + 1, dtype=torch.int64)
+        need = ct.c_int64(0)
+        check(lib().ade_neighbours(self._h, _ptr(offsets), None, 0, ct.byref(need)))
+        return self._out(offsets)
+
     def sensor_interp(self, xs: torch.Tensor) -> torch.Tensor:
         xs = xs.to(self.device, torch.float64).contiguous()
         self._inputs_ready(xs)

@@ -32,14 +32,17 @@ __device__ __forceinline__ uint32_t xcd_item(uint32_t x, uint32_t m, uint32_t n,
     return t < n ? t : n;
 }
 
-// Cell of a fixed-point position: rows of the (y[, z]) grid, x cells inside a row.
+// Cell of a fixed-point position: rows of the (y[, z]) grid, x cells inside a
+// row, sub-rows (in y) inside an x cell; the position inside the row is the
+// low word of uy * nr.
 template <int DIM>
 __device__ __forceinline__ uint32_t cell_key(const PlumeDev& P, uint32_t ux, uint32_t uy,
                                              uint32_t uz) {
     const uint32_t fx = __umulhi(ux, P.nfx);
     const uint32_t ry = __umulhi(uy, P.nr);
     const uint32_t rz = (DIM == 3) ? __umulhi(uz, P.nr) : 0u;
-    return P.cbase + (rz * P.nr + ry) * P.nfx + fx;
+    const uint32_t sy = __umulhi(uy * P.nr, P.nsub);
+    return P.cbase + ((rz * P.nr + ry) * P.nfx + fx) * P.nsub + sy;
 }
 
 // Counting pass: count the particle with this id in its cell and record the

@@ -84,7 +84,7 @@ __device__ __forceinline__ bool row_halfwidth(const PlumeDev& P, const Target& T
 
 // First cell of row (yy, zz) of a plume (row indices already wrapped).
 __device__ __forceinline__ uint32_t row_base(const PlumeDev& P, int yy, int zz) {
-    return P.cbase + ((uint32_t)zz * P.nr + (uint32_t)yy) * P.nfx;
+    return P.cbase + ((uint32_t)zz * P.nr + (uint32_t)yy) * P.nfx * P.nsub;
 }
 
 __device__ __forceinline__ int wrap_row(const PlumeDev& P, int y) {
@@ -97,22 +97,22 @@ __device__ __forceinline__ int wrap_row(const PlumeDev& P, int y) {
 // Cells of row `row` under the x window [xlo, xhi] (fixed point, inclusive,
 // xhi - xlo < 2^32 - one cell width as an unsigned difference): k0 .. k1,
 // and k2 .. k3 when the window wraps around the periodic seam (k2 > k3
-// marks it empty).
+// marks it empty).  Whole x cells, every sub-row of each.
 __device__ __forceinline__ void window_cells(const PlumeDev& P, uint32_t row, uint32_t xlo, uint32_t xhi,
                                              uint32_t& k0, uint32_t& k1, uint32_t& k2, uint32_t& k3) {
-    const uint32_t nfx = P.nfx;
+    const uint32_t nfx = P.nfx, ns = P.nsub;
     const uint32_t clo = __umulhi(xlo, nfx);
     const uint32_t chi = __umulhi(xhi, nfx);
     if (clo <= chi) {
-        k0 = row + clo;
-        k1 = row + chi;
+        k0 = row + clo * ns;
+        k1 = row + chi * ns + ns - 1u;
         k2 = 1u;
         k3 = 0u;
     } else {
-        k0 = row + clo;
-        k1 = row + nfx - 1u;
+        k0 = row + clo * ns;
+        k1 = row + nfx * ns - 1u;
         k2 = row;
-        k3 = row + chi;
+        k3 = row + chi * ns + ns - 1u;
     }
 }
 

@@ -26,7 +26,8 @@ struct PlumeDev {
     int32_t R;              // rows to each side that can hold neighbours
     uint32_t hx;            // half-width of the x search window (>= H_u (1 + 2^-16))
     uint32_t tfirst, tcount;// tiles of this plume
-    uint32_t pad0, pad1;
+    uint32_t nsub;          // sub-rows per row (cells of a row: nfx x-cells of nsub sub-rows each)
+    uint32_t pad1;
     double Hu;              // support radius in grid units
     double H2d;             // Hu^2 (double)
     float H2f;              // Hu^2 rounded to float

@@ -167,11 +167,24 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         if (nr < 3 || nfx < 3) return fail(ADE_EINVAL, "plume %d: box holds fewer than 3 cells", p);
         int R = (int)std::ceil(Hc * nr / kTwo32);
         if (2 * R + 1 > nr) return fail(ADE_EINVAL, "plume %d: cell rows overlap (H too large)", p);
+        // A support radius holding thousands of particles leaves these cells
+        // with hundreds each, far past their buckets.  Then (2D) the x cells
+        // are narrowed and every row is split into sub-rows, to near-square
+        // cells of about two particles, so that a lattice puts one or two of
+        // its rows and columns in a cell.  Candidate windows still take whole
+        // x cells, so the candidates of a row stay one contiguous range.
+        double nsub = 1.0;
+        if (pl.dim == 2 && (double)counts[p] / (nr * nfx) > 4.0) {
+            const double side = std::sqrt(2.0 / (double)counts[p]);  // of a two-particle cell, in box units
+            nfx = std::max(nfx, std::floor(1.0 / side));
+            nsub = std::max(1.0, std::floor(1.0 / nr / side));
+        }
         d.nr = (uint32_t)nr;
         d.nfx = (uint32_t)nfx;
+        d.nsub = (uint32_t)nsub;
         d.R = R;
         d.hx = (uint32_t)std::ceil(Hc) + 1u;
-        d.ncell = (uint32_t)(std::pow(nr, pl.dim - 1) * nfx);
+        d.ncell = (uint32_t)(std::pow(nr, pl.dim - 1) * nfx * nsub);
         d.cbase = (uint32_t)cbase;
         cbase += d.ncell;
         if (cbase >= 0xffffffffull) return fail(ADE_EINVAL, "too many cells");
@@ -266,6 +279,7 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
             const ade_params& q = params[p];
             const double vol = (pl.dim == 2) ? kPi * q.H * q.H : 4.0 / 3.0 * kPi * q.H * q.H * q.H;
             cost.emplace_back(-(double)counts[p] * vol / std::pow(q.L, pl.dim), p);
+            pl.nbar_max = std::max(pl.nbar_max, -cost.back().first);
         }
         std::stable_sort(cost.begin(), cost.end());
         pl.pair_tiles.clear();
@@ -504,18 +518,24 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
         delete c;
         return rc;
     }
-    // default launch shape: the fewest lanes per particle that still give
-    // the chip about 4 wavefronts per SIMD (4096 wavefronts of 64 lanes, i.e.
-    // 2^18 lanes): two targets per lane from 2^19 particles on (the fastest
-    // shape on the 2D sweep), one lane per target from 2^18, two lanes from
-    // 2^17, else four; then the next shapes whose candidate lists fit in LDS
+    // the velocity-field kernel's lists (one target per lane, at least 64 per workgroup)
     if (c->plan.general && (size_t)64 * (size_t)c->plan.list_cap * 8u > kPairLdsMax) {
         delete c;
         return fail(ADE_EINVAL, "too many neighbour rows: the candidate lists do not fit in LDS");
     }
+    // default launch shape: the fewest lanes per particle that still give
+    // the chip about 4 wavefronts per SIMD (4096 wavefronts of 64 lanes, i.e.
+    // 2^18 lanes): two targets per lane from 2^19 particles on (the fastest
+    // shape on the 2D sweep), one lane per target from 2^18, two lanes from
+    // 2^17, else four; then the next shapes whose candidate lists fit in LDS.
+    // Plumes of thousands of neighbours per particle take four lanes per
+    // target: the 16 targets of a wavefront then walk nearly the same
+    // candidate ranges and share their cache lines (the autotuner's choice on
+    // the 10^6-particle, 31k-neighbour problem).
     {
         const int64_t N = c->plan.N;
-        const ade_tuning first = N >= (1 << 19)   ? ade_tuning{64, 1, 0, 0, 2}
+        const ade_tuning first = c->plan.nbar_max > 2000.0 ? ade_tuning{128, 4, 128, 0, 1}
+                                 : N >= (1 << 19)          ? ade_tuning{64, 1, 0, 0, 2}
                                  : N >= (1 << 18) ? ade_tuning{256, 1, 0, 0, 1}
                                  : N >= (1 << 17) ? ade_tuning{256, 2, 0, 0, 1}
                                                   : ade_tuning{256, 4, 0, 0, 1};

@@ -30,6 +30,7 @@ struct Plan {
     uint32_t ntiles = 0, nscan = 0;
     int list_cap = 0;       // candidate-list entries per target (largest plume)
     int list_cap_pair = 0;  // the same for a lane's merged list of two targets
+    double nbar_max = 0.0;  // largest expected neighbours per particle of a plume
     bool general = false;   // velocity field: per-particle velocities (ADE_VELOCITY_FIELD)
     std::vector<PlumeDev> plumes;
     std::vector<TileDev> tiles;

@@ -348,7 +348,7 @@ __device__ __forceinline__ RowRanges union_row(const PlumeDev& P, const uint32_t
     uint32_t k0, k1, k2, k3;
     if (hi - lo >= (int64_t)4294967296ll - (int64_t)(4294967296ull / P.nfx) - 2) {  // the whole row
         k0 = row;
-        k1 = row + P.nfx - 1u;
+        k1 = row + P.nfx * P.nsub - 1u;
         k2 = 1u;
         k3 = 0u;
     } else {

@@ -217,6 +217,8 @@ def config(name: str, **over) -> PlumeSpec:
              alpha_L/alpha_T in {10, 100}, 1000 steps, dt from Eq. (10).
     cfg3     3D FP32, 128^3 jittered lattice, C4, h = 2 dp, 500 steps of 5e-5.
     cfg5     2D FP32, 256^2 regular lattice, C4, h = 1.5 dp, 500 steps of 1e-4 (adjoint problem).
+    paper*   2D FP32, the paper-scale problems of Table 1 (1000^2, 1414^2, 2000^2 particles,
+             31.5k-80k neighbours, jitter +-0.1 dp), dt from Eq. (10), 300 days.
     """
     if name == "cfg1":
         s = PlumeSpec(dim=2, n_side=64, jitter=0.0, h_over_dp=1.3, kernel=2, alpha_L=1e-2,
@@ -235,6 +237,22 @@ def config(name: str, **over) -> PlumeSpec:
         s = PlumeSpec(dim=3, n_side=128, jitter=0.1, h_over_dp=2.0, kernel=4, alpha_L=1e-2,
                       alpha_T=1e-3, D_m=1e-6, v=(1.0, 0.0, 0.0), sigma0=0.05,
                       centre=(0.25, 0.5, 0.5), dt=5e-5, steps=500, real_bytes=4, name=name)
+    elif name.startswith("paper"):
+        # Table 1 resolutions: N = 1M, 2M, 4M particles with support radius
+        # H/L = 0.099, 0.089, 0.079 (Table 1's h/L column, read as the support
+        # radius: pi (H/L)^2 N reproduces its neighbour counts 31529, 50339,
+        # 80371 to 2.5%); Section 3 model: L = 2000 m, plume centred, w = 44 m,
+        # alpha_L = 10 m, alpha_T/alpha_L = 0.1 (paper1m_r100, _r1000: 0.01,
+        # 0.001), D_m = 0, |v| = 1.16e-5 m/s at 45 degrees, 300 days.
+        parts = name.split("_")
+        side, HL = {"paper1m": (1000, 0.099), "paper2m": (1414, 0.089), "paper4m": (2000, 0.079)}[parts[0]]
+        ratio = {"r10": 10.0, "r100": 100.0, "r1000": 1000.0}[parts[1] if len(parts) > 1 else "r10"]
+        vv = 1.16e-5 * math.sqrt(0.5)
+        s = PlumeSpec(dim=2, n_side=side, L=2000.0, jitter=0.1, h_over_dp=HL * side / 2.0, kernel=4,
+                      alpha_L=10.0, alpha_T=10.0 / ratio, D_m=0.0, v=(vv, vv, 0.0), sigma0=44.0,
+                      centre=(1000.0, 1000.0, 1000.0), real_bytes=4, name=name)
+        s.dt = eq10_dt(s)
+        s.steps = int(math.ceil(300 * 86400.0 / s.dt))
     elif name == "cfg5":
         s = PlumeSpec(dim=2, n_side=256, jitter=0.0, h_over_dp=1.5, kernel=4, alpha_L=2e-2,
                       alpha_T=2e-3, D_m=1e-6, v=(1.0, 0.0, 0.0), sigma0=0.05,

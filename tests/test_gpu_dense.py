@@ -1,0 +1,132 @@
+"""The paper-scale regime (Table 1: a support radius holding 30k-80k
+particles) and smaller problems of the same shape (H = 0.099 L, hundreds of
+neighbours), through the C ABI against the FP64 CPU oracle.
+
+Such plumes get x cells narrowed and rows split into sub-rows (cells of about
+two particles).  Tolerances as for the other problems: neighbour sets
+bit-exact; FP64 1e-12 and FP32 1e-5 relative L2.  The FP32 sums run over
+hundreds to 31.5k terms; each adds a rounding, a random walk of about
+sqrt(n) u (u = 2^-24) relative to the size of the terms: 2e-6 at n = 31.5k.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2108_09488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+TWO32 = 4294967296.0
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def _dense(n_side, real_bytes=4, HL=0.099):
+    """The paper's plume at a smaller particle count, same support radius in box units."""
+    return I.config("paper1m", n_side=n_side, h_over_dp=HL * n_side / 2.0, real_bytes=real_bytes)
+
+
+def _ctx(spec):
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    print(f"[case] dense {spec.name} n_side={spec.n_side} h/dp={spec.h_over_dp:.2f} rb={spec.real_bytes}",
+          flush=True)
+    ctx = Context([params_from_spec(spec)], [spec.n])
+    x = spec.positions()
+    C = spec.concentration(x)
+    if spec.real_bytes == 4:
+        C = C.astype(np.float32).astype(np.float64)
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+    return ctx, x, C
+
+
+def _sets(offsets, ids):
+    offsets = np.asarray(offsets, dtype=np.int64)
+    ids = np.asarray(ids, dtype=np.int64)
+    seg = np.repeat(np.arange(len(offsets) - 1), np.diff(offsets))
+    return offsets, ids[np.lexsort((ids, seg))]
+
+
+@pytest.mark.parametrize("n_side,rb", [(160, 4), (150, 8)])
+def test_dense_neighbour_sets_bit_exact(n_side, rb):
+    spec = _dense(n_side, rb)
+    ctx, x, _ = _ctx(spec)
+    info = ctx.info()
+    assert info["cells"] <= spec.n  # sub-rows engaged: about two particles per cell
+    off, ids = ctx.neighbours()
+    g_off, g_ids = _sets(off.cpu().numpy(), ids.cpu().numpy())
+    o_off, o_ids = O.neighbours_fixed(2, x, spec.L, spec.H, rb)
+    assert np.array_equal(g_off, o_off) and np.array_equal(g_ids, o_ids)
+    assert g_off[-1] / spec.n > 600
+    k = 3
+    ctx.step(k)
+    off, ids = ctx.neighbours()
+    g_off, g_ids = _sets(off.cpu().numpy(), ids.cpu().numpy())
+    u = O.to_fixed(x, spec.L).astype(np.int64)
+    v = spec.velocity()
+    xk = np.empty_like(x)
+    for c in range(2):
+        s = int(np.rint(k * spec.dt * v[c] / spec.L * TWO32))
+        xk[c] = np.mod(u[c] + s, 1 << 32).astype(np.float64) / TWO32 * spec.L
+    o_off, o_ids = O.neighbours_fixed(2, xk, spec.L, spec.H, rb)
+    assert np.array_equal(g_off, o_off) and np.array_equal(g_ids, o_ids)
+    ctx.close()
+
+
+@pytest.mark.parametrize("n_side,rb", [(150, 8), (160, 4), (129, 4)])
+def test_dense_rhs_parity(n_side, rb):
+    spec = _dense(n_side, rb)
+    ctx, x, C = _ctx(spec)
+    g = ctx.rhs().double().cpu().numpy()
+    r = O.rhs(O.model_from_spec(spec), x, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+    e = _rel(g, r)
+    print(f"[dense rhs] n_side={n_side} rb={rb} rel L2 {e:.3e}", flush=True)
+    assert e < (1e-12 if rb == 8 else 1e-5)
+    ctx.close()
+
+
+def test_dense_fp64_trajectory_and_mass():
+    spec = _dense(120, 8)
+    ctx, x, C0 = _ctx(spec)
+    m0 = ctx.mass().cpu().numpy()[0]
+    steps = 4
+    ctx.step(steps)
+    C = ctx.read_C().cpu().numpy()
+    m1 = ctx.mass().cpu().numpy()[0]
+    _, Co, _ = O.run(O.model_from_spec(spec), x, C0, spec.dt, steps, v_uniform=spec.velocity(),
+                     mass=spec.mass, rho=spec.rho0)
+    assert _rel(C, Co) < 1e-12
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
+    ctx.close()
+
+
+def test_paper_scale_sampled():
+    """Table 1's first resolution at full size: 10^6 particles, ~31.5k
+    neighbours each.  The neighbour count matches the table, the right-hand
+    side matches the oracle at a seeded sample inside the plume, and one step
+    moves every particle by the exact fixed-point shift."""
+    spec = I.config("paper1m")
+    ctx, x, C = _ctx(spec)
+    off = ctx.neighbour_counts().cpu().numpy()
+    nbar = off[-1] / spec.n
+    print(f"[paper1m] mean neighbours {nbar:.1f}, cells {ctx.info()['cells']}", flush=True)
+    assert abs(nbar - 31529) < 0.03 * 31529
+    g = ctx.rhs().double().cpu().numpy()
+    rng = np.random.default_rng(13)
+    inside = np.flatnonzero(C > 1e-3)
+    idx = np.sort(rng.choice(inside, size=1500, replace=False))
+    r = O.rhs(O.model_from_spec(spec), x, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0, idx=idx)
+    e = _rel(g[idx], r)
+    print(f"[paper1m] rhs rel L2 over the sample {e:.3e}", flush=True)
+    assert e < 1e-5
+    ctx.step(1)
+    xg = ctx.read_x().cpu().numpy()
+    u0 = O.to_fixed(x, spec.L).astype(np.int64)
+    for c in range(2):
+        s = int(np.rint(spec.dt * spec.velocity()[c] / spec.L * TWO32))
+        assert np.array_equal(xg[c], np.mod(u0[c] + s, 1 << 32).astype(np.float64) / TWO32 * spec.L)
+    ctx.close()
