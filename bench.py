@@ -49,18 +49,19 @@ def step_kernel_name(tuning):
     return f"k_pair<2, float, 4, 0, {tuning['lanes']}>"
 
 
-def pair_traffic(kernel):
-    """HBM bytes per pair-kernel launch from the committed FETCH_SIZE/WRITE_SIZE
-    profile, or None when the kernel sources changed since it was taken or the
-    profile covers another launch shape's kernel."""
+def pair_profile(kernel, key="traffic_bytes_per_launch"):
+    """A figure of the pair kernel from the committed counter profile (HBM
+    bytes per launch from FETCH_SIZE/WRITE_SIZE, or the L2 and L1 hit rates),
+    or None when the kernel sources changed since it was taken or the profile
+    covers another launch shape's kernel."""
     import hashlib
     try:
         text = open(TRAFFIC_PROFILE).read()
     except OSError:
         return None
     vals = dict(l.split(":", 1) for l in text.splitlines()
-                if l.startswith(("traffic_bytes_per_launch:", "source_sha256:", "kernel:")))
-    if vals.get("kernel", "").strip() != kernel:
+                if l.startswith((key + ":", "source_sha256:", "kernel:")))
+    if vals.get("kernel", "").strip() != kernel or key not in vals:
         return None
     h = hashlib.sha256()
     for f in PAIR_SOURCES:
@@ -68,7 +69,11 @@ def pair_traffic(kernel):
             h.update(fh.read())
     if vals.get("source_sha256", "").strip() != h.hexdigest():
         return None
-    return float(vals["traffic_bytes_per_launch"])
+    return float(vals[key])
+
+
+def pair_traffic(kernel):
+    return pair_profile(kernel, "traffic_bytes_per_launch")
 
 
 def _sync():
@@ -438,7 +443,9 @@ def main():
                      "kernel": step_kernel_name(sweep["tuning"]) + " (update mode)", "avg_launch_ms": avg_ms,
                      "launches": pair["launches"],
                      "flops_per_interaction": FLOPS_PER_INTERACTION[2],
-                     "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS},
+                     "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                     "l2_hit_rate": pair_profile(step_kernel_name(sweep["tuning"]), "l2_hit_rate"),
+                     "l1_hit_rate": pair_profile(step_kernel_name(sweep["tuning"]), "l1_hit_rate")},
         "extras": extras,
     }
     if not args.no_cpu:

@@ -351,10 +351,9 @@ int flush_events(ade_ctx* c) {
 
 namespace ade {
 
-// a pair of timing events from the context's pool, or false when timing is
-// off (or a graph is being captured)
-static int take_events(ade_ctx* c, hipEvent_t& e0, hipEvent_t& e1, bool& took) {
-    took = false;
+// a pair of timing events from the context's pool into e0, e1; they are left
+// as they are when timing is off (or a graph is being captured)
+static int take_events(ade_ctx* c, hipEvent_t& e0, hipEvent_t& e1) {
     if (!c->timing || c->capturing) return ADE_OK;
     if (c->ev_used + 2 > c->events.size()) {
         if (c->events.size() < 4096) {
@@ -368,7 +367,6 @@ static int take_events(ade_ctx* c, hipEvent_t& e0, hipEvent_t& e1, bool& took) {
     }
     e0 = c->events[c->ev_used++];
     e1 = c->events[c->ev_used++];
-    took = true;
     return ADE_OK;
 }
 
@@ -378,8 +376,7 @@ int run_pair(ade_ctx* c, int mode, const PairLaunch& a) {
     const Plan& pl = c->plan;
     PairLaunch b = a;
     b.ev0 = b.ev1 = nullptr;
-    bool took = false;
-    int rc = take_events(c, b.ev0, b.ev1, took);
+    int rc = take_events(c, b.ev0, b.ev1);
     if (rc) return rc;
     HIPCHK(launch_pair(pl.dim, pl.real_bytes, pl.kernel, mode, b, c->tuning.block, c->stream));
     return ADE_OK;
@@ -389,8 +386,7 @@ int run_pair(ade_ctx* c, int mode, const PairLaunch& a) {
 int run_gen(ade_ctx* c, int mode, void* out) {
     const Plan& pl = c->plan;
     GenLaunch g = gen_args(c, out);
-    bool took = false;
-    int rc = take_events(c, g.ev0, g.ev1, took);
+    int rc = take_events(c, g.ev0, g.ev1);
     if (rc) return rc;
     HIPCHK(launch_pair_gen(pl.dim, pl.real_bytes, pl.kernel, mode, g, c->stream));
     return ADE_OK;
