@@ -87,7 +87,8 @@ typedef struct {
                            same on every plume of a context, ADE_EULER and
                            dt > 0 only)                                      */
     int32_t cell_rows;  /* cell grid: rows per support radius in y (and z),
-                           1..4; 0 = default                                */
+                           1..4; 0 = default (2, or 4 for more than 2000
+                           expected neighbours per particle)                */
     int32_t cell_xsub;  /* cell grid: cells per support radius along x,
                            1..16; 0 = default                               */
     int32_t reserved;   /* must be 0                                         */

@@ -155,7 +155,15 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
         // cell grid in grid units: rows of height >= Hc / rows_per_H, x cells of width >= Hc / xsub
         const double Hu = q.H / q.L * kTwo32;
         const double Hc = Hu * (1.0 + 1.0 / 65536.0) + 2.0;
-        const int rsub = q.cell_rows ? q.cell_rows : 2;
+        // expected neighbours per particle (support volume over particle volume)
+        const double nbar = (double)counts[p] *
+                            (pl.dim == 2 ? kPi * q.H * q.H : 4.0 / 3.0 * kPi * q.H * q.H * q.H) /
+                            std::pow(q.L, pl.dim);
+        // rows of H/2, or H/4 for thousands of neighbours per particle, where
+        // the tighter row windows (fewer candidates per neighbour) outweigh
+        // the row work (measured: -6% and -8.5% on the 10^6 and 4x10^6
+        // paper-scale problems)
+        const int rsub = q.cell_rows ? q.cell_rows : (nbar > 2000.0 ? 4 : 2);
         const int xsub = q.cell_xsub ? q.cell_xsub : 8;
         const double cap = std::max(8.0 * (double)counts[p], 4096.0);
         double nr = std::floor(kTwo32 * rsub / Hc);
