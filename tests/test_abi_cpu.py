@@ -102,3 +102,14 @@ def test_create_rejects_null_and_small_workspace():
     assert _lib.lib().ade_create(arr, cn, 1, None, 0, None, ct.byref(out)) == _lib.ADE_EINVAL
     # misaligned pointer is rejected before any device call
     assert _lib.lib().ade_create(arr, cn, 1, ct.c_void_p(0x1001), 1 << 30, None, ct.byref(out)) == _lib.ADE_EINVAL
+
+
+def test_particle_limit_per_context():
+    """A context holds at most 2^28 - 256 particles (32-bit byte offsets of the
+    16-byte candidate records); the plan rejects one more, before any device
+    work."""
+    p = params_from_spec(I.config("cfg2_h20_r10"))
+    lim = (1 << 28) - 256
+    rc, nb = _wsbytes([p, p], [lim // 2, lim - lim // 2])
+    assert rc == 0 and nb > lim * 40
+    assert _wsbytes([p, p], [lim // 2, lim - lim // 2 + 1])[0] == _lib.ADE_EINVAL

@@ -1,0 +1,134 @@
+"""Degenerate cases of the method through the C ABI against the FP64 CPU
+oracle: no flow (D = D_m I, nothing moves), alpha_T > alpha_L (the transverse
+direction dominates, the 2D pair term folds a negative a1), isotropic
+dispersion (alpha_L = alpha_T), D_m = 0, particles of a velocity field with a
+zero tensor (v = 0 and D_m = 0: every harmonic mean with them is 0), and
+plumes of one and of seven particles beside a normal one.  Tolerances: FP64
+1e-12, FP32 1e-5 relative L2 (absolute where the exact answer is 0)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from paper_2108_09488_amd import _lib
+from paper_2108_09488_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+FLOWS = [  # (dim, real_bytes, v, alpha_L, alpha_T, D_m)
+    (2, 8, (0.0, 0.0, 0.0), 1e-2, 1e-3, 1e-6),
+    (2, 4, (0.0, 0.0, 0.0), 1e-2, 1e-3, 1e-6),
+    (2, 8, (0.6, 0.8, 0.0), 1e-3, 1e-2, 1e-6),
+    (2, 4, (1.0, 0.0, 0.0), 1e-3, 2e-2, 0.0),
+    (2, 8, (0.6, -0.8, 0.0), 5e-3, 5e-3, 1e-6),
+    (2, 4, (-0.28, 0.96, 0.0), 2e-2, 2e-3, 0.0),
+    (3, 4, (0.0, 0.0, 0.0), 1e-2, 1e-3, 1e-6),
+    (3, 8, (0.48, 0.6, 0.64), 1e-3, 1e-2, 1e-6),
+]
+
+
+@pytest.mark.parametrize("dim,rb,v,aL,aT,Dm", FLOWS)
+def test_degenerate_flows(dim, rb, v, aL, aT, Dm):
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    base = "cfg1" if dim == 2 else "cfg3"
+    spec = I.config(base, n_side=48 if dim == 2 else 14, real_bytes=rb, kernel=4, h_over_dp=1.5,
+                    jitter=0.1, v=v, alpha_L=aL, alpha_T=aT, D_m=Dm, dt=2.0 ** -14)
+    print(f"[case] flow dim={dim} rb={rb} v={v} aL={aL} aT={aT} Dm={Dm}", flush=True)
+    ctx = Context([params_from_spec(spec)], [spec.n])
+    x = spec.positions()
+    C = spec.concentration(x)
+    if rb == 4:
+        C = C.astype(np.float32).astype(np.float64)
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+    g = ctx.rhs().double().cpu().numpy()
+    m = O.model(dim, 4, spec.H, L=spec.L, alpha_L=aL, alpha_T=aT, D_m=Dm)
+    r = O.rhs(m, x, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+    assert _rel(g, r) < (1e-12 if rb == 8 else 1e-5)
+    steps = 6
+    ctx.step(steps)
+    Cg = ctx.read_C().double().cpu().numpy()
+    xg = ctx.read_x().cpu().numpy()
+    _, Co, _ = O.run(m, x, C, spec.dt, steps, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+    assert _rel(Cg, Co) < (1e-12 if rb == 8 else 1e-5)
+    if not any(v[:dim]):
+        assert np.array_equal(xg, x)  # no flow: nothing moves
+    ctx.close()
+
+
+@pytest.mark.parametrize("rb", [8, 4])
+def test_velocity_field_with_zero_tensors(rb):
+    """With D_m = 0, particles at rest have D = 0: their reciprocals are
+    infinite and every harmonic mean with them vanishes (Eq. 5 with the zero
+    product rule), while the convective term still acts."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = I.config("cfg1", n_side=40, real_bytes=rb, kernel=4, h_over_dp=1.5, jitter=0.1, D_m=0.0,
+                    dt=2.0 ** -12)
+    x = spec.positions()
+    v = I.velocity_field(x, spec.L, quantum=2.0 ** -20)
+    rest = (np.arange(spec.n) % 3) == 0  # every third particle at rest
+    v[:, rest] = 0.0
+    v[1, ~rest & ((np.arange(spec.n) % 3) == 1)] = 0.0  # others along x only: D_xy = 0
+    C = spec.concentration(x)
+    if rb == 4:
+        C = C.astype(np.float32).astype(np.float64)
+    print(f"[case] velocity field with zero tensors rb={rb}", flush=True)
+    ctx = Context([params_from_spec(spec, flags=_lib.ADE_VELOCITY_FIELD)], [spec.n])
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C)).set_velocities(torch.from_numpy(v)).build()
+    g = ctx.rhs().double().cpu().numpy()
+    assert np.all(np.isfinite(g))
+    m = O.model_from_spec(spec)
+    r = O.rhs(m, x, C, v=v, mass=spec.mass, rho=spec.rho0)
+    assert _rel(g, r) < (1e-12 if rb == 8 else 1e-5)
+    ctx.step(5)
+    Cg = ctx.read_C().double().cpu().numpy()
+    xo, Co, _ = O.run(m, x, C, spec.dt, 5, v=v, mass=spec.mass, rho=spec.rho0)
+    assert np.array_equal(ctx.read_x().cpu().numpy(), xo)
+    assert _rel(Cg, Co) < (1e-12 if rb == 8 else 1e-5)
+    ctx.close()
+
+
+def test_tiny_plumes_in_an_ensemble():
+    """Plumes of one particle (no neighbours: rhs 0, C unchanged) and of seven
+    (one ragged tile, a few neighbours) beside a normal plume: each matches the
+    oracle and the normal plume matches itself alone."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    big = I.config("cfg1", n_side=32, real_bytes=8, kernel=4, h_over_dp=1.5)
+    one = I.config("cfg1", n_side=1, real_bytes=8, kernel=4, h_over_dp=0.15)
+    seven = I.config("cfg1", n_side=1, real_bytes=8, kernel=4, h_over_dp=0.15)
+    x_one = np.array([[0.3], [0.7]])
+    # seven particles within H = 0.3 of each other around (0.5, 0.5)
+    ang = np.arange(7) * 2 * np.pi / 7
+    x_seven = I.quantize(np.stack([0.5 + 0.08 * np.cos(ang), 0.5 + 0.08 * np.sin(ang)]), 1.0)
+    x_big = big.positions()
+    C_big = big.concentration(x_big)
+    C_one = np.array([0.8])
+    C_seven = np.linspace(0.1, 0.9, 7)
+    specs = [big, one, seven]
+    xs, Cs, ns = [x_big, x_one, x_seven], [C_big, C_one, C_seven], [big.n, 1, 7]
+    print("[case] tiny plumes", flush=True)
+    ens = Context([params_from_spec(s) for s in specs], ns)
+    ens.init(torch.from_numpy(np.concatenate(xs, axis=1)), torch.from_numpy(np.concatenate(Cs))).build()
+    g = ens.rhs().cpu().numpy()
+    off = 0
+    for s, x, C, n in zip(specs, xs, Cs, ns):
+        r = O.rhs(O.model_from_spec(s), x, C, v_uniform=s.velocity(), mass=s.mass, rho=s.rho0)
+        if n == 1:
+            assert g[off] == 0.0 and r[0] == 0.0
+        else:
+            assert np.max(np.abs(r)) > 0
+            assert _rel(g[off:off + n], r) < 1e-12
+        off += n
+    ens.step(4)
+    Ce = ens.read_C().cpu().numpy()
+    assert Ce[big.n] == C_one[0]
+    alone = Context([params_from_spec(big)], [big.n])
+    alone.init(torch.from_numpy(x_big), torch.from_numpy(C_big)).build()
+    alone.step(4)
+    assert np.array_equal(alone.read_C().cpu().numpy(), Ce[:big.n])
+    alone.close()
+    ens.close()
