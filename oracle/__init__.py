@@ -74,6 +74,11 @@ def lib():
         L.or_adjoint.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, i32, p, p, p]
         L.or_misfit.restype = d
         L.or_misfit.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, i32, p]
+        L.or_rhs_deriv.argtypes = [mp, i64, p, p, p, p, p, i32, p]
+        L.or_apply_LT_field.argtypes = [mp, i64, p, p, p, p, p, p]
+        L.or_adjoint_field.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, p, p, p]
+        L.or_misfit_field.restype = d
+        L.or_misfit_field.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p]
         L.or_num_threads.restype = ct.c_int
         _lib = L
     return _lib
@@ -286,6 +291,50 @@ def misfit(m: Model, x0, C0, v_uniform, dt, nsteps, xs, obs=None, mass=1.0, rho=
     J = lib().or_misfit(ct.byref(m), n, _ptr(x0), _ptr(C0), _ptr(vu), _ptr(m_arr), _ptr(r_arr), dt,
                         nsteps, xs.shape[1], _ptr(xs), _ptr(ob), int(integrator), _ptr(pred))
     return J, pred
+
+
+def rhs_deriv(m: Model, x, C, v, k, mass=1.0, rho=1.0):
+    """L_k C: the derivative of the right-hand side with respect to theta_k
+    (0: alpha_L, 1: alpha_T, 2: D_m) for per-particle velocities v (dim, n)."""
+    x, C, v = _f64(x), _f64(C), _f64(v)
+    n = x.shape[1]
+    m_arr, r_arr = _particle_arrays(n, mass, rho)
+    out = np.zeros(n)
+    lib().or_rhs_deriv(ct.byref(m), n, _ptr(x), _ptr(C), _ptr(v), _ptr(m_arr), _ptr(r_arr), int(k), _ptr(out))
+    return out
+
+
+def apply_LT_field(m: Model, x, lam, v, mass=1.0, rho=1.0):
+    """y = L^T lam for per-particle velocities v (dim, n)."""
+    x, lam, v = _f64(x), _f64(lam), _f64(v)
+    n = x.shape[1]
+    m_arr, r_arr = _particle_arrays(n, mass, rho)
+    y = np.zeros(n)
+    lib().or_apply_LT_field(ct.byref(m), n, _ptr(x), _ptr(v), _ptr(m_arr), _ptr(r_arr), _ptr(lam), _ptr(y))
+    return y
+
+
+def adjoint_field(m: Model, x0, C0, v, dt, nsteps, xs, obs, mass=1.0, rho=1.0):
+    """Discrete adjoint of the explicit Euler run with per-particle velocities v
+    (dim, n): returns (J, grad[alpha_L, alpha_T, D_m], C^N)."""
+    x0, C0, v, xs, obs = _f64(x0), _f64(C0), _f64(v), _f64(xs), _f64(obs)
+    n = x0.shape[1]
+    m_arr, r_arr = _particle_arrays(n, mass, rho)
+    J = np.zeros(1)
+    g = np.zeros(3)
+    CN = np.zeros(n)
+    lib().or_adjoint_field(ct.byref(m), n, _ptr(x0), _ptr(C0), _ptr(v), _ptr(m_arr), _ptr(r_arr), dt, nsteps,
+                           xs.shape[1], _ptr(xs), _ptr(obs), _ptr(J), _ptr(g), _ptr(CN))
+    return float(J[0]), g, CN
+
+
+def misfit_field(m: Model, x0, C0, v, dt, nsteps, xs, obs, mass=1.0, rho=1.0):
+    """Euler run with per-particle velocities and J = sum_s (C_s - d_s)^2."""
+    x0, C0, v, xs, obs = _f64(x0), _f64(C0), _f64(v), _f64(xs), _f64(obs)
+    n = x0.shape[1]
+    m_arr, r_arr = _particle_arrays(n, mass, rho)
+    return lib().or_misfit_field(ct.byref(m), n, _ptr(x0), _ptr(C0), _ptr(v), _ptr(m_arr), _ptr(r_arr), dt,
+                                 nsteps, xs.shape[1], _ptr(xs), _ptr(obs))
 
 
 def num_threads():

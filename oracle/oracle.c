@@ -424,7 +424,36 @@ typedef struct {
     const double *x, *C, *v, *mass, *rho, *D; /* D: per-particle tensors, n x dim*dim */
     const double *Dfix;  /* if non-NULL: h_ij replaced by this tensor for every pair */
     double disp, conv;
+    int dk;              /* 0: Eq. (4); k = 1..3: the derivative of its dispersion part with
+                            respect to theta_k = (alpha_L, alpha_T, D_m) for per-particle
+                            tensors (h_ij replaced by dh_ij/dtheta_k, no convective part) */
 } rhs_ctx;
+
+/* dD/dtheta_k of Eq. (3) at velocity v (k = 0: alpha_L, 1: alpha_T, 2: D_m):
+ * v v^T/|v|, |v| I - v v^T/|v|, I (the v v^T/|v| parts taken as 0 for v = 0). */
+static void dispersion_deriv(int dim, int k, const double *v, double *dD)
+{
+    double speed2 = 0.0;
+    for (int i = 0; i < dim; ++i) speed2 += v[i] * v[i];
+    double speed = sqrt(speed2);
+    for (int i = 0; i < dim; ++i)
+        for (int j = 0; j < dim; ++j) {
+            double vv = speed > 0.0 ? v[i] * v[j] / speed : 0.0;
+            double id = (i == j) ? 1.0 : 0.0;
+            dD[i * dim + j] = (k == 0) ? vv : (k == 1) ? speed * id - vv : id;
+        }
+}
+
+/* dh/dtheta of the harmonic mean h = 4 p q / (p + q) of Eq. (5), elementwise:
+ * 4 (q^2 dp + p^2 dq) / (p + q)^2, and 0 where p q <= 0 (R3). */
+static void harmonic_deriv(int dim, const double *Da, const double *Db, const double *dDa,
+                           const double *dDb, double *dh)
+{
+    for (int k = 0; k < dim * dim; ++k) {
+        double p = Da[k], q = Db[k];
+        dh[k] = (p * q > 0.0) ? 4.0 * (q * q * dDa[k] + p * p * dDb[k]) / ((p + q) * (p + q)) : 0.0;
+    }
+}
 
 static void rhs_visit(int64_t b, const double *xab, double r2, void *vctx)
 {
@@ -440,7 +469,16 @@ static void rhs_visit(int64_t b, const double *xab, double r2, void *vctx)
     double vol = c->mass[b] / rhobar;
     double h[9];
     if (c->Dfix) memcpy(h, c->Dfix, sizeof(double) * dim * dim);
-    else or_harmonic(dim, c->D + a * dim * dim, c->D + b * dim * dim, h);
+    else if (c->dk > 0) {
+        double va[3] = {0, 0, 0}, vb[3] = {0, 0, 0}, dDa[9], dDb[9];
+        for (int i = 0; i < dim; ++i) {
+            va[i] = c->v[i * n + a];
+            vb[i] = c->v[i * n + b];
+        }
+        dispersion_deriv(dim, c->dk - 1, va, dDa);
+        dispersion_deriv(dim, c->dk - 1, vb, dDb);
+        harmonic_deriv(dim, c->D + a * dim * dim, c->D + b * dim * dim, dDa, dDb, h);
+    } else or_harmonic(dim, c->D + a * dim * dim, c->D + b * dim * dim, h);
     double Dcal = 0.0;
     for (int i = 0; i < dim; ++i)
         for (int j = 0; j < dim; ++j)
@@ -448,7 +486,7 @@ static void rhs_visit(int64_t b, const double *xab, double r2, void *vctx)
     double xdotgrad = 0.0;
     for (int i = 0; i < dim; ++i) xdotgrad += xab[i] * gradW[i];
     c->disp += 0.5 * vol * Dcal * (c->C[a] - c->C[b]) / r2 * xdotgrad;
-    if (c->v) {
+    if (c->v && c->dk == 0) {
         double s = 0.0;
         for (int i = 0; i < dim; ++i) s += (c->v[i * n + a] - c->v[i * n + b]) * gradW[i];
         c->conv += vol * s;
@@ -907,6 +945,154 @@ double or_misfit(const or_model *m, int64_t n, const double *x0, const double *C
         J += r * r;
     }
     if (pred_out) memcpy(pred_out, pred, sizeof(double) * ns);
+    free(x); free(C); free(pred);
+    return J;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Velocity field (per-particle v, explicit Euler)                            */
+/* ------------------------------------------------------------------------- */
+/* L_k C: the derivative of rhs = L C with respect to theta_k (k = 0, 1, 2 for */
+/* alpha_L, alpha_T, D_m) with per-particle tensors; the convective part of   */
+/* Eq. (4) does not depend on theta.                                           */
+void or_rhs_deriv(const or_model *m, int64_t n, const double *x, const double *C, const double *v,
+                  const double *mass, const double *rho, int k, double *out)
+{
+    or_cells cl;
+    cells_build(m, n, x, &cl);
+    double *D = tensors_per_particle(m, n, v, NULL);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t a = 0; a < n; ++a) {
+        rhs_ctx c = {m, n, a, x, C, v, mass, rho, D, NULL, 0.0, 0.0, k + 1};
+        double xa[3];
+        for (int i = 0; i < m->dim; ++i) xa[i] = x[i * n + a];
+        for_neighbours(m, n, x, &cl, xa, a, rhs_visit, &c);
+        out[a] = c.disp;
+    }
+    free(D);
+    cells_free(&cl);
+}
+
+typedef struct {
+    const or_model *m;
+    int64_t n, b;
+    const double *v, *mass, *rho, *D, *lam;
+    double y, conv;
+} ltf_ctx;
+
+/* Row b of L^T for per-particle tensors: with L_bb = sum_j w_bj + c_b (c_b the
+ * convective factor of Eq. 4, multiplying C_b) and L_ab = -w_ab,
+ * (L^T lam)_b = (sum_a w_ba + c_b) lam_b - sum_{a != b} w_ab lam_a. */
+static void ltf_visit(int64_t a, const double *xba, double r2, void *vctx)
+{
+    ltf_ctx *c = (ltf_ctx *)vctx;
+    const or_model *m = c->m;
+    int dim = m->dim;
+    int64_t b = c->b, n = c->n;
+    double xab[3], h[9];
+    for (int k = 0; k < dim; ++k) xab[k] = -xba[k];
+    or_harmonic(dim, c->D + b * dim * dim, c->D + a * dim * dim, h);
+    double w_ba = pair_weight(m, c->mass, c->rho, h, b, a, xba, r2);
+    double w_ab = pair_weight(m, c->mass, c->rho, h, a, b, xab, r2);
+    c->y += w_ba * c->lam[b] - w_ab * c->lam[a];
+    double r = sqrt(r2);
+    double dWdr = or_kernel_dWdr(m->kernel, dim, m->H, r);
+    double s = 0.0;
+    for (int i = 0; i < dim; ++i) s += (c->v[i * n + b] - c->v[i * n + a]) * dWdr * xba[i] / r;
+    c->conv += c->mass[a] / (0.5 * (c->rho[a] + c->rho[b])) * s;
+}
+
+void or_apply_LT_field(const or_model *m, int64_t n, const double *x, const double *v,
+                       const double *mass, const double *rho, const double *lam, double *y)
+{
+    or_cells cl;
+    cells_build(m, n, x, &cl);
+    double *D = tensors_per_particle(m, n, v, NULL);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t b = 0; b < n; ++b) {
+        ltf_ctx c = {m, n, b, v, mass, rho, D, lam, 0.0, 0.0};
+        double xb[3];
+        for (int i = 0; i < m->dim; ++i) xb[i] = x[i * n + b];
+        for_neighbours(m, n, x, &cl, xb, b, ltf_visit, &c);
+        y[b] = c.y + c.conv * lam[b];
+    }
+    free(D);
+    cells_free(&cl);
+}
+
+/* Discrete adjoint of the explicit Euler run with per-particle velocities:
+ * C^{n+1} = C^n + dt L^n C^n, x^{n+1} = x^n + dt v, J = sum_s (P C^N - d)_s^2;
+ *   lam^N = P^T 2 (P C^N - d),  lam^n = lam^{n+1} + dt (L^n)^T lam^{n+1},
+ *   dJ/dtheta_k += dt lam^{n+1} . L^n_k C^n.
+ * All states are kept in memory (plain reverse sweep). */
+void or_adjoint_field(const or_model *m, int64_t n, const double *x0, const double *C0,
+                      const double *v, const double *mass, const double *rho, double dt,
+                      int64_t nsteps, int64_t ns, const double *xs, const double *obs,
+                      double *J_out, double *grad_out, double *Cfinal_out)
+{
+    int dim = m->dim;
+    double *X = (double *)malloc(sizeof(double) * dim * n * (nsteps + 1));
+    double *Cs = (double *)malloc(sizeof(double) * n * (nsteps + 1));
+    double *rhs = (double *)malloc(sizeof(double) * n);
+    memcpy(X, x0, sizeof(double) * dim * n);
+    memcpy(Cs, C0, sizeof(double) * n);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        const double *xs_n = X + (size_t)s * dim * n;
+        const double *C_n = Cs + (size_t)s * n;
+        or_rhs(m, n, xs_n, C_n, v, NULL, mass, rho, NULL, n, NULL, rhs);
+        for (int64_t a = 0; a < n; ++a) Cs[(size_t)(s + 1) * n + a] = C_n[a] + dt * rhs[a];
+        advect(m, n, xs_n, v, NULL, dt, X + (size_t)(s + 1) * dim * n);
+    }
+    const double *xN = X + (size_t)nsteps * dim * n, *CN = Cs + (size_t)nsteps * n;
+    double *pred = (double *)malloc(sizeof(double) * (ns > 0 ? ns : 1));
+    double *g = (double *)malloc(sizeof(double) * (ns > 0 ? ns : 1));
+    or_sensor_interp(m, n, xN, CN, ns, xs, pred, NULL);
+    double J = 0.0;
+    for (int64_t s = 0; s < ns; ++s) {
+        double r = pred[s] - obs[s];
+        J += r * r;
+        g[s] = 2.0 * r;
+    }
+    double *lam = (double *)malloc(sizeof(double) * n);
+    double *y = (double *)malloc(sizeof(double) * n);
+    sensor_interp_T(m, n, xN, ns, xs, g, lam);
+    double grad[3] = {0.0, 0.0, 0.0};
+    for (int64_t s = nsteps - 1; s >= 0; --s) {
+        const double *xs_n = X + (size_t)s * dim * n;
+        const double *C_n = Cs + (size_t)s * n;
+        for (int k = 0; k < 3; ++k) {
+            or_rhs_deriv(m, n, xs_n, C_n, v, mass, rho, k, rhs);
+            double acc = 0.0;
+            for (int64_t a = 0; a < n; ++a) acc += lam[a] * rhs[a];
+            grad[k] += dt * acc;
+        }
+        or_apply_LT_field(m, n, xs_n, v, mass, rho, lam, y);
+        for (int64_t a = 0; a < n; ++a) lam[a] += dt * y[a];
+    }
+    *J_out = J;
+    for (int k = 0; k < 3; ++k) grad_out[k] = grad[k];
+    if (Cfinal_out) memcpy(Cfinal_out, CN, sizeof(double) * n);
+    free(X); free(Cs); free(rhs); free(pred); free(g); free(lam); free(y);
+}
+
+/* Forward run with per-particle velocities (Euler) and J only. */
+double or_misfit_field(const or_model *m, int64_t n, const double *x0, const double *C0,
+                       const double *v, const double *mass, const double *rho, double dt,
+                       int64_t nsteps, int64_t ns, const double *xs, const double *obs)
+{
+    int dim = m->dim;
+    double *x = (double *)malloc(sizeof(double) * dim * n);
+    double *C = (double *)malloc(sizeof(double) * n);
+    memcpy(x, x0, sizeof(double) * dim * n);
+    memcpy(C, C0, sizeof(double) * n);
+    or_run(m, n, x, C, v, NULL, mass, rho, dt, nsteps, 1, NULL);
+    double *pred = (double *)malloc(sizeof(double) * (ns > 0 ? ns : 1));
+    or_sensor_interp(m, n, x, C, ns, xs, pred, NULL);
+    double J = 0.0;
+    for (int64_t s = 0; s < ns; ++s) {
+        double r = pred[s] - obs[s];
+        J += r * r;
+    }
     free(x); free(C); free(pred);
     return J;
 }
