@@ -266,6 +266,7 @@ def velocity_field(device, steps=50, warmup=3):
                      "interactions_per_step": inter, "interactions_per_s": inter * steps / wall}
     f = out["field"]
     f["vs_uniform"] = f["interactions_per_s"] / out["uniform"]["interactions_per_s"]
+    out["fwd_adjoint"] = velocity_field_adjoint(device)
     achieved = FLOPS_PER_INTERACTION_FIELD[2] * f["interactions_per_step"] / (f["pair_kernel_ms"] * 1e-3) / 1e12
     f["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
@@ -314,6 +315,59 @@ def paper_scale(device, steps=3):
         print(f"[bench] {name}: {out[name]['ms_per_step']:.1f} ms/step, "
               f"{out[name]['interactions_per_s']:.3e} interactions/s", file=sys.stderr, flush=True)
     return out
+
+
+def velocity_field_adjoint(device, steps=200, ckpt=20):
+    """The inverse problem of fwd_adjoint (256^2 particles, 1024 sensors, guess
+    alpha_L = 1e-2, alpha_T = 5e-3) with the velocity field of
+    inputs.velocity_field: forward + recompute + reverse sweep with a
+    checkpoint every 20 steps against the plain forward, 200 steps.
+    Observations from a GPU forward run at the true parameters (timing only)."""
+    import numpy as np
+    import torch
+    from paper_2108_09488_amd import _lib
+    from paper_2108_09488_amd import inputs as I
+    from paper_2108_09488_amd.context import Context, params_from_spec
+
+    xs = torch.from_numpy(I.sensors(1024, [0.05, 0.25], [0.55, 0.75]))
+    truth = I.config("cfg5", steps=steps)
+    guess = I.config("cfg5", steps=steps, alpha_L=1e-2, alpha_T=5e-3)
+    x = truth.positions()
+    v = torch.from_numpy(I.velocity_field(x, truth.L))
+    C0 = torch.from_numpy(truth.concentration(x).astype(np.float32))
+    flags = _lib.ADE_VELOCITY_FIELD
+
+    def fresh(spec):
+        c = Context([params_from_spec(spec, flags=flags)], [spec.n], device=device)
+        c.init(torch.from_numpy(x), C0).set_velocities(v).build()
+        return c
+
+    c = fresh(truth)
+    c.step(steps)
+    obs = c.sensor_interp(xs)
+    c.close()
+    c = fresh(guess)
+    inter = int(c.neighbour_counts()[-1].item())
+    c.adjoint(steps, ckpt, xs, obs)  # warm-up
+    c.close()
+    c = fresh(guess)
+    _sync()
+    t0 = time.perf_counter()
+    J, g = c.adjoint(steps, ckpt, xs, obs)
+    _sync()
+    wall_adj = time.perf_counter() - t0
+    c.close()
+    c = fresh(guess)
+    _sync()
+    t0 = time.perf_counter()
+    c.step(steps)
+    _sync()
+    wall_fwd = time.perf_counter() - t0
+    c.close()
+    return {"particles": guess.n, "steps": steps, "ckpt_every": ckpt, "interactions_per_step": inter,
+            "ms_fwd_adjoint": 1e3 * wall_adj, "ms_fwd": 1e3 * wall_fwd,
+            "interactions_per_s": inter * steps / wall_adj, "vs_plain": wall_fwd / wall_adj,
+            "J": J, "grad": g}
 
 
 def cpu_baseline(cells, budget_s=20.0):
@@ -414,7 +468,9 @@ def main():
         extras["velocity_field"] = vf
         print(f"[bench] velocity field: {vf['field']['ms_per_step']:.3f} ms/step "
               f"(pair kernel {1e3 * vf['field']['pair_kernel_ms']:.1f} us), uniform "
-              f"{vf['uniform']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
+              f"{vf['uniform']['ms_per_step']:.3f} ms/step; fwd+adjoint "
+              f"{vf['fwd_adjoint']['ms_fwd_adjoint']:.1f} ms vs fwd {vf['fwd_adjoint']['ms_fwd']:.1f} ms",
+              file=sys.stderr, flush=True)
     per_cell = {n: {"interactions_per_step": i, "neighbours_mean": i / s.n}
                 for n, i, s in zip(sweep["names"], sweep["interactions"], sweep["specs"])}
     sweep["ctx"].close()

@@ -156,9 +156,10 @@ int ade_init_particles(ade_ctx *ctx, const double *d_x, const void *d_C);
  * Every step, particle a moves by rint((k + 1) u_a) - rint(k u_a) grid
  * units (u_a = dt v_a / L * 2^32, k the step index), so the displacement
  * after k steps is rint(k u_a): exact when u_a is an integer.  The pair sum
- * runs one lane per target with a fixed launch shape; ade_set_tuning,
- * ade_autotune and the adjoint entry points return ADE_EINVAL for such a
- * context. */
+ * runs one lane per target with a fixed launch shape; ade_set_tuning and
+ * ade_autotune return ADE_EINVAL for such a context.  ade_adjoint takes it
+ * (explicit Euler): its checkpoints then hold the velocities and tensors
+ * too, and the gradient differentiates every pair's harmonic mean. */
 int ade_set_velocities(ade_ctx *ctx, const double *d_v);
 
 /* Cell-linked list: cell hash, counting sort by cell (stable, ordered by
@@ -206,7 +207,11 @@ int ade_adjoint_workspace_bytes(const ade_ctx *ctx, int64_t nsteps, int32_t ckpt
  * 8-9: its step is C <- (I + dt L + dt^2/2 L^2) C for a uniform flow, and the
  * adjoint applies the same two stages to lambda) from the current state,
  * w.r.t. (alpha_L, alpha_T, D_m) of plume 0, by a discrete adjoint with a
- * checkpoint every ckpt_every steps and recompute.
+ * checkpoint every ckpt_every steps and recompute.  For a velocity field
+ * (ADE_VELOCITY_FIELD, explicit Euler) the operator is again its own
+ * transpose (symmetric pair weights, a convective term diagonal in C) and
+ * the gradient takes d(h/4)_ij = (q^2 dp + p^2 dq) / (p + q)^2 per pair and
+ * component (p, q the two particles' tensor components).
  * d_obs holds S reals.  On return the context holds the state at step
  * nsteps.  h_grad receives 3 doubles; synchronises the stream. */
 int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *d_xs,

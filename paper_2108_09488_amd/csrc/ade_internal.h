@@ -155,6 +155,22 @@ struct GenLaunch {
 };
 hipError_t launch_setvel(int dim, int real_bytes, const PlumeDev* plumes, const TileDev* tiles, uint32_t ntiles,
                          const double* v, uint32_t N, StateArrays U, hipStream_t s);
+// Adjoint pass of the velocity-field Euler step over a state snapshot S:
+// lam_out (id order) = lambda + dt L^T lambda, gradient partials per
+// workgroup added to gpart[3 * workgroup + k].
+struct AdjGenLaunch {
+    const PlumeDev* plumes;
+    const TileDev* tiles;
+    uint32_t ntiles;
+    int list_cap;
+    StateArrays S;
+    const uint32_t* cell_start;
+    const void* lam_s;  // lambda in the snapshot's cell order
+    void* lam_out;      // lambda^n in id order
+    double* gpart;
+};
+hipError_t launch_adjoint_gen(int dim, int real_bytes, int kernel, const AdjGenLaunch& a, uint32_t block,
+                              hipStream_t s);
 hipError_t launch_pair_gen(int dim, int real_bytes, int kernel, int mode, const GenLaunch& g, hipStream_t s);
 hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const PairLaunch& a,
                        int block, hipStream_t s);

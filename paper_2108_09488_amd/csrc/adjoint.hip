@@ -342,6 +342,12 @@ struct SnapCopy {
     int64_t* dstep;
     const int64_t* sstep;
     uint32_t n, ncs, cwords;
+    // velocity field: the per-particle arrays (velocities, tensor reciprocals,
+    // 2D FP32 records) as 32-bit words, xn[e] words each
+    uint32_t* dx[10];
+    const uint32_t* sx[10];
+    uint32_t xn[10];
+    int nx;
 };
 
 __global__ __launch_bounds__(256) void k_copy_snap(SnapCopy a) {
@@ -355,6 +361,14 @@ __global__ __launch_bounds__(256) void k_copy_snap(SnapCopy a) {
         if (a.dpos[d]) a.dpos[d][i] = a.spos[d][i];
     a.did[i] = a.sid[i];
     if (a.drec) a.drec[i] = a.srec[i];
+}
+
+// the velocity-field arrays of a snapshot copy (a separate launch: the
+// 32-byte records make them the largest arrays)
+__global__ __launch_bounds__(256) void k_copy_snap_x(SnapCopy a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    for (int e = 0; e < a.nx; ++e)
+        if (i < a.xn[e]) a.dx[e][i] = a.sx[e][i];
 }
 
 namespace {
@@ -379,6 +393,9 @@ struct Snap {
     uint4* rec;
     uint32_t* cs;
     int64_t* step;
+    void* vel[3];  // velocity field only (null otherwise)
+    void* rD[6];
+    uint4* grec;
 };
 
 constexpr uint32_t kAdjMaxSubs = 4;  // workgroups per tile of the adjoint passes (64 threads)
@@ -424,6 +441,9 @@ void take_snap(char* base, size_t& off, const ade_ctx* c, Snap& s) {
     s.rec = c->S.rec ? (uint4*)take(N * 16) : nullptr;
     s.cs = (uint32_t*)take((pl.ncell + 1) * 4);
     s.step = (int64_t*)take(8);
+    for (int d = 0; d < 3; ++d) s.vel[d] = c->S.vel[d] ? take(N * pl.real_bytes) : nullptr;
+    for (int d = 0; d < 6; ++d) s.rD[d] = c->S.rD[d] ? take(N * pl.real_bytes) : nullptr;
+    s.grec = c->S.grec ? (uint4*)take(N * 32) : nullptr;
 }
 
 void adj_layout(const ade_ctx* c, int64_t nsteps, int32_t K, int32_t ns, char* base, AdjLayout& L) {
@@ -484,8 +504,25 @@ int copy_state(const ade_ctx* c, const Snap& dst, const Snap& src) {
     a.ncs = nc;
     a.cwords = words;
     const uint32_t items = std::max(N * words, nc);
+    a.nx = 0;
+    uint32_t xitems = 0;
+    auto extra = [&](void* d, const void* s, uint32_t nw) {
+        if (!d || !s) return;
+        a.dx[a.nx] = static_cast<uint32_t*>(d);
+        a.sx[a.nx] = static_cast<const uint32_t*>(s);
+        a.xn[a.nx] = nw;
+        ++a.nx;
+        xitems = std::max(xitems, nw);
+    };
+    for (int d = 0; d < 3; ++d) extra(dst.vel[d], src.vel[d], N * words);
+    for (int d = 0; d < 6; ++d) extra(dst.rD[d], src.rD[d], N * words);
+    extra(dst.grec, src.grec, N * 8);
     hipLaunchKernelGGL(k_copy_snap, dim3((items + 255) / 256), dim3(256), 0, c->stream, a);
     HIPCHK(hipGetLastError());
+    if (a.nx > 0) {
+        hipLaunchKernelGGL(k_copy_snap_x, dim3((xitems + 255) / 256), dim3(256), 0, c->stream, a);
+        HIPCHK(hipGetLastError());
+    }
     return ADE_OK;
 }
 
@@ -497,6 +534,9 @@ Snap live(ade_ctx* c) {
     s.rec = c->S.rec;
     s.cs = c->cell_start;
     s.step = c->step;
+    for (int d = 0; d < 3; ++d) s.vel[d] = c->S.vel[d];
+    for (int d = 0; d < 6; ++d) s.rD[d] = c->S.rD[d];
+    s.grec = c->S.grec;
     return s;
 }
 
@@ -506,6 +546,9 @@ StateArrays snap_arrays(const ade_ctx* c, const Snap& s) {
     a.C = s.C;
     a.id = s.id;
     a.rec = s.rec;
+    for (int d = 0; d < 3; ++d) a.vel[d] = s.vel[d];
+    for (int d = 0; d < 6; ++d) a.rD[d] = s.rD[d];
+    a.grec = s.grec;
     return a;
 }
 
@@ -549,7 +592,6 @@ int ade_adjoint_workspace_bytes(const ade_ctx* c, int64_t nsteps, int32_t ckpt_e
     if (!c || !bytes) return fail(ADE_EINVAL, "null argument");
     if (nsteps < 1 || ckpt_every < 1 || n_sensors < 1)
         return fail(ADE_EINVAL, "nsteps, ckpt_every and n_sensors must be positive");
-    if (c->plan.general) return fail(ADE_EINVAL, "the adjoint takes a uniform flow");
     AdjLayout L;
     adj_layout(c, nsteps, ckpt_every, n_sensors, nullptr, L);
     *bytes = L.bytes;
@@ -562,7 +604,6 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     if (rc) return rc;
     if (!d_obs || !d_ws || !h_J || !h_grad) return fail(ADE_EINVAL, "null argument");
     if (nsteps < 1 || K < 1) return fail(ADE_EINVAL, "nsteps and ckpt_every must be positive");
-    if (c->plan.general) return fail(ADE_EINVAL, "the adjoint takes a uniform flow");
     if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
     AdjLayout L;
     adj_layout(c, nsteps, K, ns, nullptr, L);
@@ -637,7 +678,19 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     hipLaunchKernelGGL((k_adjoint<D, R, KK, MODE>), ag, abk, (uint32_t)ashm, st, c->plumes, c->tiles, Sa,     \
                        sn.cs, (const R*)(U), (const R*)L.lam_s, (const R*)(X), (const uint4*)(REC), (R*)(OUT), \
                        (R*)(XH), (uint4*)(RECOUT), ac, L.gpart)
-            if (pl.integrator == ADE_PC) {
+            if (pl.general) {  // velocity field (explicit Euler)
+                AdjGenLaunch ga;
+                ga.plumes = c->plumes;
+                ga.tiles = c->tiles;
+                ga.ntiles = pl.ntiles;
+                ga.list_cap = pl.list_cap;
+                ga.S = Sa;
+                ga.cell_start = sn.cs;
+                ga.lam_s = L.lam_s;
+                ga.lam_out = L.lam[1 - li];
+                ga.gpart = L.gpart;
+                HIPCHK(launch_adjoint_gen(pl.dim, pl.real_bytes, pl.kernel, ga, ab, st));
+            } else if (pl.integrator == ADE_PC) {
 #define CALL(D, R, KK)                                                                                    \
     LAUNCH(D, R, KK, kAdjHalf, L.lam_s, sn.C, L.arec, L.mu_s, L.ch_s, L.arec2);                              \
     LAUNCH(D, R, KK, kAdjFull, L.mu_s, L.ch_s, L.arec2, L.lam[1 - li], nullptr, nullptr)

@@ -253,6 +253,182 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
     enlist(g.lists, key, id);
 }
 
+// dD/dtheta_k of Eq. (3) at velocity v, in the stored component order (k =
+// 0: alpha_L, v v^T/|v|; 1: alpha_T, |v| I - v v^T/|v|; 2: D_m, I; the v v^T/|v|
+// parts are 0 for v = 0)
+template <int DIM, typename real>
+__device__ __forceinline__ void tensor_derivs(const real* v, real (&dD)[3][GenDims<DIM>::kT]) {
+    real s2 = v[0] * v[0];
+#pragma unroll
+    for (int c = 1; c < DIM; ++c) s2 = fmar(v[c], v[c], s2);
+    const real sp = sqrt(s2);
+    const real inv = sp > (real)0 ? (real)1 / sp : (real)0;
+    // (i, j) of stored component q: 2D xx, xy, yy; 3D xx, xy, xz, yy, yz, zz
+    constexpr int ci[6] = {0, 0, DIM == 2 ? 1 : 0, 1, 1, 2};
+    constexpr int cj[6] = {0, 1, DIM == 2 ? 1 : 2, 1, 2, 2};
+#pragma unroll
+    for (int q = 0; q < GenDims<DIM>::kT; ++q) {
+        const int i = ci[q], j = cj[q];
+        const real vv = v[i] * v[j] * inv;
+        const real id = (i == j) ? (real)1 : (real)0;
+        dD[0][q] = vv;
+        dD[1][q] = fmar(sp, id, -vv);
+        dD[2][q] = id;
+    }
+}
+
+// Adjoint pass of the velocity-field Euler step.  With equal particle volumes
+// the dispersion weights w_ab of the pair sum are symmetric and the convective
+// term of Eq. (4) is diagonal in C, so L^T = L and
+//     lambda^n = lambda + dt L lambda
+// is the forward pair sum applied to lambda.  The gradient gains
+// dt lambda_a (L_k C)_a, where L_k has each pair's harmonic mean replaced by
+// its derivative with respect to theta_k: with p = D_ij,a and q = D_ij,b,
+//     d(h/4)_ij = (q^2 dp + p^2 dq) / (p + q)^2   (0 where p q <= 0),
+// and no convective part (it does not depend on theta).  The tensors come
+// from the stored reciprocals (1 / inf = 0 for a zero component).
+template <int DIM, typename real, int KERN>
+__global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
+    extern __shared__ uint2 lds_list[];
+    __shared__ double lds[kTile / kWave];
+    constexpr int NT = GenDims<DIM>::kT;
+    const uint32_t tpb = blockDim.x, subs = kTile / tpb;
+    const TileDev t = g.tiles[blockIdx.x / subs];
+    const uint32_t i0 = t.start + (blockIdx.x % subs) * tpb;
+    if (i0 >= t.end) return;  // whole workgroup: ragged last tile
+    const uint32_t i1 = min(t.end, i0 + tpb);
+    const PlumeDev P = g.plumes[t.plume];
+    const bool active = i0 + threadIdx.x < i1;
+    const uint32_t i = active ? i0 + threadIdx.x : i0;
+
+    const StateArrays& S = g.S;
+    const real* __restrict__ lam_s = static_cast<const real*>(g.lam_s);
+    const GPart<DIM, real> A = load_part<DIM, real>(S, i);
+    const real la = lam_s[i];
+    const Target T = make_target<DIM>(P, A.x, A.y, A.z);
+    real Da[NT], dA[3][NT];
+#pragma unroll
+    for (int q = 0; q < NT; ++q) Da[q] = (real)1 / A.r[q];
+    tensor_derivs<DIM, real>(A.v, dA);
+
+    uint2* list = lds_list + threadIdx.x;
+    uint32_t total = 0;
+    if (active) total = build_list<DIM, 1>(P, g.cell_start, T, list, tpb);
+    else list[0] = make_uint2(kListEndStart, kListEndEnd);
+
+    const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
+    const real gam = (real)(DIM + 2);
+    real al = 0, cv = 0, gk[3] = {0, 0, 0};
+    struct Cand {
+        GPart<DIM, real> p;
+        real lam;
+    };
+    auto fetch = [&](uint32_t k) {
+        k /= kRecBytes;
+        return Cand{load_part<DIM, real>(S, k), lam_s[k]};
+    };
+    // the Dcal-type bracket Gamma x^T M x / r^2 - tr M of a symmetric tensor M
+    // (stored components), times r^2 / r^2 in grid units
+    auto bracket = [&](const real (&M)[NT], real dx, real dy, real dz, real ir2) {
+        real quad, tr;
+        if (DIM == 2) {
+            quad = fmar(M[0] * dx, dx, fmar((real)2 * M[1] * dx, dy, M[2] * dy * dy));
+            tr = M[0] + M[2];
+        } else {
+            quad = M[0] * dx * dx + M[3] * dy * dy + M[5] * dz * dz +
+                   (real)2 * (M[1] * dx * dy + M[2] * dx * dz + M[4] * dy * dz);
+            tr = M[0] + M[3] + M[5];
+        }
+        return fmar(gam * quad, ir2, -tr);
+    };
+    auto eval = [&](const Cand& cc, bool keep) {
+        const GPart<DIM, real>& c = cc.p;
+        const real dx = (real)(int32_t)(T.ux - c.x);
+        const real dy = (real)(int32_t)(T.uy - c.y);
+        const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - c.z) : (real)0;
+        real r2 = dx * dx;
+        r2 = fmar(dy, dy, r2);
+        if (DIM == 3) r2 = fmar(dz, dz, r2);
+        const bool in = keep && r2 > (real)0 && r2 <= H2;
+        const real rinv = rsqrt_r(r2);
+        const real q = r2 * rinv * invHu;
+        real omq = (real)1 - q;
+        omq = omq > (real)0 ? omq : (real)0;
+        real f;
+        if (KERN == 4) {
+            const real o2 = omq * omq;
+            f = o2 * o2 * omq * fmar((real)5, q, (real)1);
+        } else {
+            f = omq * omq * omq;
+        }
+        f = in ? f : (real)0;
+        const real ir2 = in ? rinv * rinv : (real)0;
+        real h[NT];
+#pragma unroll
+        for (int k = 0; k < NT; ++k) h[k] = is_diag<DIM>(k) ? hmean_diag(A.r[k], c.r[k]) : hmean(A.r[k], c.r[k]);
+        al = fmar(bracket(h, dx, dy, dz, ir2) * f, la - cc.lam, al);
+        real vx = (A.v[0] - c.v[0]) * dx;
+        vx = fmar(A.v[1] - c.v[1], dy, vx);
+        if (DIM == 3) vx = fmar(A.v[DIM - 1] - c.v[DIM - 1], dz, vx);
+        cv = fmar(f, vx, cv);
+        // derivative operators: d(h/4) = wa dD_a + wb dD_b per component
+        real dB[3][NT], wa[NT], wb[NT];
+        tensor_derivs<DIM, real>(c.v, dB);
+#pragma unroll
+        for (int k = 0; k < NT; ++k) {
+            const real p = Da[k], qq = (real)1 / c.r[k];
+            const real s = p + qq;
+            const real inv2 = p * qq > (real)0 ? (real)1 / (s * s) : (real)0;
+            wa[k] = qq * qq * inv2;
+            wb[k] = p * p * inv2;
+        }
+        const real dC = (A.C - c.C) * f;
+#pragma unroll
+        for (int th = 0; th < 3; ++th) {
+            real dh[NT];
+#pragma unroll
+            for (int k = 0; k < NT; ++k) dh[k] = fmar(wa[k], dA[th][k], wb[k] * dB[th][k]);
+            gk[th] = fmar(bracket(dh, dx, dy, dz, ir2), dC, gk[th]);
+        }
+    };
+    walk_stream<kGenBatch>(list, tpb, total, i, fetch, eval);
+
+    const double sd = P.dt * P.vphi;
+    if (active) {
+        // 1/2 of the sum of Dcal terms = 2 al (al sums Dcal / 4)
+        const real Lx = fmar(la * (real)(P.L * (1.0 / 4294967296.0)), cv, (real)2 * al);
+        static_cast<real*>(g.lam_out)[S.id[i]] = fmar((real)sd, Lx, la);
+    }
+    // dt lambda_a (L_k C)_a = dt vphi lambda_a 2 gk (gk sums Dcal_k / 4)
+    const double m = active ? 2.0 * sd * (double)la : 0.0;
+#pragma unroll
+    for (int th = 0; th < 3; ++th) {
+        const double c = block_sum(m * (double)gk[th], lds);
+        if (threadIdx.x == 0) g.gpart[3 * blockIdx.x + th] += c;
+    }
+}
+
+template <int DIM, typename real, int KERN>
+static hipError_t launch_adj_gen_t(const AdjGenLaunch& a, uint32_t block, hipStream_t s) {
+    const size_t shm = (size_t)block * (size_t)a.list_cap * 8u;
+    if (shm > kPairLdsMax || block < 64 || block > 256 || kTile % block) return hipErrorInvalidValue;
+    if (DIM == 2 && sizeof(real) == 4 && !a.S.grec) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_adjoint_gen<DIM, real, KERN>), dim3(a.ntiles * (kTile / block)), dim3(block), shm, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adjoint_gen(int dim, int real_bytes, int kernel, const AdjGenLaunch& a, uint32_t block,
+                              hipStream_t s) {
+    if (dim == 2) {
+        if (real_bytes == 4)
+            return kernel == 4 ? launch_adj_gen_t<2, float, 4>(a, block, s) : launch_adj_gen_t<2, float, 2>(a, block, s);
+        return kernel == 4 ? launch_adj_gen_t<2, double, 4>(a, block, s) : launch_adj_gen_t<2, double, 2>(a, block, s);
+    }
+    if (real_bytes == 4)
+        return kernel == 4 ? launch_adj_gen_t<3, float, 4>(a, block, s) : launch_adj_gen_t<3, float, 2>(a, block, s);
+    return kernel == 4 ? launch_adj_gen_t<3, double, 4>(a, block, s) : launch_adj_gen_t<3, double, 2>(a, block, s);
+}
+
 hipError_t launch_setvel(int dim, int real_bytes, const PlumeDev* plumes, const TileDev* tiles, uint32_t ntiles,
                          const double* v, uint32_t N, StateArrays U, hipStream_t s) {
     dim3 gr(ntiles), b(kTile);

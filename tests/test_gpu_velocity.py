@@ -203,6 +203,38 @@ def test_velocity_field_ensemble_matches_single_plumes():
         off += s.n
 
 
+@pytest.mark.parametrize("rb,K", [(8, 7), (4, 7), (8, 1), (4, 40)])
+def test_velocity_field_adjoint_matches_oracle(rb, K):
+    """J, the gradient w.r.t. (alpha_L, alpha_T, D_m) and the final state of the
+    velocity-field Euler run against the oracle's discrete adjoint (itself
+    pinned by finite differences), for checkpoints every 1, 7 and 40 steps."""
+    spec = I.config("cfg5", n_side=48, steps=30, dt=DT_EXACT, real_bytes=rb, jitter=0.1, alpha_L=1e-2,
+                    alpha_T=5e-3)
+    x = spec.positions()
+    v = _field(spec)
+    C0 = spec.concentration(x)
+    if rb == 4:
+        C0 = C0.astype(np.float32).astype(np.float64)
+    xs = I.sensors(64, [0.05, 0.25], [0.55, 0.75])
+    truth = O.model(2, 4, spec.H, alpha_L=2e-2, alpha_T=2e-3, D_m=1e-6)
+    _, _, CN = O.adjoint_field(truth, x, C0, v, spec.dt, spec.steps, xs, np.zeros(xs.shape[1]),
+                               mass=spec.mass, rho=spec.rho0)
+    obs, _ = O.sensor_interp(truth, (x + spec.steps * spec.dt * v) % spec.L, CN, xs)
+    if rb == 4:
+        obs = obs.astype(np.float32).astype(np.float64)
+    ctx, _, _ = _ctx(spec, v, C=C0)
+    J, g = ctx.adjoint(spec.steps, K, torch.from_numpy(xs), torch.from_numpy(obs))
+    Jo, go, Co = O.adjoint_field(O.model_from_spec(spec), x, C0, v, spec.dt, spec.steps, xs, obs,
+                                 mass=spec.mass, rho=spec.rho0)
+    Cg = ctx.read_C().double().cpu().numpy()
+    assert _rel(Cg, Co) < (1e-12 if rb == 8 else 1e-5)
+    tol = 1e-10 if rb == 8 else 1e-4
+    print(f"[vf adjoint] rb={rb} K={K} J {J:.6e} vs {Jo:.6e}, grad {g} vs {list(go)}", flush=True)
+    assert J == pytest.approx(Jo, rel=tol)
+    assert np.allclose(g, go, rtol=tol, atol=tol * np.abs(go).max())
+    ctx.close()
+
+
 def test_velocity_field_validation():
     from paper_2108_09488_amd.context import Context, params_from_spec
     spec = _spec(2, 4, 32, 4, 1.5)
