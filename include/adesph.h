@@ -18,7 +18,8 @@
  * the pair term takes the harmonic mean of Eq. (5) per component, and the
  * convective term of Eq. (4),
  *     + C_a sum_b (m_b / rhobar_ab) (v_a - v_b) . grad_a W_ab,
- * is added; particles move with their own velocities (explicit Euler).
+ * is added; particles move with their own velocities (explicit Euler, or
+ * the predictor-corrector with a cell build at the half-step positions).
  * Reference: Klapp, Sigalotti, Alvarado-Rodriguez & Rendon, "Consistent SPH
  * simulations of the anisotropic dispersion of a contaminant plume",
  * arXiv:2108.09488, Sections 2.1-2.4.
@@ -84,8 +85,7 @@ typedef struct {
     double mass;        /* mass of every particle (> 0)                      */
     uint32_t flags;     /* ADE_STRICT_DT | ADE_CHECK_FINITE |
                            ADE_VELOCITY_FIELD (per-particle velocities; the
-                           same on every plume of a context, ADE_EULER and
-                           dt > 0 only)                                      */
+                           same on every plume of a context; dt > 0)         */
     int32_t cell_rows;  /* cell grid: rows per support radius in y (and z),
                            1..4; 0 = default (2, or 4 for more than 2000
                            expected neighbours per particle)                */
@@ -155,11 +155,15 @@ int ade_init_particles(ade_ctx *ctx, const double *d_x, const void *d_C);
  * the whole run; its tensor D_a (Eq. 3) is formed from the stored value.
  * Every step, particle a moves by rint((k + 1) u_a) - rint(k u_a) grid
  * units (u_a = dt v_a / L * 2^32, k the step index), so the displacement
- * after k steps is rint(k u_a): exact when u_a is an integer.  The pair sum
+ * after k steps is rint(k u_a): exact when u_a is an integer.  With ADE_PC
+ * the predictor moves it to x + rint((k + 1/2) u_a) - rint(k u_a), the cells
+ * are rebuilt there for the corrector, and the corrector completes the step.
+ * The pair sum
  * runs one lane per target with a fixed launch shape; ade_set_tuning and
  * ade_autotune return ADE_EINVAL for such a context.  ade_adjoint takes it
- * (explicit Euler): its checkpoints then hold the velocities and tensors
- * too, and the gradient differentiates every pair's harmonic mean. */
+ * with explicit Euler (ADE_EINVAL with ADE_PC): its checkpoints then hold
+ * the velocities and tensors too, and the gradient differentiates every
+ * pair's harmonic mean. */
 int ade_set_velocities(ade_ctx *ctx, const double *d_v);
 
 /* Cell-linked list: cell hash, counting sort by cell (stable, ordered by

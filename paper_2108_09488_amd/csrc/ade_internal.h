@@ -70,6 +70,9 @@ struct StateArrays {
     // 1/0 = inf), in the working precision
     void* vel[3];
     void* rD[6];
+    // velocity field with the predictor-corrector: C^n carried through the
+    // predictor's build (null otherwise)
+    void* Cb;
     // velocity field in 2D FP32, sorted buffer S only (null otherwise): a
     // 32-byte record per particle, {x, y, C, v_x} {v_y, 1/D_xx, 1/D_xy, 1/D_yy}
     uint4* grec;
@@ -86,7 +89,8 @@ struct CellLists {
     uint32_t* ovf_count;  // [0] pairs added since the last scan, [1] pairs of the current build
 };
 
-enum PairMode { kModeStep = 0, kModeHalf = 1, kModeRhs = 2 };
+// kModeFull: the corrector of the velocity-field predictor-corrector step
+enum PairMode { kModeStep = 0, kModeHalf = 1, kModeRhs = 2, kModeFull = 3 };
 
 struct PairLaunch {
     const PlumeDev* plumes;

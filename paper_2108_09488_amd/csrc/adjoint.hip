@@ -604,6 +604,8 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     if (rc) return rc;
     if (!d_obs || !d_ws || !h_J || !h_grad) return fail(ADE_EINVAL, "null argument");
     if (nsteps < 1 || K < 1) return fail(ADE_EINVAL, "nsteps and ckpt_every must be positive");
+    if (c->plan.general && c->plan.integrator != ADE_EULER)
+        return fail(ADE_EINVAL, "the velocity-field adjoint takes explicit Euler");
     if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
     AdjLayout L;
     adj_layout(c, nsteps, K, ns, nullptr, L);

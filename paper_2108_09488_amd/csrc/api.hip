@@ -129,8 +129,6 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
             return fail(ADE_EINVAL, "plume %d: ADE_VELOCITY_FIELD must match plume 0", p);
         if (q.flags & ~(uint32_t)(ADE_STRICT_DT | ADE_CHECK_FINITE | ADE_VELOCITY_FIELD))
             return fail(ADE_EINVAL, "plume %d: unknown flags", p);
-        if (pl.general && q.integrator != ADE_EULER)
-            return fail(ADE_EINVAL, "plume %d: a velocity field steps with ADE_EULER only", p);
         if (pl.general && !(q.dt > 0))
             return fail(ADE_EINVAL, "plume %d: a velocity field needs dt > 0", p);
         if (counts[p] <= 0) return fail(ADE_EINVAL, "plume %d: count must be positive", p);
@@ -323,6 +321,7 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
         for (int d = 0; d < 3; ++d) s.vel[d] = (pl.general && d < pl.dim) ? b.take_bytes(N * rb) : nullptr;
         for (int d = 0; d < 6; ++d) s.rD[d] = (pl.general && d < (pl.dim == 2 ? 3 : 6)) ? b.take_bytes(N * rb) : nullptr;
         s.grec = (k == 0 && pl.general && pl.dim == 2 && pl.real_bytes == 4) ? b.take<uint4>(2 * N) : nullptr;
+        s.Cb = (pl.general && pl.integrator == ADE_PC) ? b.take_bytes(N * rb) : nullptr;
     }
     if (pl.dim == 2) {  // never read in 2D, but keep the pointers valid
         c->S.pos[2] = c->S.pos[0];
@@ -462,7 +461,13 @@ GenLaunch gen_args(ade_ctx* c, void* out) {
 int enqueue_step(ade_ctx* c) {
     const Plan& pl = c->plan;
     int rc;
-    if (pl.general) {  // velocity field: explicit Euler
+    if (pl.general && pl.integrator == ADE_PC) {
+        // velocity field, predictor-corrector: the corrector's positions
+        // x^(1/2) have their own relative geometry, so they get a cell build
+        if ((rc = run_gen(c, kModeHalf, nullptr))) return rc;
+        if ((rc = enqueue_build(c, 0))) return rc;
+        if ((rc = run_gen(c, kModeFull, nullptr))) return rc;
+    } else if (pl.general) {  // velocity field: explicit Euler
         if ((rc = run_gen(c, kModeStep, nullptr))) return rc;
     } else if (pl.integrator == ADE_PC) {
         PairLaunch h = pair_args(c, kModeHalf, c->S.C, c->S.C, 0.5, c->aux);

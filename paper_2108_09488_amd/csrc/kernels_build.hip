@@ -208,6 +208,7 @@ __global__ __launch_bounds__(256) void k_place(StateArrays U, StateArrays S, Cel
         for (int c = 0; c < DIM; ++c) static_cast<real*>(S.vel[c])[d] = w[c];
 #pragma unroll
         for (int q = 0; q < (DIM == 2 ? 3 : 6); ++q) static_cast<real*>(S.rD[q])[d] = w[DIM + q];
+        if (U.Cb) static_cast<real*>(S.Cb)[d] = static_cast<const real*>(U.Cb)[i];
         if (DIM == 2 && sizeof(real) == 4 && S.grec) {
             auto bits = [](real f) { return __float_as_uint((float)f); };
             S.grec[2 * (size_t)d] = make_uint4(u[0], u[1], bits(C), bits(w[0]));

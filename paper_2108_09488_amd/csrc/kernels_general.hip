@@ -230,16 +230,31 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
         static_cast<real*>(g.out)[S.id[i]] = rhs;
         return;
     }
-    // step: C, the move on the particle's own schedule, hashing and counting
+    // step (Euler), or the predictor-corrector's two stages (Eqs. 8-9, each
+    // followed by a cell build): the predictor writes C^(1/2) = C + dt/2 rhs,
+    // carries C^n and moves to x^(1/2); the corrector, evaluated there,
+    // writes C^n + dt rhs and moves on to x^(n+1).  C, the move on the
+    // particle's own schedule (from step k + f0 to k + f1), hashing and
+    // counting
     const StateArrays& U = g.U;
-    static_cast<real*>(U.C)[i] = fmar((real)P.dt, rhs, A.C);
+    double f0 = 0.0, f1 = 1.0;
+    if (MODE == kModeHalf) {
+        static_cast<real*>(U.C)[i] = fmar((real)(0.5 * P.dt), rhs, A.C);
+        static_cast<real*>(U.Cb)[i] = A.C;
+        f1 = 0.5;
+    } else if (MODE == kModeFull) {
+        static_cast<real*>(U.C)[i] = fmar((real)P.dt, rhs, static_cast<const real*>(S.Cb)[i]);
+        f0 = 0.5;
+    } else {
+        static_cast<real*>(U.C)[i] = fmar((real)P.dt, rhs, A.C);
+    }
     const int64_t k = *g.step;
     uint32_t u[3] = {T.ux, T.uy, T.uz};
 #pragma unroll
     for (int c = 0; c < DIM; ++c) {
         const double us = (double)A.v[c] * P.dt / P.L * 4294967296.0;
-        const int64_t s1 = (int64_t)rint((double)(k + 1) * us);
-        const int64_t s0 = (int64_t)rint((double)k * us);
+        const int64_t s1 = (int64_t)rint(((double)k + f1) * us);
+        const int64_t s0 = (int64_t)rint(((double)k + f0) * us);
         u[c] += (uint32_t)(s1 - s0);
         U.pos[c][i] = u[c];
         static_cast<real*>(U.vel[c])[i] = A.v[c];
@@ -447,7 +462,10 @@ static hipError_t launch_gen_t(int mode, const GenLaunch& g, hipStream_t s) {
     if (shm > kPairLdsMax) return hipErrorInvalidValue;
     if (DIM == 2 && sizeof(real) == 4 && !g.S.grec) return hipErrorInvalidValue;
     dim3 gr(g.ntiles * (kTile / block)), b(block);
-    auto kern = (mode == kModeStep) ? k_pair_gen<DIM, real, KERN, kModeStep> : k_pair_gen<DIM, real, KERN, kModeRhs>;
+    auto kern = (mode == kModeStep)   ? k_pair_gen<DIM, real, KERN, kModeStep>
+                : (mode == kModeHalf) ? k_pair_gen<DIM, real, KERN, kModeHalf>
+                : (mode == kModeFull) ? k_pair_gen<DIM, real, KERN, kModeFull>
+                                      : k_pair_gen<DIM, real, KERN, kModeRhs>;
     if (g.ev0)  // timed launch: the events carry the kernel's own start and end stamps
         hipExtLaunchKernelGGL(kern, gr, b, (uint32_t)shm, s, g.ev0, g.ev1, 0u, g);
     else
@@ -456,7 +474,8 @@ static hipError_t launch_gen_t(int mode, const GenLaunch& g, hipStream_t s) {
 }
 
 hipError_t launch_pair_gen(int dim, int real_bytes, int kernel, int mode, const GenLaunch& g, hipStream_t s) {
-    if (mode != kModeStep && mode != kModeRhs) return hipErrorInvalidValue;
+    if (mode != kModeStep && mode != kModeRhs && mode != kModeHalf && mode != kModeFull) return hipErrorInvalidValue;
+    if ((mode == kModeHalf || mode == kModeFull) && (!g.U.Cb || !g.S.Cb)) return hipErrorInvalidValue;
     if (dim == 2) {
         if (real_bytes == 4) return kernel == 4 ? launch_gen_t<2, float, 4>(mode, g, s) : launch_gen_t<2, float, 2>(mode, g, s);
         return kernel == 4 ? launch_gen_t<2, double, 4>(mode, g, s) : launch_gen_t<2, double, 2>(mode, g, s);

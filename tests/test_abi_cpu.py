@@ -74,8 +74,9 @@ def test_strict_dt_flags_unstable_step():
 
 
 def test_velocity_field_flag_validation():
-    """ADE_VELOCITY_FIELD: explicit Euler with a given dt, the same on every
-    plume; its workspace holds the per-particle velocities and tensors."""
+    """ADE_VELOCITY_FIELD: a given dt, the same on every plume; its workspace
+    holds the per-particle velocities and tensors (and, for the
+    predictor-corrector, C^n carried through the predictor's build)."""
     s = I.config("cfg1")
     base = params_from_spec(s)
     p = params_from_spec(s, flags=_lib.ADE_VELOCITY_FIELD)
@@ -85,7 +86,8 @@ def test_velocity_field_flag_validation():
     # two buffers (sorted and hashed) of 2 velocity and 3 tensor components, FP64
     assert nb - nb0 >= 2 * 5 * 8 * s.n
     pc = params_from_spec(s, integrator=_lib.ADE_PC, flags=_lib.ADE_VELOCITY_FIELD)
-    assert _wsbytes([pc], [s.n])[0] == _lib.ADE_EINVAL
+    rc_pc, nb_pc = _wsbytes([pc], [s.n])
+    assert rc_pc == 0 and nb_pc >= nb + 2 * 8 * s.n  # C^n carried through the predictor's build
     p0 = params_from_spec(s, flags=_lib.ADE_VELOCITY_FIELD)
     p0.dt = 0.0
     assert _wsbytes([p0], [s.n])[0] == _lib.ADE_EINVAL

@@ -136,6 +136,74 @@ def test_velocity_field_trajectory(dim, rb, n_side, steps):
     ctx.close()
 
 
+@pytest.mark.parametrize("dim,rb,n_side,steps", [(2, 8, 48, 30), (2, 4, 64, 30), (3, 4, 14, 8), (3, 8, 12, 6)])
+def test_velocity_field_predictor_corrector(dim, rb, n_side, steps):
+    """The predictor-corrector of Eqs. (8)-(9) with per-particle velocities:
+    the corrector's rhs at x^(1/2) = x + dt/2 v with C^(1/2), after a cell
+    build of its own.  Velocities are multiples of 2^-19 with dt = 2^-12, so
+    half steps are whole fixed-point units too: positions bit-exact, C within
+    the tolerance of the oracle's PC run, neighbour sets bit-exact."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = _spec(dim, rb, n_side, 4, 1.5 if dim == 2 else 2.0)
+    x = spec.positions()
+    v = I.velocity_field(x, spec.L, quantum=2.0 ** -19)
+    if rb == 4:
+        v = v.astype(np.float32).astype(np.float64)
+    C0 = spec.concentration(x)
+    if rb == 4:
+        C0 = C0.astype(np.float32).astype(np.float64)
+    print(f"[case] velocity field PC dim={dim} rb={rb} n={spec.n}", flush=True)
+    ctx = Context([params_from_spec(spec, integrator=_lib.ADE_PC, flags=_lib.ADE_VELOCITY_FIELD)], [spec.n])
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C0)).set_velocities(torch.from_numpy(v)).build()
+    ctx.step(steps)
+    assert ctx.info()["step"] == steps
+    C = ctx.read_C().double().cpu().numpy()
+    xg = ctx.read_x().cpu().numpy()
+    xo, Co, _ = O.run(O.model_from_spec(spec), x, C0, spec.dt, steps, v=v, mass=spec.mass, rho=spec.rho0,
+                      integrator=2)
+    assert np.array_equal(xg, xo)
+    assert _rel(C, Co) < (1e-12 if rb == 8 else 1e-5)
+    # and it is not the Euler run
+    _, Ce, _ = O.run(O.model_from_spec(spec), x, C0, spec.dt, steps, v=v, mass=spec.mass, rho=spec.rho0)
+    assert _rel(Ce, Co) > 1e-7
+    off, ids = ctx.neighbours()
+    off, ids = off.cpu().numpy(), ids.cpu().numpy()
+    seg = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    ids = ids[np.lexsort((ids, seg))]
+    o_off, o_ids = O.neighbours_fixed(dim, xo, spec.L, spec.H, rb)
+    assert np.array_equal(off, o_off) and np.array_equal(ids, o_ids)
+    ctx.close()
+
+
+def test_velocity_field_pc_graph_replay_and_adjoint_rejected():
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = _spec(2, 4, 48, 4, 1.5)
+    x = spec.positions()
+    v = torch.from_numpy(I.velocity_field(x, spec.L, quantum=2.0 ** -19))
+    C0 = torch.from_numpy(spec.concentration(x).astype(np.float32))
+    p = params_from_spec(spec, integrator=_lib.ADE_PC, flags=_lib.ADE_VELOCITY_FIELD)
+    outs = []
+    for graph in (False, True):
+        stream = torch.cuda.Stream()
+        ctx = Context([p], [spec.n], stream=stream)
+        ctx.init(torch.from_numpy(x), C0).set_velocities(v).build()
+        if graph:
+            for _ in range(3):
+                ctx.step_graph(4)
+                torch.cuda.synchronize()
+        else:
+            ctx.step(12)
+        outs.append((ctx.read_C().cpu().numpy().copy(), ctx.read_x().cpu().numpy().copy()))
+        stream.synchronize()
+        if graph:
+            xs = torch.from_numpy(I.sensors(8, [0.1, 0.1], [0.9, 0.9]))
+            with pytest.raises(_lib.AdeError) as e:
+                ctx.adjoint(4, 2, xs, torch.zeros(8, dtype=torch.float32))
+            assert e.value.code == _lib.ADE_EINVAL
+        ctx.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
 def test_velocity_field_moves_on_the_exact_schedule():
     """Velocities that are not whole fixed-point units per step: after k steps
     a particle has moved by rint(k u) units, u = dt v / L 2^32 (FP64 state)."""
