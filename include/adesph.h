@@ -172,10 +172,14 @@ int ade_set_velocities(ade_ctx *ctx, const double *d_v);
  * rebuilds it. */
 int ade_build_cells(ade_ctx *ctx);
 
-/* nsteps explicit steps (pair sum of Eqs. 4-5, update of C and x, rebuild). */
+/* nsteps explicit steps (pair sum of Eqs. 4-5, update of C and x, rebuild).
+ * With ADE_CHECK_FINITE on any plume of the context, the concentrations are
+ * checked after the last step (the stream is synchronised) and a NaN or an
+ * infinity returns ADE_ENONFINITE (the steps have run). */
 int ade_step(ade_ctx *ctx, int64_t nsteps);
 
-/* The same steps replayed from a HIP graph holding one captured step. */
+/* The same steps replayed from a HIP graph holding one captured step (the
+ * finite check as for ade_step, after the replays). */
 int ade_step_graph(ade_ctx *ctx, int64_t nsteps);
 
 /* rhs of Eq. (4) at the current state, written in particle-id order to
@@ -250,6 +254,18 @@ int ade_get_tuning(const ade_ctx *ctx, ade_tuning *t);
  * step of plume p actually used, and the step counter. */
 int ade_info(const ade_ctx *ctx, int32_t plume, int64_t *n_total, int64_t *n_cells,
              int64_t *n_tiles, double *dt, int64_t *step);
+
+/* Checkpoint and resume.  ade_state_bytes gives the size of a saved state
+ * (host-only).  ade_save_state copies the context's state (the sorted
+ * particle state with its candidate records and velocity-field arrays, the
+ * cell table and the step counter; after ade_build_cells) into the caller's
+ * host buffer h_buf of at least that many bytes, synchronising the stream.
+ * ade_load_state puts such a state into a context created with the same
+ * parameters and counts (ADE_EINVAL otherwise, or for a short buffer): the
+ * context then continues bit-identically to the one saved, as if built. */
+int ade_state_bytes(const ade_ctx *ctx, size_t *bytes);
+int ade_save_state(const ade_ctx *ctx, void *h_buf, size_t bytes);
+int ade_load_state(ade_ctx *ctx, const void *h_buf, size_t bytes);
 
 int ade_destroy(ade_ctx *ctx);
 

@@ -25,7 +25,8 @@ ERROR_NAMES = {0: "ADE_OK", -1: "ADE_EINVAL", -2: "ADE_EWORKSPACE", -3: "ADE_EHI
 EXPORTS = ["ade_workspace_bytes", "ade_create", "ade_init_particles", "ade_set_velocities", "ade_build_cells",
            "ade_step", "ade_step_graph", "ade_rhs", "ade_read_C", "ade_read_x", "ade_mass",
            "ade_neighbours", "ade_sensor_interp", "ade_adjoint_workspace_bytes", "ade_adjoint",
-           "ade_kernel_timing", "ade_autotune", "ade_set_tuning", "ade_get_tuning", "ade_info", "ade_destroy", "ade_last_error",
+           "ade_kernel_timing", "ade_autotune", "ade_set_tuning", "ade_get_tuning", "ade_info",
+           "ade_state_bytes", "ade_save_state", "ade_load_state", "ade_destroy", "ade_last_error",
            "ade_version"]
 
 
@@ -86,6 +87,9 @@ def lib() -> ct.CDLL:
         "ade_set_tuning": [p, T],
         "ade_get_tuning": [p, T],
         "ade_info": [p, i32, pi64, pi64, pi64, pd, pi64],
+        "ade_state_bytes": [p, psz],
+        "ade_save_state": [p, p, sz],
+        "ade_load_state": [p, p, sz],
         "ade_destroy": [p],
     }
     for name, args in sigs.items():

@@ -5,6 +5,7 @@ from __future__ import annotations
 import ctypes as ct
 from typing import Sequence
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -159,6 +160,20 @@ class Context:
         ids = self._empty(max(need.value, 1), dtype=torch.int32)
         check(lib().ade_neighbours(self._h, _ptr(offsets), _ptr(ids), need.value, ct.byref(need)))
         return self._out(offsets), self._out(ids)[: need.value]
+
+    def save_state(self) -> np.ndarray:
+        """The context's state (ade_save_state) as a host byte array."""
+        nb = ct.c_size_t(0)
+        check(lib().ade_state_bytes(self._h, ct.byref(nb)))
+        buf = np.zeros(nb.value, dtype=np.uint8)
+        check(lib().ade_save_state(self._h, buf.ctypes.data_as(ct.c_void_p), nb.value))
+        return buf
+
+    def load_state(self, buf: np.ndarray):
+        """Resume from a state saved by a context of the same parameters."""
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        check(lib().ade_load_state(self._h, buf.ctypes.data_as(ct.c_void_p), buf.nbytes))
+        return self
 
     def neighbour_counts(self) -> torch.Tensor:
         """offsets (N+1,) int64 of the neighbour lists (id order), without the ids."""

@@ -109,6 +109,8 @@ int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes,
     pl.kernel = p0.kernel;
     pl.integrator = p0.integrator;
     pl.general = (p0.flags & ADE_VELOCITY_FIELD) != 0;
+    pl.check_finite = false;
+    for (int p = 0; p < nplumes; ++p) pl.check_finite = pl.check_finite || (params[p].flags & ADE_CHECK_FINITE);
     pl.P = nplumes;
     if (pl.dim != 2 && pl.dim != 3) return fail(ADE_EINVAL, "dim must be 2 or 3 (got %d)", pl.dim);
     if (pl.real_bytes != 4 && pl.real_bytes != 8) return fail(ADE_EINVAL, "real_bytes must be 4 or 8");
@@ -338,6 +340,16 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
     c->aux_rec = (pl.dim == 3 && pl.real_bytes == 8) ? nullptr : b.take<uint4>(N);
     c->mass_partial = b.take<double>(pl.ntiles);
     c->step = b.take<int64_t>(1);
+    c->nonfinite = b.take<uint32_t>(1);
+}
+
+// finite check of the sorted concentrations: any NaN or infinity sets *flag
+// (vector stores of the same value, order-free)
+template <typename real>
+__global__ __launch_bounds__(256) void k_check_finite(const real* __restrict__ C, uint32_t N,
+                                                     uint32_t* __restrict__ flag) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < N && !isfinite(C[i])) *flag = 1u;
 }
 
 // Sum the recorded event pairs into the totals and recycle the events.
@@ -625,6 +637,27 @@ int ade_build_cells(ade_ctx* c) {
     return ADE_OK;
 }
 
+// ADE_CHECK_FINITE: after a call's steps, every concentration must be finite
+// (synchronises the stream)
+static int check_finite(ade_ctx* c) {
+    const Plan& pl = c->plan;
+    if (!pl.check_finite) return ADE_OK;
+    uint32_t h = 0;
+    HIPCHK(hipMemsetAsync(c->nonfinite, 0, sizeof(uint32_t), c->stream));
+    const uint32_t N = (uint32_t)pl.N;
+    if (pl.real_bytes == 4)
+        hipLaunchKernelGGL((k_check_finite<float>), dim3((N + 255) / 256), dim3(256), 0, c->stream,
+                           (const float*)c->S.C, N, c->nonfinite);
+    else
+        hipLaunchKernelGGL((k_check_finite<double>), dim3((N + 255) / 256), dim3(256), 0, c->stream,
+                           (const double*)c->S.C, N, c->nonfinite);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(&h, c->nonfinite, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (h) return fail(ADE_ENONFINITE, "a concentration is not finite after the step (ADE_CHECK_FINITE)");
+    return ADE_OK;
+}
+
 int ade_step(ade_ctx* c, int64_t nsteps) {
     if (!c) return fail(ADE_EINVAL, "null ctx");
     if (nsteps < 0) return fail(ADE_EINVAL, "nsteps must be >= 0");
@@ -633,7 +666,7 @@ int ade_step(ade_ctx* c, int64_t nsteps) {
         int rc = enqueue_step(c);
         if (rc) return rc;
     }
-    return ADE_OK;
+    return nsteps > 0 ? check_finite(c) : ADE_OK;
 }
 
 int ade_step_graph(ade_ctx* c, int64_t nsteps) {
@@ -661,7 +694,7 @@ int ade_step_graph(ade_ctx* c, int64_t nsteps) {
         }
     }
     for (int64_t s = 0; s < nsteps; ++s) HIPCHK(hipGraphLaunch(c->graph_exec, c->stream));
-    return ADE_OK;
+    return nsteps > 0 ? check_finite(c) : ADE_OK;
 }
 
 int ade_rhs(ade_ctx* c, void* d_rhs) {
@@ -849,6 +882,107 @@ int ade_info(const ade_ctx* c, int32_t plume, int64_t* n_total, int64_t* n_cells
         HIPCHK(hipStreamSynchronize(c->stream));
         *step = v;
     }
+    return ADE_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// A saved state: this header, then the sorted particle state as the device
+// holds it (positions, C, ids, candidate records, the velocity-field arrays),
+// the cell-start table (with its sentinel) and the step counter: everything
+// the next step reads, so a loaded state continues bit-identically.
+struct StateHeader {
+    uint64_t magic;
+    uint32_t dim, real_bytes, general, integrator;
+    uint64_t N, ncell, bytes;
+};
+constexpr uint64_t kStateMagic = 0x3154415453454441ull;  // "ADESTAT1"
+
+struct Section {
+    void* dev;
+    size_t bytes;
+};
+
+std::vector<Section> state_sections(const ade_ctx* c) {
+    const Plan& pl = c->plan;
+    const size_t N = (size_t)pl.N, rb = (size_t)pl.real_bytes;
+    const StateArrays& S = c->S;
+    std::vector<Section> v;
+    for (int d = 0; d < pl.dim; ++d) v.push_back({S.pos[d], N * 4});
+    v.push_back({S.C, N * rb});
+    v.push_back({S.id, N * 4});
+    if (S.rec) v.push_back({S.rec, N * 16});
+    for (int d = 0; d < 3; ++d)
+        if (S.vel[d]) v.push_back({S.vel[d], N * rb});
+    for (int d = 0; d < 6; ++d)
+        if (S.rD[d]) v.push_back({S.rD[d], N * rb});
+    if (S.grec) v.push_back({S.grec, N * 32});
+    v.push_back({c->cell_start, ((size_t)pl.ncell + 1) * 4});
+    v.push_back({c->step, 8});
+    return v;
+}
+
+size_t state_size(const ade_ctx* c) {
+    size_t b = sizeof(StateHeader);
+    for (const Section& s : state_sections(c)) b += s.bytes;
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ade_state_bytes(const ade_ctx* c, size_t* bytes) {
+    if (!c || !bytes) return fail(ADE_EINVAL, "null argument");
+    *bytes = state_size(c);
+    return ADE_OK;
+}
+
+int ade_save_state(const ade_ctx* c, void* h_buf, size_t bytes) {
+    if (!c || !h_buf) return fail(ADE_EINVAL, "null argument");
+    if (!c->built) return fail(ADE_ESTATE, "ade_save_state before ade_build_cells");
+    const size_t need = state_size(c);
+    if (bytes < need) return fail(ADE_EINVAL, "state buffer too small: need %zu bytes", need);
+    const Plan& pl = c->plan;
+    StateHeader h{kStateMagic, (uint32_t)pl.dim, (uint32_t)pl.real_bytes, pl.general ? 1u : 0u,
+                  (uint32_t)pl.integrator, (uint64_t)pl.N, (uint64_t)pl.ncell, (uint64_t)need};
+    char* p = static_cast<char*>(h_buf);
+    std::memcpy(p, &h, sizeof h);
+    p += sizeof h;
+    for (const Section& s : state_sections(c)) {
+        HIPCHK(hipMemcpyAsync(p, s.dev, s.bytes, hipMemcpyDeviceToHost, c->stream));
+        p += s.bytes;
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return ADE_OK;
+}
+
+int ade_load_state(ade_ctx* c, const void* h_buf, size_t bytes) {
+    if (!c || !h_buf) return fail(ADE_EINVAL, "null argument");
+    const Plan& pl = c->plan;
+    StateHeader h;
+    if (bytes < sizeof h) return fail(ADE_EINVAL, "state buffer too small");
+    std::memcpy(&h, h_buf, sizeof h);
+    const size_t need = state_size(c);
+    if (h.magic != kStateMagic || h.dim != (uint32_t)pl.dim || h.real_bytes != (uint32_t)pl.real_bytes ||
+        h.general != (pl.general ? 1u : 0u) || h.integrator != (uint32_t)pl.integrator ||
+        h.N != (uint64_t)pl.N || h.ncell != (uint64_t)pl.ncell || h.bytes != need)
+        return fail(ADE_EINVAL, "saved state does not belong to a context of these parameters");
+    if (bytes < need) return fail(ADE_EINVAL, "state buffer too small: need %zu bytes", need);
+    const char* p = static_cast<const char*>(h_buf) + sizeof h;
+    for (const Section& s : state_sections(c)) {
+        HIPCHK(hipMemcpyAsync(s.dev, p, s.bytes, hipMemcpyHostToDevice, c->stream));
+        p += s.bytes;
+    }
+    // the next step's counting pass starts from empty cells
+    HIPCHK(hipMemsetAsync(c->count, 0, sizeof(uint32_t) * cell_pad(pl.ncell), c->stream));
+    HIPCHK(hipMemsetAsync(c->lists.ovf_count, 0, 2 * sizeof(uint32_t), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->initialized = true;
+    c->built = true;
+    c->vel_set = true;
     return ADE_OK;
 }
 

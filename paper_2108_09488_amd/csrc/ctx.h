@@ -32,6 +32,7 @@ struct Plan {
     int list_cap_pair = 0;  // the same for a lane's merged list of two targets
     double nbar_max = 0.0;  // largest expected neighbours per particle of a plume
     bool general = false;   // velocity field: per-particle velocities (ADE_VELOCITY_FIELD)
+    bool check_finite = false;  // ADE_CHECK_FINITE on any plume
     std::vector<PlumeDev> plumes;
     std::vector<TileDev> tiles;
     std::vector<TileDev> pair_tiles;  // the tiles in the pair kernel's order (costliest plumes first)
@@ -61,6 +62,7 @@ struct ade_ctx {
     uint4* aux_rec = nullptr;
     double* mass_partial = nullptr;
     int64_t* step = nullptr;
+    uint32_t* nonfinite = nullptr;  // finite check: set when a concentration is not finite
     uint32_t h_total = 0;  // host copy of N for the cell-start sentinel
     bool initialized = false, built = false;
     bool vel_set = false;  // velocity field: ade_set_velocities called since init

@@ -132,3 +132,78 @@ def test_tiny_plumes_in_an_ensemble():
     assert np.array_equal(alone.read_C().cpu().numpy(), Ce[:big.n])
     alone.close()
     ens.close()
+
+
+@pytest.mark.parametrize("flags", [0, _lib.ADE_CHECK_FINITE])
+def test_finite_check(flags):
+    """A NaN forced into C from the host: with ADE_CHECK_FINITE the step
+    reports ADE_ENONFINITE (eager and graph replay); without it the steps run
+    and the NaN spreads to the neighbours."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = I.config("cfg1", n_side=32, real_bytes=4, kernel=4, h_over_dp=1.5)
+    x = spec.positions()
+    C = spec.concentration(x).astype(np.float32)
+    clean = C.copy()
+    C[spec.n // 2] = np.nan
+    print(f"[case] finite check flags={flags}", flush=True)
+    for graph in (False, True):
+        stream = torch.cuda.Stream()
+        ctx = Context([params_from_spec(spec, flags=flags)], [spec.n], stream=stream)
+        ctx.init(torch.from_numpy(x), torch.from_numpy(clean)).build()
+        (ctx.step_graph if graph else ctx.step)(2)  # finite: no error either way
+        ctx.init(torch.from_numpy(x), torch.from_numpy(C)).build()
+        if flags:
+            with pytest.raises(_lib.AdeError) as e:
+                (ctx.step_graph if graph else ctx.step)(2)
+            assert e.value.code == _lib.ADE_ENONFINITE
+        else:
+            (ctx.step_graph if graph else ctx.step)(2)
+            assert np.isnan(ctx.read_C().cpu().numpy()).sum() > 1
+        stream.synchronize()
+        ctx.close()
+
+
+@pytest.mark.parametrize("velocity_field,integrator", [(False, 1), (False, 2), (True, 1), (True, 2)])
+def test_save_and_resume_is_bit_identical(velocity_field, integrator):
+    """ade_save_state after some steps, ade_load_state into a fresh context of
+    the same parameters: the resumed run matches the uninterrupted one bit for
+    bit (C, positions, step counter).  A state of other parameters, or a
+    short buffer, is rejected."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = I.config("cfg2_h20_r10", n_side=96)
+    x = spec.positions()
+    C = spec.concentration(x).astype(np.float32)
+    flags = _lib.ADE_VELOCITY_FIELD if velocity_field else 0
+    p = params_from_spec(spec, integrator=integrator, flags=flags)
+    v = torch.from_numpy(I.velocity_field(x, spec.L, quantum=2.0 ** -20))
+    print(f"[case] save/resume vf={velocity_field} integ={integrator}", flush=True)
+
+    def fresh():
+        c = Context([p], [spec.n])
+        c.init(torch.from_numpy(x), torch.from_numpy(C))
+        if velocity_field:
+            c.set_velocities(v)
+        return c.build()
+
+    a = fresh()
+    a.step(7)
+    state = a.save_state()
+    a.step(9)
+    Ca, xa, sa = a.read_C().cpu().numpy(), a.read_x().cpu().numpy(), a.info()["step"]
+    b = Context([p], [spec.n])
+    b.load_state(state)
+    assert b.info()["step"] == 7
+    b.step(9)
+    assert np.array_equal(b.read_C().cpu().numpy(), Ca)
+    assert np.array_equal(b.read_x().cpu().numpy(), xa)
+    assert b.info()["step"] == sa == 16
+    with pytest.raises(_lib.AdeError) as e:
+        b.load_state(state[: len(state) - 1])
+    assert e.value.code == _lib.ADE_EINVAL
+    other = Context([params_from_spec(I.config("cfg2_h20_r10", n_side=64), integrator=integrator, flags=flags)],
+                    [64 * 64])
+    with pytest.raises(_lib.AdeError) as e:
+        other.load_state(state)
+    assert e.value.code == _lib.ADE_EINVAL
+    for c in (a, b, other):
+        c.close()
