@@ -148,9 +148,29 @@ def batched(device, steps, warmup, n_plumes=256):
     wall = time.perf_counter() - t0
     n = ctx.N
     ctx.close()
+    # plain reference at the ensemble's neighbour count: one 512^2 plume with
+    # h = 1.5 dp (the ensemble's smoothing length), the same kernel and jitter
+    ref = I.config("cfg2_h20_r10", h_over_dp=1.5)
+    rc = Context([params_from_spec(ref)], [ref.n], device=device, stream=stream)
+    xr = ref.positions()
+    rc.init(torch.from_numpy(xr), torch.from_numpy(ref.concentration(xr).astype(np.float32))).build()
+    rinter = int(rc.neighbour_counts()[-1].item())
+    rc.autotune(reps=3)
+    rc.step_graph(warmup)
+    _sync()
+    t0 = time.perf_counter()
+    rc.step_graph(steps)
+    _sync()
+    rwall = time.perf_counter() - t0
+    rc.close()
+    plain = rinter * steps / rwall
+    rate = inter * steps / wall
     return {"plumes": n_plumes, "particles": n, "interactions_per_step": inter,
             "steps": steps, "ms_per_step": 1e3 * wall / steps, "tuning": tuned,
-            "interactions_per_s": inter * steps / wall}
+            "interactions_per_s": rate,
+            "plain_same_nbar": {"workload": "one 512^2 plume, h/dp 1.5, C4, FP32, graph replay",
+                                "neighbours_mean": rinter / ref.n, "interactions_per_s": plain},
+            "vs_plain_same_nbar": rate / plain}
 
 
 def fwd_adjoint(device):
