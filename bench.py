@@ -40,6 +40,15 @@ PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published vector FP32 (packed FMA)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.md")
 PAIR_SOURCES = ["kernels_pair.hip", "ade_walk.h", "ade_geom.h", "ade_device.h", "ade_internal.h"]
 PEAK_FP32_NONPACKED_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA)
+# single-issue VALU roof: 256 CU x 64 lanes x 2.4 GHz lane-slots per second, and
+# the issue slots one directed interaction needs (the pair term's operations,
+# the reciprocal square root at 4 slots): the VALU fraction of a pair kernel
+VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+ISSUE_SLOTS_PER_INTERACTION = {2: 27, 3: 36}
+
+
+def valu_issue_frac(dim, interactions, seconds):
+    return ISSUE_SLOTS_PER_INTERACTION[dim] * interactions / seconds / VALU_SLOTS_PER_S
 
 
 def step_kernel_name(tuning):
@@ -242,7 +251,8 @@ def single_3d(device, steps=10):
     wall = time.perf_counter() - t0
     c.close()
     return {"particles": s.n, "interactions_per_step": inter, "steps": steps, "tuning": tuned,
-            "ms_per_step": 1e3 * wall / steps, "interactions_per_s": inter * steps / wall}
+            "ms_per_step": 1e3 * wall / steps, "interactions_per_s": inter * steps / wall,
+            "valu_issue_frac_of_step": valu_issue_frac(3, inter * steps, wall)}
 
 
 def velocity_field(device, steps=50, warmup=3):
@@ -330,7 +340,8 @@ def paper_scale(device, steps=3):
                      "cells": cells, "steps": steps, "tuning": tuning, "ms_per_step": 1e3 * wall / steps,
                      "pair_kernel_ms": ms / n, "interactions_per_s": inter * steps / wall,
                      "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                                  "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS}}
+                                  "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+                                  "valu_issue_frac": valu_issue_frac(2, inter, ms / n * 1e-3)}}
         _sync()
         print(f"[bench] {name}: {out[name]['ms_per_step']:.1f} ms/step, "
               f"{out[name]['interactions_per_s']:.3e} interactions/s", file=sys.stderr, flush=True)
@@ -520,6 +531,7 @@ def main():
                      "launches": pair["launches"],
                      "flops_per_interaction": FLOPS_PER_INTERACTION[2],
                      "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+                     "valu_issue_frac": valu_issue_frac(2, inter_step * pair["launches"], pair["ms_total"] * 1e-3),
                      "l2_hit_rate": pair_profile(step_kernel_name(sweep["tuning"]), "l2_hit_rate"),
                      "l1_hit_rate": pair_profile(step_kernel_name(sweep["tuning"]), "l1_hit_rate")},
         "extras": extras,
