@@ -150,6 +150,7 @@ struct GenLaunch {
     const TileDev* tiles;
     uint32_t ntiles;
     int list_cap;
+    int lanes;              // lanes per target particle: 1, 2 or 4
     StateArrays S, U;
     const uint32_t* cell_start;
     CellLists lists;

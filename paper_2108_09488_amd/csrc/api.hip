@@ -461,6 +461,9 @@ GenLaunch gen_args(ade_ctx* c, void* out) {
     g.tiles = c->pair_tiles;
     g.ntiles = c->plan.ntiles;
     g.list_cap = c->plan.list_cap;
+    // four lanes per target: on the 512^2 plume 49-51 us per update launch,
+    // against 52-53 (two lanes) and 54-56 (one)
+    g.lanes = 4;
     g.S = c->S;
     g.U = c->U;
     g.cell_start = c->cell_start;

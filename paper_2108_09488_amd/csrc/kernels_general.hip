@@ -147,28 +147,89 @@ __device__ __forceinline__ double hmean(double ra, double rb) {
 __device__ __forceinline__ float hmean_diag(float ra, float rb) { return __builtin_amdgcn_rcpf(ra + rb); }
 __device__ __forceinline__ double hmean_diag(double ra, double rb) { return 1.0 / (ra + rb); }
 
-// A work item = blockDim.x consecutive targets of one tile (blockDim.x a
-// divisor of the tile, chosen so the candidate lists fit in LDS).
-template <int DIM, typename real, int KERN, int MODE>
+// The walk of a target's list by its LANES lanes: lane lj evaluates records
+// lj, lj + LANES, ... of the concatenated ranges, B at a time with the next
+// batch in flight; slots past the end of its share re-read record `self`
+// (the target's own: r2 = 0, rejected by the predicate).  The wavefront runs
+// as many batches as its largest share needs.
+template <int LANES, int B, typename Fetch, typename Eval>
+__device__ __forceinline__ void walk_lanes(const uint2* list, uint32_t stride, uint32_t total, uint32_t lj,
+                                           uint32_t self, Fetch&& fetch, Eval&& eval) {
+    using CandT = decltype(fetch(0u));
+    uint32_t share = total > lj ? (total - lj + LANES - 1) / LANES : 0u;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
+    const uint32_t nb = __builtin_amdgcn_readfirstlane((share + B - 1) / B);
+    if (nb == 0) return;
+    Cursor<LANES> cur;
+    cur.b = lj * kRecBytes;
+    cur.e = 0;
+    cur.lp = list;
+    cur.stride = stride;
+    cur.nx = list[0];
+    cur.settle();
+    __builtin_amdgcn_s_waitcnt(0);
+    CandT c0[B], c1[B];
+    auto fill = [&](CandT(&c)[B]) {
+        uint32_t idx[B];
+#pragma unroll
+        for (int q = 0; q < B; ++q) {
+            idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
+            cur.b += Cursor<LANES>::kStep;
+            cur.settle();
+        }
+#pragma unroll
+        for (int q = 0; q < B; ++q) c[q] = fetch(idx[q]);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto run = [&](const CandT(&c)[B]) {
+#pragma unroll
+        for (int q = 0; q < B; ++q) eval(c[q], true);
+    };
+    fill(c0);
+    for (uint32_t it = 1;; it += 2) {
+        if (it >= nb) {
+            run(c0);
+            break;
+        }
+        fill(c1);
+        run(c0);
+        if (it + 1 >= nb) {
+            run(c1);
+            break;
+        }
+        fill(c0);
+        run(c1);
+    }
+}
+
+// A work item = blockDim.x / LANES consecutive targets of one tile (a
+// divisor of the tile, chosen so the candidate lists fit in LDS), LANES lanes
+// per target.
+template <int DIM, typename real, int KERN, int MODE, int LANES>
 __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
     extern __shared__ uint2 lds_list[];
     constexpr int NT = GenDims<DIM>::kT;
-    const uint32_t tpb = blockDim.x, subs = kTile / tpb;
+    const uint32_t tpb = blockDim.x / LANES, subs = kTile / tpb;
     const TileDev t = g.tiles[blockIdx.x / subs];
     const uint32_t i0 = t.start + (blockIdx.x % subs) * tpb;
     if (i0 >= t.end) return;  // whole workgroup: ragged last tile
     const uint32_t i1 = min(t.end, i0 + tpb);
     const PlumeDev P = g.plumes[t.plume];
-    const bool active = i0 + threadIdx.x < i1;
-    const uint32_t i = active ? i0 + threadIdx.x : i0;
+    const uint32_t lt = threadIdx.x / LANES, lj = threadIdx.x % LANES;
+    // lanes past the end of a ragged tile stay in the walk (the wavefront
+    // reductions need every lane) with an empty list and target i0
+    const bool active = i0 + lt < i1;
+    const uint32_t i = active ? i0 + lt : i0;
 
     const StateArrays& S = g.S;
     const GPart<DIM, real> A = load_part<DIM, real>(S, i);
     const Target T = make_target<DIM>(P, A.x, A.y, A.z);
 
-    uint2* list = lds_list + threadIdx.x;
+    // every lane of a target writes the same list
+    uint2* list = lds_list + lt;
     uint32_t total = 0;
-    if (active) total = build_list<DIM, 1>(P, g.cell_start, T, list, tpb);
+    if (active) total = build_list<DIM, LANES>(P, g.cell_start, T, list, tpb);
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
 
     const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
@@ -220,8 +281,17 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
         if (DIM == 3) vx = fmar(A.v[DIM - 1] - c.v[DIM - 1], dz, vx);
         conv = fmar(f, vx, conv);
     };
-    walk_stream<kGenBatch>(list, tpb, total, i, fetch, eval);
-    if (!active) return;
+    walk_lanes<LANES, kGenBatch>(list, tpb, total, lj, i, fetch, eval);
+    // the lanes of a target combine their sums (fixed order: deterministic)
+    if (LANES >= 2) {
+        disp += __shfl_xor(disp, 1, kWave);
+        conv += __shfl_xor(conv, 1, kWave);
+    }
+    if (LANES >= 4) {
+        disp += __shfl_xor(disp, 2, kWave);
+        conv += __shfl_xor(conv, 2, kWave);
+    }
+    if (!active || lj != 0) return;
 
     // 1/2 of the sum of Dcal terms = 2 disp (disp sums Dcal / 4); x_ab of the
     // convective term is in grid units, L / 2^32 each
@@ -454,23 +524,31 @@ hipError_t launch_setvel(int dim, int real_bytes, const PlumeDev* plumes, const 
     return hipGetLastError();
 }
 
-template <int DIM, typename real, int KERN>
-static hipError_t launch_gen_t(int mode, const GenLaunch& g, hipStream_t s) {
-    uint32_t block = 256;  // the largest divisor of the tile whose lists fit in LDS
-    while (block > 64 && (size_t)block * (size_t)g.list_cap * 8u > kPairLdsMax) block /= 2;
-    const size_t shm = (size_t)block * (size_t)g.list_cap * 8u;
+template <int DIM, typename real, int KERN, int LANES>
+static hipError_t launch_gen_l(int mode, const GenLaunch& g, hipStream_t s) {
+    uint32_t block = 256;  // the largest workgroup whose lists fit in LDS
+    while (block > 64 && (size_t)(block / LANES) * (size_t)g.list_cap * 8u > kPairLdsMax) block /= 2;
+    const size_t shm = (size_t)(block / LANES) * (size_t)g.list_cap * 8u;
     if (shm > kPairLdsMax) return hipErrorInvalidValue;
     if (DIM == 2 && sizeof(real) == 4 && !g.S.grec) return hipErrorInvalidValue;
-    dim3 gr(g.ntiles * (kTile / block)), b(block);
-    auto kern = (mode == kModeStep)   ? k_pair_gen<DIM, real, KERN, kModeStep>
-                : (mode == kModeHalf) ? k_pair_gen<DIM, real, KERN, kModeHalf>
-                : (mode == kModeFull) ? k_pair_gen<DIM, real, KERN, kModeFull>
-                                      : k_pair_gen<DIM, real, KERN, kModeRhs>;
+    dim3 gr(g.ntiles * (kTile / (block / LANES))), b(block);
+    auto kern = (mode == kModeStep)   ? k_pair_gen<DIM, real, KERN, kModeStep, LANES>
+                : (mode == kModeHalf) ? k_pair_gen<DIM, real, KERN, kModeHalf, LANES>
+                : (mode == kModeFull) ? k_pair_gen<DIM, real, KERN, kModeFull, LANES>
+                                      : k_pair_gen<DIM, real, KERN, kModeRhs, LANES>;
     if (g.ev0)  // timed launch: the events carry the kernel's own start and end stamps
         hipExtLaunchKernelGGL(kern, gr, b, (uint32_t)shm, s, g.ev0, g.ev1, 0u, g);
     else
         hipLaunchKernelGGL(kern, gr, b, shm, s, g);
     return hipGetLastError();
+}
+
+template <int DIM, typename real, int KERN>
+static hipError_t launch_gen_t(int mode, const GenLaunch& g, hipStream_t s) {
+    if (g.lanes == 4) return launch_gen_l<DIM, real, KERN, 4>(mode, g, s);
+    if (g.lanes == 2) return launch_gen_l<DIM, real, KERN, 2>(mode, g, s);
+    if (g.lanes == 1) return launch_gen_l<DIM, real, KERN, 1>(mode, g, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_pair_gen(int dim, int real_bytes, int kernel, int mode, const GenLaunch& g, hipStream_t s) {
