@@ -399,6 +399,9 @@ struct Snap {
 };
 
 constexpr uint32_t kAdjMaxSubs = 4;  // workgroups per tile of the adjoint passes (64 threads)
+// the velocity-field pass: 256 threads, four lanes per target, so 64 targets
+// and kAdjMaxSubs workgroups per tile
+constexpr uint32_t kGenAdjBlock = 256;
 
 // threads per workgroup of the adjoint passes: the largest of 256, 128, 64
 // whose candidate lists fit in 64 KiB of LDS
@@ -691,7 +694,7 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
                 ga.lam_s = L.lam_s;
                 ga.lam_out = L.lam[1 - li];
                 ga.gpart = L.gpart;
-                HIPCHK(launch_adjoint_gen(pl.dim, pl.real_bytes, pl.kernel, ga, ab, st));
+                HIPCHK(launch_adjoint_gen(pl.dim, pl.real_bytes, pl.kernel, ga, kGenAdjBlock, st));
             } else if (pl.integrator == ADE_PC) {
 #define CALL(D, R, KK)                                                                                    \
     LAUNCH(D, R, KK, kAdjHalf, L.lam_s, sn.C, L.arec, L.mu_s, L.ch_s, L.arec2);                              \
@@ -710,7 +713,8 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     }
     // leave the context at step nsteps
     if ((rc = copy_state(c, cur, L.ck[(size_t)nck]))) return rc;
-    hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, L.gpart, pl.ntiles * asubs, L.grad);
+    const uint32_t nparts = pl.ntiles * (pl.general ? kAdjMaxSubs : asubs);  // workgroups of the passes
+    hipLaunchKernelGGL(k_grad_reduce, dim3(1), dim3(256), 0, st, L.gpart, nparts, L.grad);
     HIPCHK(hipGetLastError());
     double hostv[4];
     HIPCHK(hipMemcpyAsync(hostv, L.grad, 3 * 8, hipMemcpyDeviceToHost, st));

@@ -372,19 +372,20 @@ __device__ __forceinline__ void tensor_derivs(const real* v, real (&dD)[3][GenDi
 //     d(h/4)_ij = (q^2 dp + p^2 dq) / (p + q)^2   (0 where p q <= 0),
 // and no convective part (it does not depend on theta).  The tensors come
 // from the stored reciprocals (1 / inf = 0 for a zero component).
-template <int DIM, typename real, int KERN>
+template <int DIM, typename real, int KERN, int LANES>
 __global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
     extern __shared__ uint2 lds_list[];
     __shared__ double lds[kTile / kWave];
     constexpr int NT = GenDims<DIM>::kT;
-    const uint32_t tpb = blockDim.x, subs = kTile / tpb;
+    const uint32_t tpb = blockDim.x / LANES, subs = kTile / tpb;
     const TileDev t = g.tiles[blockIdx.x / subs];
     const uint32_t i0 = t.start + (blockIdx.x % subs) * tpb;
     if (i0 >= t.end) return;  // whole workgroup: ragged last tile
     const uint32_t i1 = min(t.end, i0 + tpb);
     const PlumeDev P = g.plumes[t.plume];
-    const bool active = i0 + threadIdx.x < i1;
-    const uint32_t i = active ? i0 + threadIdx.x : i0;
+    const uint32_t lt = threadIdx.x / LANES, lj = threadIdx.x % LANES;
+    const bool active = i0 + lt < i1;
+    const uint32_t i = active ? i0 + lt : i0;
 
     const StateArrays& S = g.S;
     const real* __restrict__ lam_s = static_cast<const real*>(g.lam_s);
@@ -396,9 +397,9 @@ __global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
     for (int q = 0; q < NT; ++q) Da[q] = (real)1 / A.r[q];
     tensor_derivs<DIM, real>(A.v, dA);
 
-    uint2* list = lds_list + threadIdx.x;
+    uint2* list = lds_list + lt;
     uint32_t total = 0;
-    if (active) total = build_list<DIM, 1>(P, g.cell_start, T, list, tpb);
+    if (active) total = build_list<DIM, LANES>(P, g.cell_start, T, list, tpb);
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
 
     const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
@@ -476,16 +477,28 @@ __global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
             gk[th] = fmar(bracket(dh, dx, dy, dz, ir2), dC, gk[th]);
         }
     };
-    walk_stream<kGenBatch>(list, tpb, total, i, fetch, eval);
+    walk_lanes<LANES, kGenBatch>(list, tpb, total, lj, i, fetch, eval);
+    // the lanes of a target combine their sums (fixed order: deterministic)
+    real red[5] = {al, cv, gk[0], gk[1], gk[2]};
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        if (LANES >= 2) red[k] += __shfl_xor(red[k], 1, kWave);
+        if (LANES >= 4) red[k] += __shfl_xor(red[k], 2, kWave);
+    }
+    al = red[0];
+    cv = red[1];
+    gk[0] = red[2];
+    gk[1] = red[3];
+    gk[2] = red[4];
 
     const double sd = P.dt * P.vphi;
-    if (active) {
+    if (active && lj == 0) {
         // 1/2 of the sum of Dcal terms = 2 al (al sums Dcal / 4)
         const real Lx = fmar(la * (real)(P.L * (1.0 / 4294967296.0)), cv, (real)2 * al);
         static_cast<real*>(g.lam_out)[S.id[i]] = fmar((real)sd, Lx, la);
     }
     // dt lambda_a (L_k C)_a = dt vphi lambda_a 2 gk (gk sums Dcal_k / 4)
-    const double m = active ? 2.0 * sd * (double)la : 0.0;
+    const double m = (active && lj == 0) ? 2.0 * sd * (double)la : 0.0;
 #pragma unroll
     for (int th = 0; th < 3; ++th) {
         const double c = block_sum(m * (double)gk[th], lds);
@@ -493,12 +506,16 @@ __global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
     }
 }
 
+// four lanes per target, block / 4 targets per workgroup; the gradient
+// partials are indexed by workgroup (kTile / (block / 4) per tile)
 template <int DIM, typename real, int KERN>
 static hipError_t launch_adj_gen_t(const AdjGenLaunch& a, uint32_t block, hipStream_t s) {
-    const size_t shm = (size_t)block * (size_t)a.list_cap * 8u;
-    if (shm > kPairLdsMax || block < 64 || block > 256 || kTile % block) return hipErrorInvalidValue;
+    constexpr int L = 4;
+    const uint32_t tpb = block / L;  // targets per workgroup
+    const size_t shm = (size_t)tpb * (size_t)a.list_cap * 8u;
+    if (shm > kPairLdsMax || block < 64 || block > 256 || kTile % tpb) return hipErrorInvalidValue;
     if (DIM == 2 && sizeof(real) == 4 && !a.S.grec) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_adjoint_gen<DIM, real, KERN>), dim3(a.ntiles * (kTile / block)), dim3(block), shm, s, a);
+    hipLaunchKernelGGL((k_adjoint_gen<DIM, real, KERN, L>), dim3(a.ntiles * (kTile / tpb)), dim3(block), shm, s, a);
     return hipGetLastError();
 }
 
