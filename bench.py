@@ -301,7 +301,7 @@ def velocity_field(device, steps=50, warmup=3):
     f["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
                      "flops_per_interaction": FLOPS_PER_INTERACTION_FIELD[2],
-                     "kernel": "k_pair_gen<2, float, 4, 0> (update mode)"}
+                     "kernel": "k_pair_gen<2, float, 4, 0, 4> (update mode)"}
     out["workload"] = ("cfg2 plume h/dp 2, alpha_L/alpha_T 10, 512^2 FP32, explicit Euler; "
                        "interactions counted at the initial positions")
     return out
