@@ -130,3 +130,36 @@ def test_paper_scale_sampled():
         s = int(np.rint(spec.dt * spec.velocity()[c] / spec.L * TWO32))
         assert np.array_equal(xg[c], np.mod(u0[c] + s, 1 << 32).astype(np.float64) / TWO32 * spec.L)
     ctx.close()
+
+
+@pytest.mark.parametrize("n_side,rb", [(140, 8), (150, 4)])
+def test_dense_velocity_field_rhs_and_step(n_side, rb):
+    """A velocity field on a dense plume (sub-row cells, hundreds of
+    neighbours): the right-hand side against the oracle, and one step with
+    velocities of whole fixed-point units per step (positions bit-exact)."""
+    from paper_2108_09488_amd import _lib
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = _dense(n_side, rb)
+    spec.dt = 2.0 ** -12 * spec.L
+    x = spec.positions()
+    # |v| ~ L/64 per unit time (dt within the Eq. 10 bound), rounded so that
+    # dt v / L 2^32 is an integer
+    v = I.velocity_field(x, spec.L, U=spec.L / 64.0, quantum=spec.L * 2.0 ** -20)
+    if rb == 4:
+        v = v.astype(np.float32).astype(np.float64)
+    C = spec.concentration(x)
+    if rb == 4:
+        C = C.astype(np.float32).astype(np.float64)
+    print(f"[case] dense velocity field n_side={n_side} rb={rb}", flush=True)
+    ctx = Context([params_from_spec(spec, flags=_lib.ADE_VELOCITY_FIELD)], [spec.n])
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C)).set_velocities(torch.from_numpy(v)).build()
+    assert ctx.info()["cells"] <= spec.n
+    g = ctx.rhs().double().cpu().numpy()
+    m = O.model_from_spec(spec)
+    r = O.rhs(m, x, C, v=v, mass=spec.mass, rho=spec.rho0)
+    assert _rel(g, r) < (1e-12 if rb == 8 else 1e-5)
+    ctx.step(1)
+    xo, Co, _ = O.run(m, x, C, spec.dt, 1, v=v, mass=spec.mass, rho=spec.rho0)
+    assert np.array_equal(ctx.read_x().cpu().numpy(), xo)
+    assert _rel(ctx.read_C().double().cpu().numpy(), Co) < (1e-12 if rb == 8 else 1e-5)
+    ctx.close()
