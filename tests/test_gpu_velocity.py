@@ -303,6 +303,36 @@ def test_velocity_field_adjoint_matches_oracle(rb, K):
     ctx.close()
 
 
+@pytest.mark.parametrize("rb", [8, 4])
+def test_velocity_field_adjoint_3d(rb):
+    """The velocity-field adjoint of a small 3D plume against the oracle's
+    (dt = 2^-9: with velocities in multiples of 2^-20 still whole fixed-point
+    units per step; truth and guess far enough apart that J is not a
+    cancellation)."""
+    spec = I.config("cfg3", n_side=14, steps=12, dt=2.0 ** -9, real_bytes=rb, h_over_dp=2.0, alpha_L=1e-2,
+                    alpha_T=5e-3)
+    x = spec.positions()
+    v = _field(spec)
+    C0 = spec.concentration(x)
+    if rb == 4:
+        C0 = C0.astype(np.float32).astype(np.float64)
+    xs = I.sensors(40, [0.1, 0.3, 0.3], [0.5, 0.7, 0.7])
+    truth = O.model(3, 4, spec.H, alpha_L=4e-2, alpha_T=1e-3, D_m=1e-6)
+    _, _, CN = O.adjoint_field(truth, x, C0, v, spec.dt, spec.steps, xs, np.zeros(xs.shape[1]),
+                               mass=spec.mass, rho=spec.rho0)
+    obs, _ = O.sensor_interp(truth, (x + spec.steps * spec.dt * v) % spec.L, CN, xs)
+    if rb == 4:
+        obs = obs.astype(np.float32).astype(np.float64)
+    ctx, _, _ = _ctx(spec, v, C=C0)
+    J, g = ctx.adjoint(spec.steps, 3, torch.from_numpy(xs), torch.from_numpy(obs))
+    Jo, go, _ = O.adjoint_field(O.model_from_spec(spec), x, C0, v, spec.dt, spec.steps, xs, obs,
+                                mass=spec.mass, rho=spec.rho0)
+    tol = 1e-10 if rb == 8 else 1e-4
+    assert J == pytest.approx(Jo, rel=tol)
+    assert np.allclose(g, go, rtol=tol, atol=tol * np.abs(go).max())
+    ctx.close()
+
+
 def test_velocity_field_validation():
     from paper_2108_09488_amd.context import Context, params_from_spec
     spec = _spec(2, 4, 32, 4, 1.5)
