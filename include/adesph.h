@@ -159,7 +159,7 @@ int ade_init_particles(ade_ctx *ctx, const double *d_x, const void *d_C);
  * the predictor moves it to x + rint((k + 1/2) u_a) - rint(k u_a), the cells
  * are rebuilt there for the corrector, and the corrector completes the step.
  * The pair sum
- * runs one lane per target with a fixed launch shape; ade_set_tuning and
+ * runs four lanes per target with a fixed launch shape; ade_set_tuning and
  * ade_autotune return ADE_EINVAL for such a context.  ade_adjoint takes it
  * with explicit Euler (ADE_EINVAL with ADE_PC): its checkpoints then hold
  * the velocities and tensors too, and the gradient differentiates every

@@ -11,7 +11,7 @@
 // own velocities, each on the exact fixed-point schedule of the uniform case
 // (displacement rint((k+1) u_a) - rint(k u_a) at step k, u_a = dt v_a / L
 // 2^32), and are hashed and counted into the next build's cells as there.
-// One lane per target walks the target's candidate list (ade_walk.h).  Each
+// Four lanes per target walk the target's candidate list (ade_walk.h).  Each
 // particle carries the reciprocals of its tensor components, so a harmonic
 // mean costs one add and one reciprocal; in 2D FP32 a candidate is one
 // 32-byte record, elsewhere it is read from the structure-of-arrays state.
