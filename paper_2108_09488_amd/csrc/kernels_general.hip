@@ -21,10 +21,9 @@
 
 namespace ade {
 
-#ifndef ADE_GEN_BATCH
-#define ADE_GEN_BATCH 2
-#endif
-constexpr int kGenBatch = ADE_GEN_BATCH;  // candidates per lane per batch of the walk
+// candidate records per lane per batch of the walk (2: the kernel stays at
+// 64 VGPRs; 4 measured the same in update mode, slower in rhs mode)
+constexpr int kGenBatch = 2;
 
 template <int DIM>
 struct GenDims {
