@@ -163,3 +163,37 @@ def test_dense_velocity_field_rhs_and_step(n_side, rb):
     assert np.array_equal(ctx.read_x().cpu().numpy(), xo)
     assert _rel(ctx.read_C().double().cpu().numpy(), Co) < (1e-12 if rb == 8 else 1e-5)
     ctx.close()
+
+
+TABLE2_RMSE_1M = {"r10": 4.13e-6, "r100": 4.81e-6, "r1000": 6.56e-6}  # Table 2, N = 10^6
+
+
+@pytest.mark.parametrize("ratio", ["r10", "r100", "r1000"])
+def test_paper_scale_300_days_against_the_closed_form(ratio):
+    """Table 1's 10^6-particle problem run for 300 days in steps of one day
+    (the paper gives no step; its CPU time implies about 300 steps), FP32,
+    against the closed-form plume of Eqs. (12)-(13) (corrected denominator,
+    advected centre) at the particles' final positions.  RMSE over all
+    particles of C/C0 (the paper's definition is not given); the printed
+    Table 2 values are quoted beside it."""
+    spec = I.config(f"paper1m_{ratio}")
+    spec.dt = 86400.0
+    steps = 300
+    ctx, x, C0 = _ctx(spec)
+    ctx.step(steps)
+    C = ctx.read_C().double().cpu().numpy()
+    xg = ctx.read_x().cpu().numpy()
+    m0 = float(np.sum(C0))
+    ctx.close()
+    t = steps * spec.dt
+    Ca = O.analytic(O.model_from_spec(spec), spec.velocity(), [1000.0, 1000.0], spec.sigma0, 1.0, t, xg)
+    rmse = float(np.sqrt(np.mean((C - Ca) ** 2)))
+    root_sum_over_n = float(np.sqrt(np.sum((C - Ca) ** 2)) / C.size)
+    peak = float(Ca.max())
+    drift = abs(np.sum(C) - m0) / m0
+    print(f"[paper1m {ratio}] 300 days: RMSE {rmse:.3e}, sqrt(sum)/N {root_sum_over_n:.3e} "
+          f"(Table 2: {TABLE2_RMSE_1M[ratio]:.2e}), peak {peak:.4f}, max |C - Ca| "
+          f"{np.max(np.abs(C - Ca)):.3e}, mass drift {drift:.2e}", flush=True)
+    assert np.all(np.isfinite(C))
+    assert drift < 1e-5
+    assert rmse < 0.01 * peak
