@@ -193,7 +193,8 @@ def test_paper_scale_300_days_against_the_closed_form(ratio):
     drift = abs(np.sum(C) - m0) / m0
     print(f"[paper1m {ratio}] 300 days: RMSE {rmse:.3e}, sqrt(sum)/N {root_sum_over_n:.3e} "
           f"(Table 2: {TABLE2_RMSE_1M[ratio]:.2e}), peak {peak:.4f}, max |C - Ca| "
-          f"{np.max(np.abs(C - Ca)):.3e}, mass drift {drift:.2e}", flush=True)
+          f"{np.max(np.abs(C - Ca)):.3e}, numerical peak {C.max():.4f}, min C/C0 {C.min():.2e}, "
+          f"mass drift {drift:.2e}", flush=True)
     assert np.all(np.isfinite(C))
     assert drift < 1e-5
     assert rmse < 0.01 * peak
