@@ -194,6 +194,12 @@ int ade_read_x(const ade_ctx *ctx, double *d_x_out);
  * order, to d_out[nplumes] (device). */
 int ade_mass(const ade_ctx *ctx, double *d_out);
 
+/* Smallest and largest concentration of each plume (the paper's
+ * negative-concentration diagnostic, Section 4), in FP64, to
+ * d_out[2 * plume] (min) and d_out[2 * plume + 1] (max) (device); NaNs are
+ * skipped (see ADE_CHECK_FINITE). */
+int ade_conc_range(const ade_ctx *ctx, double *d_out);
+
 /* Neighbour sets as used by the pair sum: for particle a (id order), the
  * ids of all b != a with 0 < |x_ab| <= H, in d_ids[d_offsets[a] ..
  * d_offsets[a+1]) (unordered within a particle).  d_offsets has N+1

@@ -23,7 +23,7 @@ ERROR_NAMES = {0: "ADE_OK", -1: "ADE_EINVAL", -2: "ADE_EWORKSPACE", -3: "ADE_EHI
 
 # every entry point declared in include/adesph.h
 EXPORTS = ["ade_workspace_bytes", "ade_create", "ade_init_particles", "ade_set_velocities", "ade_build_cells",
-           "ade_step", "ade_step_graph", "ade_rhs", "ade_read_C", "ade_read_x", "ade_mass",
+           "ade_step", "ade_step_graph", "ade_rhs", "ade_read_C", "ade_read_x", "ade_mass", "ade_conc_range",
            "ade_neighbours", "ade_sensor_interp", "ade_adjoint_workspace_bytes", "ade_adjoint",
            "ade_kernel_timing", "ade_autotune", "ade_set_tuning", "ade_get_tuning", "ade_info",
            "ade_state_bytes", "ade_save_state", "ade_load_state", "ade_destroy", "ade_last_error",
@@ -78,6 +78,7 @@ def lib() -> ct.CDLL:
         "ade_read_C": [p, p],
         "ade_read_x": [p, p],
         "ade_mass": [p, p],
+        "ade_conc_range": [p, p],
         "ade_neighbours": [p, p, p, i64, pi64],
         "ade_sensor_interp": [p, p, i32, p],
         "ade_adjoint_workspace_bytes": [p, i64, i32, i32, psz],

@@ -175,6 +175,12 @@ class Context:
         check(lib().ade_load_state(self._h, buf.ctypes.data_as(ct.c_void_p), buf.nbytes))
         return self
 
+    def conc_range(self) -> torch.Tensor:
+        """(nplumes, 2) float64: the smallest and largest C of each plume."""
+        out = self._empty(2 * self.nplumes, dtype=torch.float64)
+        check(lib().ade_conc_range(self._h, _ptr(out)))
+        return self._out(out).view(self.nplumes, 2)
+
     def neighbour_counts(self) -> torch.Tensor:
         """offsets (N+1,) int64 of the neighbour lists (id order), without the ids."""
         offsets = self._empty(self.N + 1, dtype=torch.int64)

@@ -339,8 +339,59 @@ void layout(Bump& b, ade_ctx* c, const Plan& pl) {
     c->aux = b.take_bytes(N * rb);
     c->aux_rec = (pl.dim == 3 && pl.real_bytes == 8) ? nullptr : b.take<uint4>(N);
     c->mass_partial = b.take<double>(pl.ntiles);
+    c->range_partial = b.take<double>(2 * (size_t)pl.ntiles);
     c->step = b.take<int64_t>(1);
     c->nonfinite = b.take<uint32_t>(1);
+}
+
+// smallest and largest C of a tile, then of each plume (FP64; NaNs are
+// skipped by fmin / fmax)
+__device__ __forceinline__ void block_minmax(double& lo, double& hi, double* lds) {
+    for (int o = 32; o > 0; o >>= 1) {
+        lo = fmin(lo, __shfl_xor(lo, o, 64));
+        hi = fmax(hi, __shfl_xor(hi, o, 64));
+    }
+    const int lane = threadIdx.x & 63, w = threadIdx.x / 64, nw = blockDim.x / 64;
+    if (lane == 0) {
+        lds[2 * w] = lo;
+        lds[2 * w + 1] = hi;
+    }
+    __syncthreads();
+    for (int k = 0; k < nw; ++k) {
+        lo = fmin(lo, lds[2 * k]);
+        hi = fmax(hi, lds[2 * k + 1]);
+    }
+}
+
+template <typename real>
+__global__ __launch_bounds__(kTile) void k_range_tiles(const TileDev* __restrict__ tiles, const real* __restrict__ C,
+                                                      double* __restrict__ partial) {
+    __shared__ double lds[2 * kTile / 64];
+    const TileDev t = tiles[blockIdx.x];
+    const uint32_t i = t.start + threadIdx.x;
+    double lo = INFINITY, hi = -INFINITY;
+    if (i < t.end) lo = hi = (double)C[i];
+    block_minmax(lo, hi, lds);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = lo;
+        partial[2 * blockIdx.x + 1] = hi;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_range_plumes(const PlumeDev* __restrict__ plumes,
+                                                     const double* __restrict__ partial, double* __restrict__ out) {
+    __shared__ double lds[2 * 256 / 64];
+    const PlumeDev& P = plumes[blockIdx.x];
+    double lo = INFINITY, hi = -INFINITY;
+    for (uint32_t k = threadIdx.x; k < P.tcount; k += blockDim.x) {
+        lo = fmin(lo, partial[2 * (P.tfirst + k)]);
+        hi = fmax(hi, partial[2 * (P.tfirst + k) + 1]);
+    }
+    block_minmax(lo, hi, lds);
+    if (threadIdx.x == 0) {
+        out[2 * blockIdx.x] = lo;
+        out[2 * blockIdx.x + 1] = hi;
+    }
 }
 
 // finite check of the sorted concentrations: any NaN or infinity sets *flag
@@ -729,6 +780,22 @@ int ade_mass(const ade_ctx* c, double* d_out) {
     if (!c->built) return fail(ADE_ESTATE, "ade_mass before ade_build_cells");
     HIPCHK(launch_mass(c->plan.real_bytes, c->plumes, c->plan.P, c->tiles, c->plan.ntiles, c->S,
                        c->mass_partial, d_out, c->stream));
+    return ADE_OK;
+}
+
+int ade_conc_range(const ade_ctx* c, double* d_out) {
+    if (!c || !d_out) return fail(ADE_EINVAL, "null argument");
+    if (!c->built) return fail(ADE_ESTATE, "ade_conc_range before ade_build_cells");
+    const Plan& pl = c->plan;
+    if (pl.real_bytes == 4)
+        hipLaunchKernelGGL((k_range_tiles<float>), dim3(pl.ntiles), dim3(kTile), 0, c->stream, c->tiles,
+                           (const float*)c->S.C, c->range_partial);
+    else
+        hipLaunchKernelGGL((k_range_tiles<double>), dim3(pl.ntiles), dim3(kTile), 0, c->stream, c->tiles,
+                           (const double*)c->S.C, c->range_partial);
+    HIPCHK(hipGetLastError());
+    hipLaunchKernelGGL(k_range_plumes, dim3(pl.P), dim3(256), 0, c->stream, c->plumes, c->range_partial, d_out);
+    HIPCHK(hipGetLastError());
     return ADE_OK;
 }
 

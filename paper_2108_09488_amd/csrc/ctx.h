@@ -61,6 +61,7 @@ struct ade_ctx {
     void* aux = nullptr;
     uint4* aux_rec = nullptr;
     double* mass_partial = nullptr;
+    double* range_partial = nullptr;  // per tile: min and max of C
     int64_t* step = nullptr;
     uint32_t* nonfinite = nullptr;  // finite check: set when a concentration is not finite
     uint32_t h_total = 0;  // host copy of N for the cell-start sentinel
