@@ -76,9 +76,9 @@ def lib():
         L.or_misfit.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, i32, p]
         L.or_rhs_deriv.argtypes = [mp, i64, p, p, p, p, p, i32, p]
         L.or_apply_LT_field.argtypes = [mp, i64, p, p, p, p, p, p]
-        L.or_adjoint_field.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, p, p, p]
+        L.or_adjoint_field.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, i32, p, p, p]
         L.or_misfit_field.restype = d
-        L.or_misfit_field.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p]
+        L.or_misfit_field.argtypes = [mp, i64, p, p, p, p, p, d, i64, i64, p, p, i32]
         L.or_num_threads.restype = ct.c_int
         _lib = L
     return _lib
@@ -314,9 +314,9 @@ def apply_LT_field(m: Model, x, lam, v, mass=1.0, rho=1.0):
     return y
 
 
-def adjoint_field(m: Model, x0, C0, v, dt, nsteps, xs, obs, mass=1.0, rho=1.0):
-    """Discrete adjoint of the explicit Euler run with per-particle velocities v
-    (dim, n): returns (J, grad[alpha_L, alpha_T, D_m], C^N)."""
+def adjoint_field(m: Model, x0, C0, v, dt, nsteps, xs, obs, mass=1.0, rho=1.0, integrator=1):
+    """Discrete adjoint of the Euler (1) or predictor-corrector (2) run with
+    per-particle velocities v (dim, n): returns (J, grad[alpha_L, alpha_T, D_m], C^N)."""
     x0, C0, v, xs, obs = _f64(x0), _f64(C0), _f64(v), _f64(xs), _f64(obs)
     n = x0.shape[1]
     m_arr, r_arr = _particle_arrays(n, mass, rho)
@@ -324,17 +324,18 @@ def adjoint_field(m: Model, x0, C0, v, dt, nsteps, xs, obs, mass=1.0, rho=1.0):
     g = np.zeros(3)
     CN = np.zeros(n)
     lib().or_adjoint_field(ct.byref(m), n, _ptr(x0), _ptr(C0), _ptr(v), _ptr(m_arr), _ptr(r_arr), dt, nsteps,
-                           xs.shape[1], _ptr(xs), _ptr(obs), _ptr(J), _ptr(g), _ptr(CN))
+                           xs.shape[1], _ptr(xs), _ptr(obs), int(integrator), _ptr(J), _ptr(g), _ptr(CN))
     return float(J[0]), g, CN
 
 
-def misfit_field(m: Model, x0, C0, v, dt, nsteps, xs, obs, mass=1.0, rho=1.0):
-    """Euler run with per-particle velocities and J = sum_s (C_s - d_s)^2."""
+def misfit_field(m: Model, x0, C0, v, dt, nsteps, xs, obs, mass=1.0, rho=1.0, integrator=1):
+    """Euler (1) or predictor-corrector (2) run with per-particle velocities and
+    J = sum_s (C_s - d_s)^2."""
     x0, C0, v, xs, obs = _f64(x0), _f64(C0), _f64(v), _f64(xs), _f64(obs)
     n = x0.shape[1]
     m_arr, r_arr = _particle_arrays(n, mass, rho)
     return lib().or_misfit_field(ct.byref(m), n, _ptr(x0), _ptr(C0), _ptr(v), _ptr(m_arr), _ptr(r_arr), dt,
-                                 nsteps, xs.shape[1], _ptr(xs), _ptr(obs))
+                                 nsteps, xs.shape[1], _ptr(xs), _ptr(obs), int(integrator))
 
 
 def num_threads():

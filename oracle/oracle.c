@@ -1020,26 +1020,45 @@ void or_apply_LT_field(const or_model *m, int64_t n, const double *x, const doub
     cells_free(&cl);
 }
 
-/* Discrete adjoint of the explicit Euler run with per-particle velocities:
- * C^{n+1} = C^n + dt L^n C^n, x^{n+1} = x^n + dt v, J = sum_s (P C^N - d)_s^2;
- *   lam^N = P^T 2 (P C^N - d),  lam^n = lam^{n+1} + dt (L^n)^T lam^{n+1},
- *   dJ/dtheta_k += dt lam^{n+1} . L^n_k C^n.
+/* Discrete adjoint of the run with per-particle velocities, J = sum_s
+ * (P C^N - d)_s^2, lam^N = P^T 2 (P C^N - d).
+ * Euler (integrator 1): C^{n+1} = C^n + dt L^n C^n, x^{n+1} = x^n + dt v;
+ *   lam^n = lam^{n+1} + dt (L^n)^T lam^{n+1},  dJ/dtheta_k += dt lam^{n+1} . L^n_k C^n.
+ * Predictor-corrector (integrator 2, R6 with each particle's velocity):
+ * C^h = C^n + dt/2 L1 C^n with L1 = L(x^n), C^{n+1} = C^n + dt L2 C^h with
+ * L2 = L(x^n + dt/2 v); with y = L2^T lam^{n+1}:
+ *   lam^n = lam^{n+1} + dt y + dt^2/2 L1^T y,
+ *   dJ/dtheta_k += dt lam^{n+1} . L2_k C^h + dt^2/2 y . L1_k C^n.
  * All states are kept in memory (plain reverse sweep). */
 void or_adjoint_field(const or_model *m, int64_t n, const double *x0, const double *C0,
                       const double *v, const double *mass, const double *rho, double dt,
-                      int64_t nsteps, int64_t ns, const double *xs, const double *obs,
+                      int64_t nsteps, int64_t ns, const double *xs, const double *obs, int integrator,
                       double *J_out, double *grad_out, double *Cfinal_out)
 {
     int dim = m->dim;
     double *X = (double *)malloc(sizeof(double) * dim * n * (nsteps + 1));
     double *Cs = (double *)malloc(sizeof(double) * n * (nsteps + 1));
     double *rhs = (double *)malloc(sizeof(double) * n);
+    double *Ch = (double *)malloc(sizeof(double) * n);
+    double *xh = (double *)malloc(sizeof(double) * n * dim);
     memcpy(X, x0, sizeof(double) * dim * n);
     memcpy(Cs, C0, sizeof(double) * n);
+    /* C^h and x^h of step s: the predictor stage */
+    #define FIELD_HALF(xs_n, C_n)                                                   \
+        do {                                                                        \
+            or_rhs(m, n, xs_n, C_n, v, NULL, mass, rho, NULL, n, NULL, rhs);        \
+            for (int64_t a = 0; a < n; ++a) Ch[a] = (C_n)[a] + 0.5 * dt * rhs[a];   \
+            advect(m, n, xs_n, v, NULL, 0.5 * dt, xh);                              \
+        } while (0)
     for (int64_t s = 0; s < nsteps; ++s) {
         const double *xs_n = X + (size_t)s * dim * n;
         const double *C_n = Cs + (size_t)s * n;
-        or_rhs(m, n, xs_n, C_n, v, NULL, mass, rho, NULL, n, NULL, rhs);
+        if (integrator == 2) {
+            FIELD_HALF(xs_n, C_n);
+            or_rhs(m, n, xh, Ch, v, NULL, mass, rho, NULL, n, NULL, rhs);
+        } else {
+            or_rhs(m, n, xs_n, C_n, v, NULL, mass, rho, NULL, n, NULL, rhs);
+        }
         for (int64_t a = 0; a < n; ++a) Cs[(size_t)(s + 1) * n + a] = C_n[a] + dt * rhs[a];
         advect(m, n, xs_n, v, NULL, dt, X + (size_t)(s + 1) * dim * n);
     }
@@ -1057,35 +1076,53 @@ void or_adjoint_field(const or_model *m, int64_t n, const double *x0, const doub
     double *y = (double *)malloc(sizeof(double) * n);
     sensor_interp_T(m, n, xN, ns, xs, g, lam);
     double grad[3] = {0.0, 0.0, 0.0};
+    double *z = (double *)malloc(sizeof(double) * n);
     for (int64_t s = nsteps - 1; s >= 0; --s) {
         const double *xs_n = X + (size_t)s * dim * n;
         const double *C_n = Cs + (size_t)s * n;
-        for (int k = 0; k < 3; ++k) {
-            or_rhs_deriv(m, n, xs_n, C_n, v, mass, rho, k, rhs);
-            double acc = 0.0;
-            for (int64_t a = 0; a < n; ++a) acc += lam[a] * rhs[a];
-            grad[k] += dt * acc;
+        if (integrator == 2) {
+            FIELD_HALF(xs_n, C_n);
+            or_apply_LT_field(m, n, xh, v, mass, rho, lam, y); /* y = L2^T lam */
+            for (int k = 0; k < 3; ++k) {
+                double acc = 0.0;
+                or_rhs_deriv(m, n, xh, Ch, v, mass, rho, k, rhs);
+                for (int64_t a = 0; a < n; ++a) acc += dt * lam[a] * rhs[a];
+                or_rhs_deriv(m, n, xs_n, C_n, v, mass, rho, k, rhs);
+                for (int64_t a = 0; a < n; ++a) acc += 0.5 * dt * dt * y[a] * rhs[a];
+                grad[k] += acc;
+            }
+            or_apply_LT_field(m, n, xs_n, v, mass, rho, y, z); /* z = L1^T y */
+            for (int64_t a = 0; a < n; ++a) lam[a] += dt * y[a] + 0.5 * dt * dt * z[a];
+        } else {
+            for (int k = 0; k < 3; ++k) {
+                or_rhs_deriv(m, n, xs_n, C_n, v, mass, rho, k, rhs);
+                double acc = 0.0;
+                for (int64_t a = 0; a < n; ++a) acc += lam[a] * rhs[a];
+                grad[k] += dt * acc;
+            }
+            or_apply_LT_field(m, n, xs_n, v, mass, rho, lam, y);
+            for (int64_t a = 0; a < n; ++a) lam[a] += dt * y[a];
         }
-        or_apply_LT_field(m, n, xs_n, v, mass, rho, lam, y);
-        for (int64_t a = 0; a < n; ++a) lam[a] += dt * y[a];
     }
+    #undef FIELD_HALF
     *J_out = J;
     for (int k = 0; k < 3; ++k) grad_out[k] = grad[k];
     if (Cfinal_out) memcpy(Cfinal_out, CN, sizeof(double) * n);
-    free(X); free(Cs); free(rhs); free(pred); free(g); free(lam); free(y);
+    free(X); free(Cs); free(rhs); free(pred); free(g); free(lam); free(y); free(z); free(Ch); free(xh);
 }
 
-/* Forward run with per-particle velocities (Euler) and J only. */
+/* Forward run with per-particle velocities (Euler 1, predictor-corrector 2)
+ * and J only. */
 double or_misfit_field(const or_model *m, int64_t n, const double *x0, const double *C0,
                        const double *v, const double *mass, const double *rho, double dt,
-                       int64_t nsteps, int64_t ns, const double *xs, const double *obs)
+                       int64_t nsteps, int64_t ns, const double *xs, const double *obs, int integrator)
 {
     int dim = m->dim;
     double *x = (double *)malloc(sizeof(double) * dim * n);
     double *C = (double *)malloc(sizeof(double) * n);
     memcpy(x, x0, sizeof(double) * dim * n);
     memcpy(C, C0, sizeof(double) * n);
-    or_run(m, n, x, C, v, NULL, mass, rho, dt, nsteps, 1, NULL);
+    or_run(m, n, x, C, v, NULL, mass, rho, dt, nsteps, integrator, NULL);
     double *pred = (double *)malloc(sizeof(double) * (ns > 0 ? ns : 1));
     or_sensor_interp(m, n, x, C, ns, xs, pred, NULL);
     double J = 0.0;

@@ -604,10 +604,12 @@ def test_field_transpose_dot_product(uniform):
         assert np.max(np.abs(O.rhs(m, x, nu, v=v, mass=mass, rho=rho) - LTnu)) <= 1e-12 * np.max(np.abs(LTnu))
 
 
-def test_field_adjoint_against_finite_differences():
-    """FP64 discrete adjoint of the Euler run with per-particle velocities:
-    gradient w.r.t. (alpha_L, alpha_T, D_m) against central finite differences
-    of the same forward run, and J against the run's own misfit."""
+@pytest.mark.parametrize("integrator", [1, 2])
+def test_field_adjoint_against_finite_differences(integrator):
+    """FP64 discrete adjoint of the Euler or predictor-corrector run with
+    per-particle velocities: gradient w.r.t. (alpha_L, alpha_T, D_m) against
+    central finite differences of the same forward run, and J against the
+    run's own misfit."""
     spec, x, C0, v, xs = _field_problem()
     truth = O.model(2, 4, spec.H, alpha_L=2e-2, alpha_T=2e-3, D_m=1e-6)
     _, _, CN = O.adjoint_field(truth, x, C0, v, spec.dt, spec.steps, xs, np.zeros(xs.shape[1]),
@@ -618,10 +620,12 @@ def test_field_adjoint_against_finite_differences():
 
     def J(th):
         m = O.model(2, 4, spec.H, alpha_L=th[0], alpha_T=th[1], D_m=th[2])
-        return O.misfit_field(m, x, C0, v, spec.dt, spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0)
+        return O.misfit_field(m, x, C0, v, spec.dt, spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0,
+                              integrator=integrator)
 
     m = O.model(2, 4, spec.H, alpha_L=theta[0], alpha_T=theta[1], D_m=theta[2])
-    Jv, g, _ = O.adjoint_field(m, x, C0, v, spec.dt, spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0)
+    Jv, g, _ = O.adjoint_field(m, x, C0, v, spec.dt, spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0,
+                               integrator=integrator)
     assert Jv == pytest.approx(J(theta), rel=1e-13)
     assert Jv > 0
     for k in range(3):
@@ -630,3 +634,19 @@ def test_field_adjoint_against_finite_differences():
         e[k] = h
         fd = (J(theta + e) - J(theta - e)) / (2 * h)
         assert g[k] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(g).max())
+
+
+def test_field_pc_adjoint_differs_from_euler():
+    """The velocity-field predictor-corrector adjoint is not the Euler one
+    (its corrector operator lives at x + dt/2 v), and its J is that of the
+    oracle's own PC run."""
+    spec, x, C0, v, xs = _field_problem()
+    obs = np.zeros(xs.shape[1])
+    m = O.model_from_spec(spec)
+    J1, g1, C1 = O.adjoint_field(m, x, C0, v, spec.dt, spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0)
+    J2, g2, C2 = O.adjoint_field(m, x, C0, v, spec.dt, spec.steps, xs, obs, mass=spec.mass, rho=spec.rho0,
+                                 integrator=2)
+    _, Co, _ = O.run(m, x, C0, spec.dt, spec.steps, v=v, mass=spec.mass, rho=spec.rho0, integrator=2)
+    assert np.max(np.abs(C2 - Co)) <= 1e-14 * np.max(np.abs(Co))
+    assert np.max(np.abs(C2 - C1)) > 1e-9 * np.max(np.abs(C1))
+    assert np.max(np.abs(g2 - g1)) > 1e-9 * np.max(np.abs(g1))
