@@ -161,9 +161,10 @@ int ade_init_particles(ade_ctx *ctx, const double *d_x, const void *d_C);
  * The pair sum
  * runs four lanes per target with a fixed launch shape; ade_set_tuning and
  * ade_autotune return ADE_EINVAL for such a context.  ade_adjoint takes it
- * with explicit Euler (ADE_EINVAL with ADE_PC): its checkpoints then hold
- * the velocities and tensors too, and the gradient differentiates every
- * pair's harmonic mean. */
+ * (Euler or ADE_PC): its checkpoints then hold the velocities and tensors
+ * too, the recompute keeps every step's half-step state for the
+ * predictor-corrector, and the gradient differentiates every pair's
+ * harmonic mean. */
 int ade_set_velocities(ade_ctx *ctx, const double *d_v);
 
 /* Cell-linked list: cell hash, counting sort by cell (stable, ordered by
@@ -225,7 +226,9 @@ int ade_adjoint_workspace_bytes(const ade_ctx *ctx, int64_t nsteps, int32_t ckpt
  * (ADE_VELOCITY_FIELD, explicit Euler) the operator is again its own
  * transpose (symmetric pair weights, a convective term diagonal in C) and
  * the gradient takes d(h/4)_ij = (q^2 dp + p^2 dq) / (p + q)^2 per pair and
- * component (p, q the two particles' tensor components).
+ * component (p, q the two particles' tensor components); with ADE_PC the
+ * corrector's operator L2 lives at the half-step positions, so a reverse
+ * step is y = L2 lambda there and lambda + dt y + dt^2/2 L1 y at x^n.
  * d_obs holds S reals.  On return the context holds the state at step
  * nsteps.  h_grad receives 3 doubles; synchronises the stream. */
 int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *d_xs,

@@ -170,12 +170,17 @@ struct AdjGenLaunch {
     int list_cap;
     StateArrays S;
     const uint32_t* cell_start;
-    const void* lam_s;  // lambda in the snapshot's cell order
-    void* lam_out;      // lambda^n in id order
+    const void* lam_s;  // the vector the pass applies the operator to, in the snapshot's cell order
+    const void* lam_id; // corrector pass: lambda^(n+1) in id order
+    void* lam_out;      // the pass's output in id order
     double* gpart;
 };
-hipError_t launch_adjoint_gen(int dim, int real_bytes, int kernel, const AdjGenLaunch& a, uint32_t block,
-                              hipStream_t s);
+// passes: Euler (lambda + dt L lambda), and the predictor-corrector's two:
+// at the half-step snapshot y = L lambda, at the step's snapshot
+// lambda + dt y + dt^2/2 L y
+enum AdjGenMode { kAdjGenEuler = 0, kAdjGenHalf = 1, kAdjGenFull = 2 };
+hipError_t launch_adjoint_gen(int dim, int real_bytes, int kernel, int mode, const AdjGenLaunch& a,
+                              uint32_t block, hipStream_t s);
 hipError_t launch_pair_gen(int dim, int real_bytes, int kernel, int mode, const GenLaunch& g, hipStream_t s);
 hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const PairLaunch& a,
                        int block, hipStream_t s);

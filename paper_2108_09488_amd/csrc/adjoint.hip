@@ -415,6 +415,8 @@ struct AdjLayout {
     size_t bytes = 0;
     std::vector<Snap> ck;   // checkpoints (every K steps, plus the final state)
     std::vector<Snap> seg;  // states of one segment
+    std::vector<Snap> segh; // velocity field with the predictor-corrector: their half-step states
+    void* y;                // ... and y = L lambda of the corrector stage (id order)
     void* lam[2];
     void* lam_s;
     void* mu_s;  // predictor-corrector: mu and C^h of the step (cell order)
@@ -463,10 +465,14 @@ void adj_layout(const ade_ctx* c, int64_t nsteps, int32_t K, int32_t ns, char* b
     L.seg.resize((size_t)K);
     for (auto& s : L.ck) take_snap(base, off, c, s);
     for (auto& s : L.seg) take_snap(base, off, c, s);
+    const bool gpc = pl.general && pl.integrator == ADE_PC;
+    L.segh.resize(gpc ? (size_t)K : 0);
+    for (auto& s : L.segh) take_snap(base, off, c, s);
     const size_t N = (size_t)pl.N, rb = (size_t)pl.real_bytes;
     L.lam[0] = take(N * rb);
     L.lam[1] = take(N * rb);
     L.lam_s = take(N * rb);
+    L.y = gpc ? take(N * rb) : nullptr;
     const bool pc = pl.integrator == ADE_PC;
     const bool packed = pl.dim == 2 && pl.real_bytes == 4;
     L.mu_s = pc ? take(N * rb) : nullptr;
@@ -607,8 +613,6 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     if (rc) return rc;
     if (!d_obs || !d_ws || !h_J || !h_grad) return fail(ADE_EINVAL, "null argument");
     if (nsteps < 1 || K < 1) return fail(ADE_EINVAL, "nsteps and ckpt_every must be positive");
-    if (c->plan.general && c->plan.integrator != ADE_EULER)
-        return fail(ADE_EINVAL, "the velocity-field adjoint takes explicit Euler");
     if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
     AdjLayout L;
     adj_layout(c, nsteps, K, ns, nullptr, L);
@@ -665,9 +669,16 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     for (int64_t sgi = nck - 1; sgi >= 0; --sgi) {
         const int64_t n0 = sgi * K, n1 = std::min<int64_t>(n0 + K, nsteps);
         if ((rc = copy_state(c, cur, L.ck[(size_t)sgi]))) return rc;
+        const bool gpc = pl.general && pl.integrator == ADE_PC;
         for (int64_t n = n0; n < n1; ++n) {
             if ((rc = copy_state(c, L.seg[(size_t)(n - n0)], cur))) return rc;
-            if ((rc = enqueue_step(c))) return rc;
+            if (gpc) {  // the step in its stages, keeping the half-step state
+                if ((rc = run_gen(c, kModeHalf, nullptr)) || (rc = enqueue_build(c, 0))) return rc;
+                if ((rc = copy_state(c, L.segh[(size_t)(n - n0)], cur))) return rc;
+                if ((rc = run_gen(c, kModeFull, nullptr)) || (rc = enqueue_build(c, 1))) return rc;
+            } else if ((rc = enqueue_step(c))) {
+                return rc;
+            }
         }
         for (int64_t n = n1 - 1; n >= n0; --n) {
             const Snap& sn = L.seg[(size_t)(n - n0)];
@@ -683,7 +694,7 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     hipLaunchKernelGGL((k_adjoint<D, R, KK, MODE>), ag, abk, (uint32_t)ashm, st, c->plumes, c->tiles, Sa,     \
                        sn.cs, (const R*)(U), (const R*)L.lam_s, (const R*)(X), (const uint4*)(REC), (R*)(OUT), \
                        (R*)(XH), (uint4*)(RECOUT), ac, L.gpart)
-            if (pl.general) {  // velocity field (explicit Euler)
+            if (pl.general) {  // velocity field
                 AdjGenLaunch ga;
                 ga.plumes = c->plumes;
                 ga.tiles = c->tiles;
@@ -692,9 +703,34 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
                 ga.S = Sa;
                 ga.cell_start = sn.cs;
                 ga.lam_s = L.lam_s;
+                ga.lam_id = nullptr;
                 ga.lam_out = L.lam[1 - li];
                 ga.gpart = L.gpart;
-                HIPCHK(launch_adjoint_gen(pl.dim, pl.real_bytes, pl.kernel, ga, kGenAdjBlock, st));
+                if (pl.integrator == ADE_PC) {
+                    // y = L2 lambda at the half-step state (its own cells and
+                    // order), then lambda^n = lambda + dt y + dt^2/2 L1 y here
+                    const Snap& sh = L.segh[(size_t)(n - n0)];
+                    const StateArrays Sh = snap_arrays(c, sh);
+#define GATHER_H(D, R, KK)                                                                                 \
+    hipLaunchKernelGGL((k_adj_gather<D, R>), g, b, 0, st, Sh, (const R*)L.lam[li], (const R*)sh.C, N,       \
+                       (R*)L.lam_s, L.arec)
+                    ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, GATHER_H);
+#undef GATHER_H
+                    AdjGenLaunch gh = ga;
+                    gh.S = Sh;
+                    gh.cell_start = sh.cs;
+                    gh.lam_out = L.y;
+                    HIPCHK(launch_adjoint_gen(pl.dim, pl.real_bytes, pl.kernel, kAdjGenHalf, gh, kGenAdjBlock, st));
+#define GATHER_Y(D, R, KK)                                                                                 \
+    hipLaunchKernelGGL((k_adj_gather<D, R>), g, b, 0, st, Sa, (const R*)L.y, (const R*)sn.C, N,             \
+                       (R*)L.lam_s, L.arec)
+                    ADE_DISPATCH3(pl.dim, pl.real_bytes, pl.kernel, GATHER_Y);
+#undef GATHER_Y
+                    ga.lam_id = L.lam[li];
+                    HIPCHK(launch_adjoint_gen(pl.dim, pl.real_bytes, pl.kernel, kAdjGenFull, ga, kGenAdjBlock, st));
+                } else {
+                    HIPCHK(launch_adjoint_gen(pl.dim, pl.real_bytes, pl.kernel, kAdjGenEuler, ga, kGenAdjBlock, st));
+                }
             } else if (pl.integrator == ADE_PC) {
 #define CALL(D, R, KK)                                                                                    \
     LAUNCH(D, R, KK, kAdjHalf, L.lam_s, sn.C, L.arec, L.mu_s, L.ch_s, L.arec2);                              \

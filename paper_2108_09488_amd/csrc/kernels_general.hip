@@ -371,7 +371,7 @@ __device__ __forceinline__ void tensor_derivs(const real* v, real (&dD)[3][GenDi
 //     d(h/4)_ij = (q^2 dp + p^2 dq) / (p + q)^2   (0 where p q <= 0),
 // and no convective part (it does not depend on theta).  The tensors come
 // from the stored reciprocals (1 / inf = 0 for a zero component).
-template <int DIM, typename real, int KERN, int LANES>
+template <int DIM, typename real, int KERN, int LANES, int AMODE>
 __global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
     extern __shared__ uint2 lds_list[];
     __shared__ double lds[kTile / kWave];
@@ -491,13 +491,28 @@ __global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
     gk[2] = red[4];
 
     const double sd = P.dt * P.vphi;
+    // the gradient's multiplier of (L_k X)_a / vphi = 2 gk (gk sums Dcal_k / 4):
+    // dt lambda_a (Euler and the corrector stage at x^(1/2)), dt^2/2 y_a (the
+    // predictor stage at x^n)
+    double m = 0.0;
     if (active && lj == 0) {
-        // 1/2 of the sum of Dcal terms = 2 al (al sums Dcal / 4)
+        // (L u)_a / vphi: 1/2 of the sum of Dcal terms = 2 al (al sums Dcal / 4)
         const real Lx = fmar(la * (real)(P.L * (1.0 / 4294967296.0)), cv, (real)2 * al);
-        static_cast<real*>(g.lam_out)[S.id[i]] = fmar((real)sd, Lx, la);
+        const uint32_t id = S.id[i];
+        if (AMODE == kAdjGenEuler) {
+            static_cast<real*>(g.lam_out)[id] = fmar((real)sd, Lx, la);
+            m = 2.0 * sd * (double)la;
+        } else if (AMODE == kAdjGenHalf) {
+            static_cast<real*>(g.lam_out)[id] = (real)P.vphi * Lx;  // y = L lambda
+            m = 2.0 * sd * (double)la;
+        } else {
+            // lambda + dt y + dt^2/2 L y, with la = y here
+            const real lam = static_cast<const real*>(g.lam_id)[id];
+            const real dt = (real)P.dt;
+            static_cast<real*>(g.lam_out)[id] = fmar(dt, la, fmar((real)(0.5 * P.dt * sd), Lx, lam));
+            m = P.dt * sd * (double)la;
+        }
     }
-    // dt lambda_a (L_k C)_a = dt vphi lambda_a 2 gk (gk sums Dcal_k / 4)
-    const double m = (active && lj == 0) ? 2.0 * sd * (double)la : 0.0;
 #pragma unroll
     for (int th = 0; th < 3; ++th) {
         const double c = block_sum(m * (double)gk[th], lds);
@@ -508,26 +523,35 @@ __global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
 // four lanes per target, block / 4 targets per workgroup; the gradient
 // partials are indexed by workgroup (kTile / (block / 4) per tile)
 template <int DIM, typename real, int KERN>
-static hipError_t launch_adj_gen_t(const AdjGenLaunch& a, uint32_t block, hipStream_t s) {
+static hipError_t launch_adj_gen_t(int mode, const AdjGenLaunch& a, uint32_t block, hipStream_t s) {
     constexpr int L = 4;
     const uint32_t tpb = block / L;  // targets per workgroup
     const size_t shm = (size_t)tpb * (size_t)a.list_cap * 8u;
     if (shm > kPairLdsMax || block < 64 || block > 256 || kTile % tpb) return hipErrorInvalidValue;
     if (DIM == 2 && sizeof(real) == 4 && !a.S.grec) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_adjoint_gen<DIM, real, KERN, L>), dim3(a.ntiles * (kTile / tpb)), dim3(block), shm, s, a);
+    if (mode == kAdjGenFull && !a.lam_id) return hipErrorInvalidValue;
+    auto kern = (mode == kAdjGenEuler)  ? k_adjoint_gen<DIM, real, KERN, L, kAdjGenEuler>
+                : (mode == kAdjGenHalf) ? k_adjoint_gen<DIM, real, KERN, L, kAdjGenHalf>
+                                        : k_adjoint_gen<DIM, real, KERN, L, kAdjGenFull>;
+    hipLaunchKernelGGL(kern, dim3(a.ntiles * (kTile / tpb)), dim3(block), shm, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_adjoint_gen(int dim, int real_bytes, int kernel, const AdjGenLaunch& a, uint32_t block,
-                              hipStream_t s) {
+hipError_t launch_adjoint_gen(int dim, int real_bytes, int kernel, int mode, const AdjGenLaunch& a,
+                              uint32_t block, hipStream_t s) {
+    if (mode != kAdjGenEuler && mode != kAdjGenHalf && mode != kAdjGenFull) return hipErrorInvalidValue;
     if (dim == 2) {
         if (real_bytes == 4)
-            return kernel == 4 ? launch_adj_gen_t<2, float, 4>(a, block, s) : launch_adj_gen_t<2, float, 2>(a, block, s);
-        return kernel == 4 ? launch_adj_gen_t<2, double, 4>(a, block, s) : launch_adj_gen_t<2, double, 2>(a, block, s);
+            return kernel == 4 ? launch_adj_gen_t<2, float, 4>(mode, a, block, s)
+                               : launch_adj_gen_t<2, float, 2>(mode, a, block, s);
+        return kernel == 4 ? launch_adj_gen_t<2, double, 4>(mode, a, block, s)
+                           : launch_adj_gen_t<2, double, 2>(mode, a, block, s);
     }
     if (real_bytes == 4)
-        return kernel == 4 ? launch_adj_gen_t<3, float, 4>(a, block, s) : launch_adj_gen_t<3, float, 2>(a, block, s);
-    return kernel == 4 ? launch_adj_gen_t<3, double, 4>(a, block, s) : launch_adj_gen_t<3, double, 2>(a, block, s);
+        return kernel == 4 ? launch_adj_gen_t<3, float, 4>(mode, a, block, s)
+                           : launch_adj_gen_t<3, float, 2>(mode, a, block, s);
+    return kernel == 4 ? launch_adj_gen_t<3, double, 4>(mode, a, block, s)
+                       : launch_adj_gen_t<3, double, 2>(mode, a, block, s);
 }
 
 hipError_t launch_setvel(int dim, int real_bytes, const PlumeDev* plumes, const TileDev* tiles, uint32_t ntiles,
