@@ -31,12 +31,13 @@
  *    owns every buffer; the library never allocates device memory.  Device
  *    buffers passed to ade_create must stay valid until ade_destroy.
  *  - All device work is enqueued on the HIP stream given to ade_create and is
- *    asynchronous, except where a host output (h_*) forces a synchronisation.
+ *    asynchronous, except where a host output (h_*, a saved state) or the
+ *    finite check of ADE_CHECK_FINITE forces a synchronisation.
  *  - Positions are SoA doubles, x[c * n + a] for component c of particle a.
  *    The library stores them as 32-bit fixed-point fractions of the box,
  *    u = round(x / L * 2^32) mod 2^32 (resolution L / 2^32): positions are
- *    periodic by construction and every particle of a plume moves by exactly
- *    the same displacement each step.
+ *    periodic by construction, and in a uniform flow every particle of a
+ *    plume moves by exactly the same displacement each step.
  *  - Several plumes ("an ensemble") can share one context; their particles
  *    are concatenated in plume order in every per-particle array.
  */
