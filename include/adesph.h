@@ -271,8 +271,12 @@ int ade_info(const ade_ctx *ctx, int32_t plume, int64_t *n_total, int64_t *n_cel
  * cell table and the step counter; after ade_build_cells) into the caller's
  * host buffer h_buf of at least that many bytes, synchronising the stream.
  * ade_load_state puts such a state into a context created with the same
- * parameters and counts (ADE_EINVAL otherwise, or for a short buffer): the
- * context then continues bit-identically to the one saved, as if built. */
+ * parameters and counts: the context then continues bit-identically to the
+ * one saved, as if built.  It checks the dimension, precision, integrator,
+ * flow kind, and each plume's particle range and cell grid (ADE_EINVAL when
+ * any differs, or for a short buffer).  The state holds no other plume
+ * parameter: a uniform-flow context steps with its own dispersivities and dt,
+ * a velocity-field context with the velocities and tensors saved. */
 int ade_state_bytes(const ade_ctx *ctx, size_t *bytes);
 int ade_save_state(const ade_ctx *ctx, void *h_buf, size_t bytes);
 int ade_load_state(ade_ctx *ctx, const void *h_buf, size_t bytes);

@@ -967,8 +967,33 @@ struct StateHeader {
     uint64_t magic;
     uint32_t dim, real_bytes, general, integrator;
     uint64_t N, ncell, bytes;
+    uint64_t layout;  // layout_hash of the saving context
 };
 constexpr uint64_t kStateMagic = 0x3154415453454441ull;  // "ADESTAT1"
+
+// FNV-1a over what places the saved arrays: each plume's particle range and
+// cell grid.  Two contexts of equal N and cell count but another split of
+// either into plumes do not share a state.
+uint64_t layout_hash(const Plan& pl) {
+    uint64_t h = 0xcbf29ce484222325ull;
+    auto mix = [&](uint32_t w) {
+        for (int b = 0; b < 4; ++b) {
+            h ^= (w >> (8 * b)) & 0xffu;
+            h *= 0x100000001b3ull;
+        }
+    };
+    mix((uint32_t)pl.plumes.size());
+    for (const PlumeDev& q : pl.plumes) {
+        mix(q.poff);
+        mix(q.n);
+        mix(q.cbase);
+        mix(q.ncell);
+        mix(q.nfx);
+        mix(q.nr);
+        mix(q.nsub);
+    }
+    return h;
+}
 
 struct Section {
     void* dev;
@@ -1017,7 +1042,8 @@ int ade_save_state(const ade_ctx* c, void* h_buf, size_t bytes) {
     if (bytes < need) return fail(ADE_EINVAL, "state buffer too small: need %zu bytes", need);
     const Plan& pl = c->plan;
     StateHeader h{kStateMagic, (uint32_t)pl.dim, (uint32_t)pl.real_bytes, pl.general ? 1u : 0u,
-                  (uint32_t)pl.integrator, (uint64_t)pl.N, (uint64_t)pl.ncell, (uint64_t)need};
+                  (uint32_t)pl.integrator, (uint64_t)pl.N, (uint64_t)pl.ncell, (uint64_t)need,
+                  layout_hash(pl)};
     char* p = static_cast<char*>(h_buf);
     std::memcpy(p, &h, sizeof h);
     p += sizeof h;
@@ -1038,7 +1064,8 @@ int ade_load_state(ade_ctx* c, const void* h_buf, size_t bytes) {
     const size_t need = state_size(c);
     if (h.magic != kStateMagic || h.dim != (uint32_t)pl.dim || h.real_bytes != (uint32_t)pl.real_bytes ||
         h.general != (pl.general ? 1u : 0u) || h.integrator != (uint32_t)pl.integrator ||
-        h.N != (uint64_t)pl.N || h.ncell != (uint64_t)pl.ncell || h.bytes != need)
+        h.N != (uint64_t)pl.N || h.ncell != (uint64_t)pl.ncell || h.bytes != need ||
+        h.layout != layout_hash(pl))
         return fail(ADE_EINVAL, "saved state does not belong to a context of these parameters");
     if (bytes < need) return fail(ADE_EINVAL, "state buffer too small: need %zu bytes", need);
     const char* p = static_cast<const char*>(h_buf) + sizeof h;

@@ -209,6 +209,39 @@ def test_save_and_resume_is_bit_identical(velocity_field, integrator):
         c.close()
 
 
+def test_state_of_another_plume_split_is_rejected():
+    """Two contexts of the same particle and cell totals whose plumes are
+    split differently (the same support radius on two lattices, in either
+    order) do not share a saved state; a context of the saving one's split
+    takes it."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    a = I.config("cfg2_h20_r10", n_side=64, h_over_dp=4.0)
+    b = I.config("cfg2_h20_r10", n_side=32, h_over_dp=2.0)
+    assert a.H == b.H
+    print("[case] state of another plume split", flush=True)
+
+    def ctx(specs):
+        return Context([params_from_spec(s) for s in specs], [s.n for s in specs])
+
+    xs = [s.positions() for s in (a, b)]
+    Cs = [s.concentration(x).astype(np.float32) for s, x in zip((a, b), xs)]
+    src = ctx((a, b))
+    src.init(torch.from_numpy(np.concatenate(xs, axis=1)), torch.from_numpy(np.concatenate(Cs))).build()
+    src.step(3)
+    state = src.save_state()
+    swapped, same = ctx((b, a)), ctx((a, b))
+    assert swapped.info()["cells"] == same.info()["cells"]
+    with pytest.raises(_lib.AdeError) as e:
+        swapped.load_state(state)
+    assert e.value.code == _lib.ADE_EINVAL
+    same.load_state(state)
+    src.step(2)
+    same.step(2)
+    assert np.array_equal(same.read_C().cpu().numpy(), src.read_C().cpu().numpy())
+    for c in (src, swapped, same):
+        c.close()
+
+
 def test_concentration_range_per_plume():
     """ade_conc_range gives each plume's smallest and largest C exactly
     (min and max do not depend on the order), also after steps that push
