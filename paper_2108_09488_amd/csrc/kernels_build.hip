@@ -40,10 +40,50 @@ __global__ __launch_bounds__(kTile) void k_init(const PlumeDev* __restrict__ plu
 // The tables are padded to whole 1024-cell chunks with zero counts, so the
 // entry after the last cell receives the particle total (the sentinel).
 // Two launches: the chunk totals, then every workgroup sums the totals of
-// the chunks before its own (up to a few thousand numbers, read by all its
-// threads at once) and scans its chunk.
+// the chunks before its own (read by all its threads at once) and scans its
+// chunk.  Past kDirectChunks chunks that sum would grow with the square of
+// the table, so one workgroup scans the totals in place between the two
+// launches and each chunk reads its own prefix.
 // ---------------------------------------------------------------------------
 constexpr int kCellVec = kCellChunk / (256 * 4);  // uint4 of counts per thread, contiguous
+constexpr uint32_t kDirectChunks = 2048;           // chunks whose prefixes the final launch sums itself
+constexpr int kPrefixBlock = 1024;                 // the workgroup of k_scan_prefix
+
+// Exclusive scan in place of n chunk totals by one workgroup, in passes of
+// 4 consecutive totals per thread carried from pass to pass.
+template <typename T>
+__global__ __launch_bounds__(kPrefixBlock) void k_scan_prefix(T* __restrict__ p, uint32_t n) {
+    __shared__ T lds[kPrefixBlock / kWave];
+    T carry = 0;
+    for (uint32_t base = 0; base < n; base += 4u * kPrefixBlock) {
+        const uint32_t j = base + 4u * threadIdx.x;
+        T v[4];
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[k] = (j + k < n) ? p[j + k] : T(0);
+            s += v[k];
+        }
+        T tot;
+        T ex = block_exclusive_scan(s, lds, tot) + carry;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (j + k < n) p[j + k] = ex;
+            ex += v[k];
+        }
+        carry += tot;
+    }
+}
+
+// The total of the chunks before this workgroup's: summed here, or (after
+// k_scan_prefix) read.
+template <typename T>
+__device__ __forceinline__ T chunk_prefix(const T* __restrict__ partial, uint32_t direct, T* lds) {
+    if (!direct) return partial[blockIdx.x];
+    T pre = 0;
+    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += blockDim.x) pre += partial[b];
+    return block_sum(pre, lds);
+}
 
 __global__ __launch_bounds__(256) void k_cscan_reduce(const uint4* __restrict__ count,
                                                      uint32_t* __restrict__ partial,
@@ -66,11 +106,9 @@ __global__ __launch_bounds__(256) void k_cscan_reduce(const uint4* __restrict__ 
 
 __global__ __launch_bounds__(256) void k_cscan_final(uint4* __restrict__ count,
                                                     const uint32_t* __restrict__ partial,
-                                                    uint4* __restrict__ cell_start) {
+                                                    uint4* __restrict__ cell_start, uint32_t direct) {
     __shared__ uint32_t lds[256 / kWave];
-    uint32_t pre = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += 256) pre += partial[b];
-    pre = block_sum(pre, lds);
+    const uint32_t pre = chunk_prefix(partial, direct, lds);
     const uint32_t j0 = (blockIdx.x * 256 + threadIdx.x) * kCellVec;
     uint4 c[kCellVec];
     uint32_t mine = 0;
@@ -98,9 +136,11 @@ hipError_t launch_scan(CellLists lists, uint32_t* cell_start, uint32_t* partial,
                        hipStream_t s) {
     const uint32_t nchunks = (uint32_t)(cell_pad(ncell) / kCellChunk);
     uint4* cnt = reinterpret_cast<uint4*>(lists.count);
+    const uint32_t direct = nchunks <= kDirectChunks ? 1u : 0u;
     hipLaunchKernelGGL(k_cscan_reduce, dim3(nchunks), dim3(256), 0, s, cnt, partial, lists.ovf_count);
+    if (!direct) hipLaunchKernelGGL((k_scan_prefix<uint32_t>), dim3(1), dim3(kPrefixBlock), 0, s, partial, nchunks);
     hipLaunchKernelGGL(k_cscan_final, dim3(nchunks), dim3(256), 0, s, cnt, partial,
-                       reinterpret_cast<uint4*>(cell_start));
+                       reinterpret_cast<uint4*>(cell_start), direct);
     return hipGetLastError();
 }
 
@@ -122,11 +162,9 @@ __global__ __launch_bounds__(kScanBlock) void k_scan64_partial(const int64_t* __
 
 __global__ __launch_bounds__(kScanBlock) void k_scan64_final(int64_t* __restrict__ d,
                                                             const int64_t* __restrict__ partial,
-                                                            uint32_t n, uint32_t nb) {
+                                                            uint32_t n, uint32_t nb, uint32_t direct) {
     __shared__ int64_t lds[kScanBlock / kWave];
-    int64_t pre = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += blockDim.x) pre += partial[b];
-    pre = block_sum(pre, lds);
+    const int64_t pre = chunk_prefix(partial, direct, lds);
     const uint32_t base = blockIdx.x * kScanChunk + threadIdx.x * kScanPerThread;
     int64_t v[kScanPerThread];
     int64_t s = 0;
@@ -147,8 +185,10 @@ __global__ __launch_bounds__(kScanBlock) void k_scan64_final(int64_t* __restrict
 
 hipError_t launch_scan64(int64_t* data, uint32_t n, int64_t* partial, hipStream_t s) {
     const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
+    const uint32_t direct = nb <= kDirectChunks ? 1u : 0u;
     hipLaunchKernelGGL(k_scan64_partial, dim3(nb), dim3(kScanBlock), 0, s, data, partial, n);
-    hipLaunchKernelGGL(k_scan64_final, dim3(nb), dim3(kScanBlock), 0, s, data, partial, n, nb);
+    if (!direct) hipLaunchKernelGGL((k_scan_prefix<int64_t>), dim3(1), dim3(kPrefixBlock), 0, s, partial, nb);
+    hipLaunchKernelGGL(k_scan64_final, dim3(nb), dim3(kScanBlock), 0, s, data, partial, n, nb, direct);
     return hipGetLastError();
 }
 
