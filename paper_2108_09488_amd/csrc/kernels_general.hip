@@ -22,7 +22,7 @@
 namespace ade {
 
 // candidate records per lane per batch of the walk (2: the kernel stays at
-// 64 VGPRs; 4 measured the same in update mode, slower in rhs mode)
+// 64 VGPRs; 4 measured about 13% slower in both update and rhs mode)
 constexpr int kGenBatch = 2;
 
 template <int DIM>
