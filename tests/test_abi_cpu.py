@@ -115,3 +115,19 @@ def test_particle_limit_per_context():
     rc, nb = _wsbytes([p, p], [lim // 2, lim - lim // 2])
     assert rc == 0 and nb > lim * 40
     assert _wsbytes([p, p], [lim // 2, lim - lim // 2 + 1])[0] == _lib.ADE_EINVAL
+
+
+def test_default_x_cells_coarsen_for_large_cell_tables():
+    """A context whose default cell tables (40 bytes per cell) would pass
+    160 MiB gets coarser x cells: the 256-plume ensemble (9.6M cells at H/8)
+    is sized as with H/3 cells, the six-plume sweep (2M cells) as with H/8,
+    and an explicit cell_xsub is kept."""
+    from paper_2108_09488_amd.context import workspace_bytes
+
+    def ws(specs, xsub=0):
+        return workspace_bytes([params_from_spec(s, cell_xsub=xsub) for s in specs], [s.n for s in specs])
+
+    ens = I.ensemble(256)
+    assert ws(ens) == ws(ens, 3) < ws(ens, 4) < ws(ens, 8)
+    sweep = [I.config(n) for n in I.CFG2_CELLS]
+    assert ws(sweep) == ws(sweep, 8)

@@ -29,8 +29,9 @@ def _rel(a, b):
 
 
 def test_scans_past_the_direct_size():
-    """2900^2 jittered plume (8.4M particles, 19.9M cells): both scans take
-    the scanned-totals path; the neighbour offsets match the oracle's
+    """2900^2 jittered plume (8.4M particles; 7.5M cells, its default x cells
+    coarsened to H/3 to bound the tables): both scans take the scanned-totals
+    path; the neighbour offsets match the oracle's
     exactly, before and after steps, and the right-hand side matches at a
     sample of plume particles."""
     from paper_2108_09488_amd.context import Context, params_from_spec
