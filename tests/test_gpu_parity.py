@@ -56,7 +56,7 @@ NBR_CASES = [
 
 
 @pytest.mark.parametrize("name,over", NBR_CASES)
-@pytest.mark.parametrize("grid", [(0, 0), (1, 1), (3, 16)])
+@pytest.mark.parametrize("grid", [(0, 0), (1, 1), (3, 16), (2, 3), (0, 4)])
 def test_neighbour_sets_bit_exact(name, over, grid):
     spec = I.config(name, **over)
     ctx, x, _ = _ctx(spec, cell_rows=grid[0], cell_xsub=grid[1])
