@@ -121,7 +121,8 @@ def test_default_x_cells_coarsen_for_large_cell_tables():
     """A context whose default cell tables (40 bytes per cell) would pass
     160 MiB gets coarser x cells: the 256-plume ensemble (9.6M cells at H/8)
     is sized as with H/3 cells, the six-plume sweep (2M cells) as with H/8,
-    and an explicit cell_xsub is kept."""
+    the 128^3 plume as with its 3D default of H/16, and an explicit cell_xsub
+    is kept."""
     from paper_2108_09488_amd.context import workspace_bytes
 
     def ws(specs, xsub=0):
@@ -131,3 +132,5 @@ def test_default_x_cells_coarsen_for_large_cell_tables():
     assert ws(ens) == ws(ens, 3) < ws(ens, 4) < ws(ens, 8)
     sweep = [I.config(n) for n in I.CFG2_CELLS]
     assert ws(sweep) == ws(sweep, 8)
+    cube = [I.config("cfg3")]  # 3D: H/16 by default
+    assert ws(cube) == ws(cube, 16) > ws(cube, 8)
