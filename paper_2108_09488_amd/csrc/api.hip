@@ -166,7 +166,13 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
         // the row work (measured: -6% and -8.5% on the 10^6 and 4x10^6
         // paper-scale problems)
         const int rsub = q.cell_rows ? q.cell_rows : (nbar > 2000.0 ? 4 : 2);
-        const int xsub = q.cell_xsub ? q.cell_xsub : auto_xsub;
+        // a 2D plume of many neighbours does enough pair work per cell that
+        // narrower x cells (fewer candidates per neighbour) outweigh the
+        // extra cells: H/12 from 80 expected neighbours when the tables fit
+        // (measured on the sweep: its h/dp = 3 plumes, 111 neighbours, take
+        // the pair kernel from 115 to 108.6 us; at 46 neighbours H/12 is slower)
+        const int xsub = q.cell_xsub ? q.cell_xsub
+                                     : (pl.dim == 2 && auto_xsub == 8 && nbar >= 80.0 ? 12 : auto_xsub);
         const double cap = std::max(8.0 * (double)counts[p], 4096.0);
         double nr = std::floor(kTwo32 * rsub / Hc);
         double nfx = std::floor(kTwo32 * xsub / Hc);

@@ -120,8 +120,8 @@ def test_particle_limit_per_context():
 def test_default_x_cells_coarsen_for_large_cell_tables():
     """A context whose default cell tables (40 bytes per cell) would pass
     160 MiB gets coarser x cells: the 256-plume ensemble (9.6M cells at H/8)
-    is sized as with H/3 cells, the six-plume sweep (2M cells) as with H/8,
-    the 128^3 plume as with its 3D default of H/16, and an explicit cell_xsub
+    is sized as with H/3 cells, the six-plume sweep (2M cells) as with H/8
+    (H/12 for its plumes of 111 neighbours), the 128^3 plume as with its 3D default of H/16, and an explicit cell_xsub
     is kept."""
     from paper_2108_09488_amd.context import workspace_bytes
 
@@ -131,6 +131,9 @@ def test_default_x_cells_coarsen_for_large_cell_tables():
     ens = I.ensemble(256)
     assert ws(ens) == ws(ens, 3) < ws(ens, 4) < ws(ens, 8)
     sweep = [I.config(n) for n in I.CFG2_CELLS]
-    assert ws(sweep) == ws(sweep, 8)
+    # H/12 for the plumes of 80 or more expected neighbours (h/dp = 3), H/8 for the rest
+    mixed = workspace_bytes([params_from_spec(s, cell_xsub=12 if s.h_over_dp == 3.0 else 8) for s in sweep],
+                            [s.n for s in sweep])
+    assert ws(sweep) == mixed > ws(sweep, 8)
     cube = [I.config("cfg3")]  # 3D: H/16 by default
     assert ws(cube) == ws(cube, 16) > ws(cube, 8)
