@@ -103,9 +103,10 @@ typedef struct {
  * candidates are interleaved over them and the partial sums are combined by
  * a wavefront reduction); with N particles the kernel runs N*lanes/64
  * wavefronts, so lanes is the waves-per-CU knob.  Each target keeps the list
- * of its candidate ranges in LDS: 8 * (2 * rows + 2) bytes per target, rows =
- * (2R+1)^(dim-1) neighbour rows of the plume with the most, and block / lanes
- * targets per workgroup must fit in 64 KiB (ADE_EINVAL otherwise).
+ * of its candidate ranges in LDS: 8 * (P * (S + 2) + 2) bytes per target,
+ * S = 2R+1 neighbour rows per axis of the plume with the most and P = 1 (2D)
+ * or S (3D) planes of rows, and block / lanes targets per workgroup must fit
+ * in 64 KiB (ADE_EINVAL otherwise).
  * targets = 2 (with lanes = 1 and block <= 128) gives each lane two
  * consecutive target particles of the cell order: the lane walks one list
  * holding the candidates of both, 8 * (P * (S + 3) + 2) bytes per lane with

@@ -32,6 +32,7 @@ struct Target {
     uint32_t ux, uy, uz;
     int ry, rz;
     float fy, fz;
+    float xc;  // x in x cells of the plume (float; PlumeDev::cslack covers its rounding)
 };
 
 template <int DIM>
@@ -40,6 +41,7 @@ __device__ __forceinline__ Target make_target(const PlumeDev& P, uint32_t ux, ui
     t.ux = ux;
     t.uy = uy;
     t.uz = uz;
+    t.xc = (float)ux * P.cellx;
     t.ry = (int)__umulhi(uy, P.nr);
     t.fy = (float)(uy * P.nr) * 2.3283064365386963e-10f;
     if (DIM == 3) {
@@ -52,16 +54,12 @@ __device__ __forceinline__ Target make_target(const PlumeDev& P, uint32_t ux, ui
     return t;
 }
 
-// Candidate cells of the neighbour row (oy, oz) of a target: the x window
-// [x - w, x + w], w being (an upper bound of) the chord of the search radius
-// at the row's nearest edge.  Returns false when the row lies beyond the
-// search radius.  k0 .. k1 (inclusive) is the first cell range and k2 .. k3
-// the second one, non-empty only when the window wraps around the periodic
-// seam (k2 > k3 marks it empty).  The bounds are conservative: the float
+// Half-width w of the x window of a target in its neighbour row (oy, oz):
+// an upper bound of the chord of the search radius at the row's nearest
+// edge, or the search radius itself in the target's own row; false when the
+// row lies beyond the search radius.  The bound is conservative: the float
 // rounding of the distances is covered by relative slack on w^2 and an
 // absolute slack of 64 grid units on w.
-// Half-width w of the x window of a target in its neighbour row (oy, oz);
-// false when the row lies beyond the search radius.
 template <int DIM>
 __device__ __forceinline__ bool row_halfwidth(const PlumeDev& P, const Target& T, int oy, int oz, uint32_t& w) {
     float dy = 0.f, dz = 0.f;
@@ -116,22 +114,19 @@ __device__ __forceinline__ void window_cells(const PlumeDev& P, uint32_t row, ui
     }
 }
 
-template <int DIM>
-__device__ __forceinline__ bool row_cells(const PlumeDev& P, const Target& T, int oy, int oz,
-                                          uint32_t& k0, uint32_t& k1, uint32_t& k2, uint32_t& k3) {
-    uint32_t w;
-    if (!row_halfwidth<DIM>(P, T, oy, oz, w)) return false;
-    const int yy = wrap_row(P, T.ry + oy);
-    const int zz = (DIM == 3) ? wrap_row(P, T.rz + oz) : 0;
-    window_cells(P, row_base(P, yy, zz), T.ux - w, T.ux + w, k0, k1, k2, k3);
-    return true;
-}
-
-// Sorted-index ranges [s0, e0) and [s1, e1) of row number j (0 .. noff-1,
-// oy fastest) of a target; all empty when the row is out of reach.
+// Sorted-index ranges of row number j (0 .. noff-1, oy fastest) of a target:
+// [s0, e0) the cells of its x window, and when the window wraps around the
+// periodic x seam [s1, e1) its low part at the start of the row ([s0, e0)
+// then ends at the end of the row); all empty when the row is out of reach.
 struct RowRanges {
     uint32_t s0, e0, s1, e1;
 };
+
+// Entry k of the cell-start table (tables are addressed with 32-bit byte
+// offsets from the table's base: a context holds fewer than 2^30 cells).
+__device__ __forceinline__ uint32_t cell_start_at(const uint32_t* __restrict__ cs, uint32_t k) {
+    return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(cs) + (k << 2));
+}
 
 template <int DIM>
 __device__ __forceinline__ RowRanges row_ranges(const PlumeDev& P, const uint32_t* __restrict__ cs,
@@ -139,14 +134,33 @@ __device__ __forceinline__ RowRanges row_ranges(const PlumeDev& P, const uint32_
     RowRanges r{0u, 0u, 0u, 0u};
     const int R = P.R;
     const int oy = j % span - R, oz = (DIM == 3) ? j / span - R : 0;
-    uint32_t k0, k1, k2, k3;
-    if (row_cells<DIM>(P, T, oy, oz, k0, k1, k2, k3)) {
-        r.s0 = cs[k0];
-        r.e0 = cs[k1 + 1];
-        if (k2 <= k3) {
-            r.s1 = cs[k2];
-            r.e1 = cs[k3 + 1];
-        }
+    uint32_t w;
+    if (!row_halfwidth<DIM>(P, T, oy, oz, w)) return r;
+    // the window [x - w, x + w] in x cells, widened by the slack: a superset
+    // of the cells the exact window touches
+    const float wc = (float)w * P.cellx + P.cslack;
+    const int nfx = (int)P.nfx, ns = (int)P.nsub;
+    int clo = __float2int_rd(T.xc - wc), chi = __float2int_rd(T.xc + wc);
+    int hi2 = -1;  // the low part [0, hi2] of a window that wraps around the seam
+    if (chi - clo + 1 >= nfx) {
+        clo = 0;
+        chi = nfx - 1;
+    } else if (clo < 0) {
+        hi2 = chi;
+        clo += nfx;
+        chi = nfx - 1;
+    } else if (chi >= nfx) {
+        hi2 = chi - nfx;
+        chi = nfx - 1;
+    }
+    const int yy = wrap_row(P, T.ry + oy);
+    const int zz = (DIM == 3) ? wrap_row(P, T.rz + oz) : 0;
+    const uint32_t row = row_base(P, yy, zz);
+    r.s0 = cell_start_at(cs, row + (uint32_t)(clo * ns));
+    r.e0 = cell_start_at(cs, row + (uint32_t)((chi + 1) * ns));
+    if (hi2 >= 0) {
+        r.s1 = cell_start_at(cs, row);
+        r.e1 = cell_start_at(cs, row + (uint32_t)((hi2 + 1) * ns));
     }
     return r;
 }

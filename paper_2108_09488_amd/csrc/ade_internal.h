@@ -31,10 +31,12 @@ struct PlumeDev {
     double Hu;              // support radius in grid units
     double H2d;             // Hu^2 (double)
     float H2f;              // Hu^2 rounded to float
-    float pad2;
+    float cellx;            // x cells per grid unit, nfx * 2^-32 (float)
     double invHu;
     float Hc2f;             // square of the search radius Hc = H_u (1 + 2^-16) + 2
     float rowh2f;           // square of the row height in grid units, (2^32 / nr)^2
+    float cslack;           // slack of a candidate window in x cells (covers float rounding)
+    float pad4;
     double a0, a1;          // Gamma x^T D x / r^2 - tr D = a0 + a1 (e . x / r)^2 (Eq. 3 tensor)
     double ehat[3];         // unit flow direction e (x axis when |v| = 0)
     double pad3;
@@ -99,7 +101,7 @@ struct PairLaunch {
     int block;              // threads per workgroup
     int lanes;              // lanes per target particle (1, 2 or 4)
     int targets;            // target particles per lane: 1, or 2 (one lane, block <= 128)
-    int list_cap;           // candidate-list entries per target in LDS (2 * rows + 2)
+    int list_cap;           // candidate-list entries per target in LDS (list_cap_for)
     int persistent;         // 0: one workgroup per work item; > 0: that many workgroups loop
     uint32_t xcd_group;     // consecutive work items an XCD takes in turn (>= 1)
     const uint4* rec;       // candidate records (position + C of Cpair), or null: SoA reads
@@ -121,10 +123,10 @@ struct PairLaunch {
     hipEvent_t ev0, ev1;    // if set: events stamped at the kernel's start and end
 };
 
-// candidate-list capacity per target for plumes with at most noff neighbour
-// rows (each row can be split in two at the periodic seam, plus a sentinel
-// and one entry read past it)
-inline int list_cap_for(int noff) { return 2 * noff + 2; }
+// candidate-list capacity per target for plumes of span = 2R + 1 neighbour
+// rows per axis: span + 2 entries per plane of rows (see build_list), plus a
+// sentinel and one entry read past it
+inline int list_cap_for(int dim, int span) { return (dim == 3 ? span : 1) * (span + 2) + 2; }
 // the same for the merged list of a lane's two targets (span + 1 rows per
 // plane, span + 1 planes in 3D; n + 2 ranges per plane of n rows)
 inline int list_cap_pair_for(int dim, int span) { return (dim == 3 ? span + 1 : 1) * (span + 3) + 2; }

@@ -8,32 +8,70 @@
 namespace ade {
 
 // ---------------------------------------------------------------------------
-// Candidate list of a target in LDS, in bytes of the 16-byte record array
-// (a context holds fewer than 2^28 - 256 particles, so offsets fit 32 bits
-// with room for a cursor step past the end).  Every stored range [s_k, e_k)
-// of the sorted order is non-empty.  With one lane per target entry k holds
-// (s_k, e_k); with several, (delta_k, e_k), delta_k = s_k - e_(k-1) (e_(-1) =
-// 0), so that a lane's overshoot past one range carries into the next.  A
-// sentinel closes the list; stepping into it puts the cursor at 2^31 or more
-// with the end at 2^30, so no slot is valid after it and no further step is
-// taken.  Entries of one target are `stride` apart (the targets of a
-// workgroup interleaved), and list[0] is the target's first entry.
+// Candidate list of a target in LDS: entries (s_k, e_k), in bytes of the
+// 16-byte record array (a context holds fewer than 2^28 - 256 particles, so
+// offsets fit 32 bits with room for a cursor step past the end), each a
+// non-empty range [s_k, e_k) of the sorted order, touching ranges stored as
+// one.  The rows are listed plane by plane (oz), in order of oy inside a
+// plane, and a row whose window wraps around the periodic x seam gives its
+// low part (at the start of the row) before its high part (which ends at the
+// end of the row, where the next row of the plane begins).  A window narrows
+// away from the target's own row, so the rows of a plane whose windows wrap
+// are consecutive: each wrapped row's high part merges with the next wrapped
+// row's low part, and a plane of n rows takes at most n + 1 entries, n + 2
+// when the row index wraps around the box among them.  A sentinel closes the
+// list; stepping into it puts the cursor at 2^31 or more with the end at
+// 2^30, so no slot is valid after it and no further step is taken.  Entries
+// of one target are `stride` apart (the targets of a workgroup interleaved),
+// and list[0] is the target's first entry.
 // ---------------------------------------------------------------------------
 constexpr uint32_t kListEndStart = 0x80000000u, kListEndEnd = 0x40000000u;
 constexpr uint32_t kRecBytes = 16;
 
-template <int DIM, int LANES>
-__device__ __forceinline__ uint32_t build_list(const PlumeDev& P, const uint32_t* __restrict__ cs,
-                                               const Target& T, uint2* list, uint32_t stride) {
+// Appends ranges to a list, merging a range that starts where the pending
+// one ends; flush() writes the pending range and the sentinel.
+struct ListWriter {
+    uint2* list;
+    uint32_t stride, k = 0, total = 0, ps = 0, pe = 0;  // pe == 0: nothing pending
+    __device__ __forceinline__ ListWriter(uint2* l, uint32_t s) : list(l), stride(s) {}
+    __device__ __forceinline__ void put(uint32_t s, uint32_t e) {
+        if (pe != 0u && s == pe) {
+            pe = e;
+            return;
+        }
+        if (pe != 0u) {
+            list[k * stride] = make_uint2(ps * kRecBytes, pe * kRecBytes);
+            total += pe - ps;
+            ++k;
+        }
+        ps = s;
+        pe = e;
+    }
+    __device__ __forceinline__ uint32_t flush() {
+        if (pe != 0u) {
+            list[k * stride] = make_uint2(ps * kRecBytes, pe * kRecBytes);
+            total += pe - ps;
+            ++k;
+        }
+        list[k * stride] = make_uint2(kListEndStart, kListEndEnd);
+        return total;
+    }
+};
+
+// Lane permutations inside a quad of lanes (full-rate DPP moves).
+template <int CTRL>
+__device__ __forceinline__ uint32_t quad_perm(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+
+// The list as one lane builds it alone (every lane of a target builds the
+// same list when LANES == 1).
+template <int DIM>
+__device__ __forceinline__ uint32_t build_list_lane(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                                    const Target& T, uint2* list, uint32_t stride) {
     const int span = 2 * P.R + 1;
     const int noff = (DIM == 3) ? span * span : span;
-    uint32_t prev = 0, k = 0, total = 0;
-    auto put = [&](uint32_t s, uint32_t e) {
-        list[k * stride] = make_uint2(LANES == 1 ? s * kRecBytes : s * kRecBytes - prev, e * kRecBytes);
-        total += e - s;
-        prev = e * kRecBytes;
-        ++k;
-    };
+    ListWriter w(list, stride);
     // four rows at a time: their cell-start loads are in flight together
     for (int j = 0; j < noff; j += 4) {
         RowRanges r[4];
@@ -44,12 +82,79 @@ __device__ __forceinline__ uint32_t build_list(const PlumeDev& P, const uint32_t
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            if (r[q].e0 > r[q].s0) put(r[q].s0, r[q].e0);
-            if (r[q].e1 > r[q].s1) put(r[q].s1, r[q].e1);
+            if (r[q].e1 > r[q].s1) w.put(r[q].s1, r[q].e1);  // low part of a wrapped row first
+            if (r[q].e0 > r[q].s0) w.put(r[q].s0, r[q].e0);
         }
     }
-    list[k * stride] = make_uint2(LANES == 1 ? kListEndStart : kListEndStart - prev, kListEndEnd);
+    return w.flush();
+}
+
+// The same ranges listed by the G lanes that serve one target (G = 2 or 4,
+// consecutive lanes of a quad) together: lane g computes rows g, g + G, ...,
+// and each round of G rows is written in row order at positions from a
+// prefix count over the group.  A row's low part that starts where the
+// previous row's range ends (a wrapped row after a wrapped row) extends that
+// row's entry instead of taking its own, so the bound of n + 2 entries per
+// plane of n rows holds as for ListWriter: in a run of wrapped rows, every
+// pair of neighbouring rows either merges or has one of the two parts empty.
+template <int DIM, int G>
+__device__ __forceinline__ uint32_t build_list_group(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                                     const Target& T, uint2* list, uint32_t stride) {
+    // quad_perm controls: the previous lane of the group, the lane two back,
+    // the group's last lane, and the two butterflies of a sum
+    constexpr int kPrev = (G == 4) ? 0x90 : 0xA0;  // [0,0,1,2] / [0,0,2,2]
+    constexpr int kPrev2 = 0x40;                    // [0,0,0,1]
+    constexpr int kLast = (G == 4) ? 0xFF : 0xF5;  // [3,3,3,3] / [1,1,3,3]
+    const uint32_t g = threadIdx.x & (G - 1);
+    const int span = 2 * P.R + 1;
+    const int noff = (DIM == 3) ? span * span : span;
+    uint32_t base = 0, total = 0;
+    uint32_t pS = 0, pE = 0;  // main range of the row before the round (end 0: none)
+    for (int j0 = 0; j0 < noff; j0 += G) {
+        RowRanges r{0u, 0u, 0u, 0u};
+        if (j0 + (int)g < noff) r = row_ranges<DIM>(P, cs, T, j0 + (int)g, span);
+        const bool hasL = r.e1 > r.s1, hasH = r.e0 > r.s0;
+        const uint32_t hS = hasH ? r.s0 : 0u, hE = hasH ? r.e0 : 0u;
+        // main range of the previous row
+        uint32_t qS = quad_perm<kPrev>(hS), qE = quad_perm<kPrev>(hE);
+        if (g == 0) {
+            qS = pS;
+            qE = pE;
+        }
+        const bool mergeL = hasL && qE != 0u && qE == r.s1;
+        const uint32_t cnt = ((hasL && !mergeL) ? 1u : 0u) + (hasH ? 1u : 0u);
+        // inclusive prefix over the group; every lane takes part in the moves
+        // (a move from a lane masked off by a branch would read nothing)
+        uint32_t incl = cnt + (quad_perm<kPrev>(cnt) & (g >= 1 ? ~0u : 0u));
+        if (G == 4) incl += quad_perm<kPrev2>(incl) & (g >= 2 ? ~0u : 0u);
+        const uint32_t first = base + incl - cnt;
+        uint32_t pos = first;
+        if (hasL && !mergeL) {
+            list[pos * stride] = make_uint2(r.s1 * kRecBytes, r.e1 * kRecBytes);
+            ++pos;
+        }
+        if (hasH) list[pos * stride] = make_uint2(r.s0 * kRecBytes, r.e0 * kRecBytes);
+        // the previous row's entry, extended by a merged low part, is
+        // rewritten after the round's entries (the LDS writes of a wavefront
+        // take effect in program order)
+        asm volatile("" ::: "memory");
+        if (mergeL) list[(first - 1u) * stride] = make_uint2(qS * kRecBytes, r.e1 * kRecBytes);
+        total += (r.e1 - r.s1) + (r.e0 - r.s0);
+        base += quad_perm<kLast>(incl);
+        pS = quad_perm<kLast>(hS);
+        pE = quad_perm<kLast>(hE);
+    }
+    list[base * stride] = make_uint2(kListEndStart, kListEndEnd);
+    total += quad_perm<0xB1>(total);                // [1,0,3,2]
+    if (G == 4) total += quad_perm<0x4E>(total);    // [2,3,0,1]
     return total;
+}
+
+template <int DIM, int LANES>
+__device__ __forceinline__ uint32_t build_list(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                               const Target& T, uint2* list, uint32_t stride) {
+    if (LANES == 2 || LANES == 4) return build_list_group<DIM, LANES>(P, cs, T, list, stride);
+    return build_list_lane<DIM>(P, cs, T, list, stride);
 }
 
 // Lane cursor over the concatenated ranges: b is the byte offset of this
@@ -57,8 +162,8 @@ __device__ __forceinline__ uint32_t build_list(const PlumeDev& P, const uint32_t
 // one (in flight from LDS).  A step advances b by LANES records.  With one
 // lane a step lands exactly on the end of a range and the cursor moves to
 // the next entry as it stands; with several, b - e < step exactly when the
-// lane has run past the end of its range by less than one step, which is the
-// overshoot carried into the next range (perhaps past it).
+// lane has run past the end of its range by less than one step, and that
+// overshoot is carried into the next range (perhaps past it).
 template <int LANES>
 struct Cursor {
     static constexpr uint32_t kStep = LANES * kRecBytes;
@@ -76,7 +181,7 @@ struct Cursor {
             }
         } else {
             while (b - e < kStep) {
-                b += nx.x;
+                b = nx.x + (b - e);
                 e = nx.y;
                 lp += stride;
                 nx = *lp;

@@ -203,13 +203,18 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
         d.ncell = (uint32_t)(std::pow(nr, pl.dim - 1) * nfx * nsub);
         d.cbase = (uint32_t)cbase;
         cbase += d.ncell;
-        if (cbase >= 0xffffffffull) return fail(ADE_EINVAL, "too many cells");
+        // cell tables are addressed with 32-bit byte offsets
+        if (cell_pad(cbase) >= (1ull << 30)) return fail(ADE_EINVAL, "too many cells (at most 2^30 per context)");
         d.Hu = Hu;
         d.H2d = Hu * Hu;
         d.H2f = (float)d.H2d;
         d.invHu = 1.0 / Hu;
         d.Hc2f = (float)(Hc * Hc);
         d.rowh2f = (float)((kTwo32 / nr) * (kTwo32 / nr));
+        // candidate windows are cut in x cells in float arithmetic: positions
+        // in cells carry a rounding of up to ~nfx 2^-23 cells, covered by the slack
+        d.cellx = (float)(nfx / kTwo32);
+        d.cslack = (float)(1.0 / 128.0 + nfx * std::ldexp(1.0, -20));
 
         double D[9];
         const double trD = trace_D(pl.dim, q.alpha_L, q.alpha_T, q.D_m, q.v, D);
@@ -279,7 +284,7 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
         }
         d.tcount = (uint32_t)pl.tiles.size() - d.tfirst;
         const int span = 2 * R + 1;
-        pl.list_cap = std::max(pl.list_cap, list_cap_for(pl.dim == 3 ? span * span : span));
+        pl.list_cap = std::max(pl.list_cap, list_cap_for(pl.dim, span));
         pl.list_cap_pair = std::max(pl.list_cap_pair, list_cap_pair_for(pl.dim, span));
         pl.plumes.push_back(d);
     }

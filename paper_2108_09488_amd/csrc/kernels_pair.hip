@@ -369,21 +369,7 @@ __device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_
     const int ny = 2 * P.R + 1 + (dy != 0 ? 1 : 0);
     const int nz = (DIM == 3) ? 2 * P.R + 1 + (dz != 0 ? 1 : 0) : 1;
     const int nrows = ny * nz;
-    uint32_t k = 0, total = 0;
-    uint32_t ps = 0, pe = 0;  // pending range (pe == 0: none; ranges are non-empty)
-    auto put = [&](uint32_t s, uint32_t e) {
-        if (pe != 0u && s == pe) {  // touches the pending range
-            pe = e;
-            return;
-        }
-        if (pe != 0u) {
-            list[k * stride] = make_uint2(ps * kRecBytes, pe * kRecBytes);
-            total += pe - ps;
-            ++k;
-        }
-        ps = s;
-        pe = e;
-    };
+    ListWriter w(list, stride);
     // two rows at a time: their cell-start loads are in flight together
     for (int j = 0; j < nrows; j += 2) {
         RowRanges r[2];
@@ -394,17 +380,11 @@ __device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            if (r[q].e1 > r[q].s1) put(r[q].s1, r[q].e1);
-            if (r[q].e0 > r[q].s0) put(r[q].s0, r[q].e0);
+            if (r[q].e1 > r[q].s1) w.put(r[q].s1, r[q].e1);
+            if (r[q].e0 > r[q].s0) w.put(r[q].s0, r[q].e0);
         }
     }
-    if (pe != 0u) {
-        list[k * stride] = make_uint2(ps * kRecBytes, pe * kRecBytes);
-        total += pe - ps;
-        ++k;
-    }
-    list[k * stride] = make_uint2(kListEndStart, kListEndEnd);
-    return total;
+    return w.flush();
 }
 
 // The walk of one lane's list (walk_stream) for two targets: every record
