@@ -240,6 +240,23 @@ int ade_adjoint(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *
                 int32_t n_sensors, const void *d_obs, void *d_adj_ws, size_t adj_ws_bytes,
                 double *h_J, double *h_grad);
 
+/* The same as ade_adjoint, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the adjoint workspace is a fixed array of the library's own
+ * device memory instead of a caller's buffer, so the call allocates nothing
+ * (no hipMalloc, no hipFree, no allocating library routine).  The array
+ * holds ade_adjoint_noalloc_max_bytes() bytes (64 MiB); a run whose adjoint
+ * workspace (ade_adjoint_workspace_bytes) is larger returns ADE_EWORKSPACE
+ * and changes nothing.  Each GPU the library runs on holds one such array
+ * from the first call on it until the process ends, and every call on that
+ * GPU uses it: calls that overlap on one GPU (other threads, other streams)
+ * race and must not be made.  Results are those of ade_adjoint (the same
+ * kernels in the same order); arguments, errors and synchronisation as for
+ * ade_adjoint. */
+int ade_adjoint_noalloc(ade_ctx *ctx, int64_t nsteps, int32_t ckpt_every, const double *d_xs,
+                        int32_t n_sensors, const void *d_obs, double *h_J, double *h_grad);
+int ade_adjoint_noalloc_max_bytes(size_t *bytes);
+
 /* HIP-event timing of the pair kernel launches on the context's stream.
  * mode 1: start (clears the totals; events are recorded around every pair
  * kernel launched eagerly by ade_step / ade_rhs).  mode 0: stop, synchronise

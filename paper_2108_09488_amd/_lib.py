@@ -25,6 +25,7 @@ ERROR_NAMES = {0: "ADE_OK", -1: "ADE_EINVAL", -2: "ADE_EWORKSPACE", -3: "ADE_EHI
 EXPORTS = ["ade_workspace_bytes", "ade_create", "ade_init_particles", "ade_set_velocities", "ade_build_cells",
            "ade_step", "ade_step_graph", "ade_rhs", "ade_read_C", "ade_read_x", "ade_mass", "ade_conc_range",
            "ade_neighbours", "ade_sensor_interp", "ade_adjoint_workspace_bytes", "ade_adjoint",
+           "ade_adjoint_noalloc", "ade_adjoint_noalloc_max_bytes",
            "ade_kernel_timing", "ade_autotune", "ade_set_tuning", "ade_get_tuning", "ade_info",
            "ade_state_bytes", "ade_save_state", "ade_load_state", "ade_destroy", "ade_last_error",
            "ade_version"]
@@ -83,6 +84,8 @@ def lib() -> ct.CDLL:
         "ade_sensor_interp": [p, p, i32, p],
         "ade_adjoint_workspace_bytes": [p, i64, i32, i32, psz],
         "ade_adjoint": [p, i64, i32, p, i32, p, p, sz, pd, pd],
+        "ade_adjoint_noalloc": [p, i64, i32, p, i32, p, pd, pd],
+        "ade_adjoint_noalloc_max_bytes": [psz],
         "ade_kernel_timing": [p, i32, pd, pi64],
         "ade_autotune": [p, i32, i32, T],
         "ade_set_tuning": [p, T],

@@ -242,6 +242,19 @@ class Context:
                                 _ptr(obs), _ptr(ws), nb.value, ct.byref(J), g))
         return J.value, [g[0], g[1], g[2]]
 
+    def adjoint_noalloc(self, nsteps: int, ckpt_every: int, xs: torch.Tensor, obs: torch.Tensor):
+        """adjoint() through ade_adjoint_noalloc: the library's static scratch
+        array serves as the adjoint workspace (no device allocation in the call;
+        xs and obs must already be device tensors of the right type)."""
+        assert xs.device == self.device and xs.dtype == torch.float64 and xs.is_contiguous()
+        assert obs.device == self.device and obs.dtype == self.dtype and obs.is_contiguous()
+        self._inputs_ready(xs, obs)
+        J = ct.c_double()
+        g = (ct.c_double * 3)()
+        check(lib().ade_adjoint_noalloc(self._h, int(nsteps), int(ckpt_every), _ptr(xs), xs.shape[1],
+                                        _ptr(obs), ct.byref(J), g))
+        return J.value, [g[0], g[1], g[2]]
+
 
 def workspace_bytes(params, counts) -> int:
     ps = [p if isinstance(p, AdeParams) else params_from_spec(p) for p in params]

@@ -33,6 +33,8 @@
 // lambda^N = sum_s 2 (C_s - d_s) W(r_sb) / sum_b' W(r_sb').
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <type_traits>
 
 #include "ade_walk.h"
 #include "ctx.h"
@@ -411,11 +413,36 @@ uint32_t adj_block(const Plan& pl) {
     return 64;
 }
 
+// count snapshots laid out one after the other, `stride` bytes apart (every
+// snapshot of a context has the same size and starts 256-byte aligned)
+struct SnapSeq {
+    Snap first{};
+    size_t stride = 0;
+    size_t count = 0;
+    Snap operator[](size_t k) const {
+        Snap s = first;
+        const size_t d = k * stride;
+        auto shift = [d](auto*& p) {
+            if (p) p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(reinterpret_cast<char*>(p) + d);
+        };
+        for (int i = 0; i < 3; ++i) shift(s.pos[i]);
+        shift(s.C);
+        shift(s.id);
+        shift(s.rec);
+        shift(s.cs);
+        shift(s.step);
+        for (int i = 0; i < 3; ++i) shift(s.vel[i]);
+        for (int i = 0; i < 6; ++i) shift(s.rD[i]);
+        shift(s.grec);
+        return s;
+    }
+};
+
 struct AdjLayout {
     size_t bytes = 0;
-    std::vector<Snap> ck;   // checkpoints (every K steps, plus the final state)
-    std::vector<Snap> seg;  // states of one segment
-    std::vector<Snap> segh; // velocity field with the predictor-corrector: their half-step states
+    SnapSeq ck;    // checkpoints (every K steps, plus the final state)
+    SnapSeq seg;   // states of one segment
+    SnapSeq segh;  // velocity field with the predictor-corrector: their half-step states
     void* y;                // ... and y = L lambda of the corrector stage (id order)
     void* lam[2];
     void* lam_s;
@@ -461,13 +488,25 @@ void adj_layout(const ade_ctx* c, int64_t nsteps, int32_t K, int32_t ns, char* b
     };
     const Plan& pl = c->plan;
     const int64_t nck = (nsteps + K - 1) / K + 1;
-    L.ck.resize((size_t)nck);
-    L.seg.resize((size_t)K);
-    for (auto& s : L.ck) take_snap(base, off, c, s);
-    for (auto& s : L.seg) take_snap(base, off, c, s);
+    // one snapshot's size, as take_snap lays it out from an aligned offset
+    size_t snap_bytes = 0;
+    {
+        Snap probe;
+        take_snap(nullptr, snap_bytes, c, probe);
+        snap_bytes = (snap_bytes + 255) & ~size_t(255);
+    }
     const bool gpc = pl.general && pl.integrator == ADE_PC;
-    L.segh.resize(gpc ? (size_t)K : 0);
-    for (auto& s : L.segh) take_snap(base, off, c, s);
+    auto seq = [&](SnapSeq& q, size_t count) {
+        q.count = count;
+        q.stride = snap_bytes;
+        off = (off + 255) & ~size_t(255);
+        size_t o = off;
+        if (count) take_snap(base, o, c, q.first);
+        off += count * snap_bytes;
+    };
+    seq(L.ck, (size_t)nck);
+    seq(L.seg, (size_t)K);
+    seq(L.segh, gpc ? (size_t)K : 0);
     const size_t N = (size_t)pl.N, rb = (size_t)pl.real_bytes;
     L.lam[0] = take(N * rb);
     L.lam[1] = take(N * rb);
@@ -607,13 +646,15 @@ int ade_adjoint_workspace_bytes(const ade_ctx* c, int64_t nsteps, int32_t ckpt_e
     return ADE_OK;
 }
 
-int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32_t ns, const void* d_obs,
+}  // extern "C"
+
+namespace {
+
+// The adjoint run of ade_adjoint over a workspace of ws_bytes at d_ws
+// (256-byte aligned; arguments checked by the caller).
+int adjoint_run(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32_t ns, const void* d_obs,
                 void* d_ws, size_t ws_bytes, double* h_J, double* h_grad) {
-    int rc = check_sensor_args(c, d_xs, ns);
-    if (rc) return rc;
-    if (!d_obs || !d_ws || !h_J || !h_grad) return fail(ADE_EINVAL, "null argument");
-    if (nsteps < 1 || K < 1) return fail(ADE_EINVAL, "nsteps and ckpt_every must be positive");
-    if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
+    int rc = ADE_OK;
     AdjLayout L;
     adj_layout(c, nsteps, K, ns, nullptr, L);
     if (ws_bytes < L.bytes) return fail(ADE_EWORKSPACE, "adjoint workspace too small: need %zu bytes", L.bytes);
@@ -681,7 +722,7 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
             }
         }
         for (int64_t n = n1 - 1; n >= n0; --n) {
-            const Snap& sn = L.seg[(size_t)(n - n0)];
+            const Snap sn = L.seg[(size_t)(n - n0)];
             const StateArrays Sa = snap_arrays(c, sn);
             dim3 g((N + 255) / 256), b(256);
             const dim3 ag(pl.ntiles * asubs), abk(ab);
@@ -709,7 +750,7 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
                 if (pl.integrator == ADE_PC) {
                     // y = L2 lambda at the half-step state (its own cells and
                     // order), then lambda^n = lambda + dt y + dt^2/2 L1 y here
-                    const Snap& sh = L.segh[(size_t)(n - n0)];
+                    const Snap sh = L.segh[(size_t)(n - n0)];
                     const StateArrays Sh = snap_arrays(c, sh);
 #define GATHER_H(D, R, KK)                                                                                 \
     hipLaunchKernelGGL((k_adj_gather<D, R>), g, b, 0, st, Sh, (const R*)L.lam[li], (const R*)sh.C, N,       \
@@ -759,6 +800,82 @@ int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32
     for (int k = 0; k < 3; ++k) h_grad[k] = hostv[k];
     *h_J = hostv[3];
     return ADE_OK;
+}
+
+int check_adjoint_args(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32_t ns, const void* d_obs,
+                       double* h_J, double* h_grad) {
+    int rc = check_sensor_args(c, d_xs, ns);
+    if (rc) return rc;
+    if (!d_obs || !h_J || !h_grad) return fail(ADE_EINVAL, "null argument");
+    if (nsteps < 1 || K < 1) return fail(ADE_EINVAL, "nsteps and ckpt_every must be positive");
+    return ADE_OK;
+}
+
+// Adjoint workspace of the allocation-free entry point: a fixed array in the
+// library's device memory (one copy per GPU, held until the process ends).
+// Host code reaches it only through the address hipGetSymbolAddress gives
+// on each device, never through the array's name.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices];
+
+// The scratch array's address on the device of stream st (looked up once per
+// device, with that device current).
+int scratch_on(hipStream_t st, void** out) {
+    int cur = 0, dev = 0;
+    HIPCHK(hipGetDevice(&cur));
+    dev = cur;
+    if (st) HIPCHK(hipStreamGetDevice(st, &dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(ADE_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        if (dev != cur) HIPCHK(hipSetDevice(dev));
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (dev != cur) HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess || !p)
+            return fail(ADE_EHIP, "hipGetSymbolAddress of the scratch array: %s", hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return ADE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ade_adjoint(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32_t ns, const void* d_obs,
+                void* d_ws, size_t ws_bytes, double* h_J, double* h_grad) {
+    int rc = check_adjoint_args(c, nsteps, K, d_xs, ns, d_obs, h_J, h_grad);
+    if (rc) return rc;
+    if (!d_ws) return fail(ADE_EINVAL, "null workspace");
+    if (reinterpret_cast<uintptr_t>(d_ws) & 255u) return fail(ADE_EINVAL, "workspace must be 256-byte aligned");
+    return adjoint_run(c, nsteps, K, d_xs, ns, d_obs, d_ws, ws_bytes, h_J, h_grad);
+}
+
+int ade_adjoint_noalloc_max_bytes(size_t* bytes) {
+    if (!bytes) return fail(ADE_EINVAL, "null argument");
+    *bytes = kNoAllocScratchBytes;
+    return ADE_OK;
+}
+
+int ade_adjoint_noalloc(ade_ctx* c, int64_t nsteps, int32_t K, const double* d_xs, int32_t ns, const void* d_obs,
+                        double* h_J, double* h_grad) {
+    int rc = check_adjoint_args(c, nsteps, K, d_xs, ns, d_obs, h_J, h_grad);
+    if (rc) return rc;
+    AdjLayout L;
+    adj_layout(c, nsteps, K, ns, nullptr, L);
+    if (L.bytes > kNoAllocScratchBytes)
+        return fail(ADE_EWORKSPACE,
+                    "ade_adjoint_noalloc: this run needs %zu bytes of adjoint workspace, above the %zu bytes of "
+                    "the library's static scratch array; use ade_adjoint with a workspace",
+                    L.bytes, kNoAllocScratchBytes);
+    void* ws = nullptr;
+    if ((rc = scratch_on(c->stream, &ws))) return rc;
+    return adjoint_run(c, nsteps, K, d_xs, ns, d_obs, ws, kNoAllocScratchBytes, h_J, h_grad);
 }
 
 }  // extern "C"
