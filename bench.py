@@ -1,19 +1,22 @@
 """Benchmark: particle-neighbour interactions per second of the SPH
 advection-dispersion step on one MI355X.
 
-Workload (default): the 2D consistency sweep -- six 512^2-particle plumes on
-jittered lattices (+-0.1 dp), Wendland C4, h/dp in {1.3, 2, 3} x
-alpha_L/alpha_T in {10, 100}, FP32, dt from Eq. (10), held in one context.
-One bench step advances each of the six plumes by one explicit step (pair sum
-of Eqs. 4-5, update of C and x, cell-list rebuild), one launch per kernel for
-all six.  value = sum over plumes of the
-directed interactions per step (pairs b != a with 0 < r <= H) times the
-steps, divided by the wall time of the timed region.
+Workload (default, the headline): the 3D plume -- 128^3 = 2,097,152 particles
+on a lattice jittered by +-0.1 dp, Wendland C4, h = 2 dp (support H = 4 dp,
+~256 neighbours), alpha_L = 1e-2, alpha_T = 1e-3, D_m = 1e-6, v = (1, 0, 0),
+FP32 state, explicit Euler steps of 5e-5.  One bench step is one step of the
+plume (pair sum of Eqs. 4-5 fused with the update of C and x and the hashing
+of the moved particles, then the cell-list rebuild), replayed from the HIP
+graph of one captured step, inputs resident in HBM.  value = the directed
+interactions of a step (pairs b != a with 0 < r <= H) times the steps,
+divided by the wall time of the timed region.
 
-Also reported: the HIP-event time of the pair kernel and its roofline, the
-same sweep replayed from HIP graphs, the batched ensemble (256 plumes of
-32^2..256^2 particles in one context), and the FP64 CPU oracle on a bounded
-sample of the same workload (cpu_baseline).
+Also reported: the roofline of the pair kernel (HIP events on its eager
+launches), the 2D consistency sweep (six 512^2 plumes in one context), the
+batched ensemble (256 plumes of 32^2..256^2 particles, 200 graph-replayed
+steps), the inverse problem (forward + adjoint), the velocity-field plume and
+the paper-scale problems, each with the pair kernel's roofline, and the FP64
+CPU oracle on a bounded sample of the headline workload (cpu_baseline).
 """
 from __future__ import annotations
 
@@ -38,6 +41,7 @@ FLOPS_PER_INTERACTION = {2: 29, 3: 39}
 FLOPS_PER_INTERACTION_FIELD = {2: 57}
 PEAK_FP32_VECTOR_TFLOPS = 157.3      # MI355X published vector FP32 (packed FMA)
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "pair_kernel_traffic.md")
+TRAFFIC_PROFILE_3D = os.path.join(ROOT, "profiles", "pair_kernel_traffic_3d.md")
 PAIR_SOURCES = ["kernels_pair.hip", "ade_walk.h", "ade_geom.h", "ade_device.h", "ade_internal.h"]
 PEAK_FP32_NONPACKED_TFLOPS = 78.6    # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 2 (FMA)
 # single-issue VALU roof: 256 CU x 64 lanes x 2.4 GHz lane-slots per second, and
@@ -51,21 +55,21 @@ def valu_issue_frac(dim, interactions, seconds):
     return ISSUE_SLOTS_PER_INTERACTION[dim] * interactions / seconds / VALU_SLOTS_PER_S
 
 
-def step_kernel_name(tuning):
-    """The update-mode pair kernel a launch shape runs (2D, FP32, Wendland C4)."""
+def step_kernel_name(tuning, dim=2):
+    """The update-mode pair kernel a launch shape runs (FP32, Wendland C4)."""
     if tuning.get("targets", 1) == 2:
-        return "k_pair2<2, float, 4, 0>"
-    return f"k_pair<2, float, 4, 0, {tuning['lanes']}>"
+        return f"k_pair2<{dim}, float, 4, 0>"
+    return f"k_pair<{dim}, float, 4, 0, {tuning['lanes']}>"
 
 
-def pair_profile(kernel, key="traffic_bytes_per_launch"):
-    """A figure of the pair kernel from the committed counter profile (HBM
-    bytes per launch from FETCH_SIZE/WRITE_SIZE, or the L2 and L1 hit rates),
-    or None when the kernel sources changed since it was taken or the profile
+def pair_profile(kernel, key="traffic_bytes_per_launch", profile=None):
+    """A figure of the pair kernel from a committed counter profile (HBM bytes
+    per launch from FETCH_SIZE/WRITE_SIZE, or the L2 and L1 hit rates), or
+    None when the kernel sources changed since it was taken or the profile
     covers another launch shape's kernel."""
     import hashlib
     try:
-        text = open(TRAFFIC_PROFILE).read()
+        text = open(profile or TRAFFIC_PROFILE).read()
     except OSError:
         return None
     vals = dict(l.split(":", 1) for l in text.splitlines()
@@ -133,8 +137,9 @@ def time_sweep(sweep, steps, warmup, graph):
 def batched(device, steps, warmup, n_plumes=256):
     """The ensemble: 256 plumes of 32^2..256^2 particles with their own
     dispersivities, flow directions and time steps, in one context: one
-    launch per kernel per step, the pair kernel on a persistent grid, steps
-    replayed from a HIP graph, launch shape picked by the autotuner."""
+    launch per kernel per step for all plumes, steps replayed from a HIP
+    graph, launch shape (work-item size, lanes and targets per lane,
+    persistent grid or not, XCD dealing) picked by the autotuner."""
     import numpy as np
     import torch
     from paper_2108_09488_amd import inputs as I
@@ -155,6 +160,12 @@ def batched(device, steps, warmup, n_plumes=256):
     ctx.step_graph(steps)
     _sync()
     wall = time.perf_counter() - t0
+    # the pair kernel's roofline from eager steps with HIP events on its launches
+    ectx_steps = min(steps, 20)
+    ctx.timing_start()
+    ctx.step(ectx_steps)
+    _sync()
+    pms, pn = ctx.timing_stop()
     n = ctx.N
     ctx.close()
     # plain reference at the ensemble's neighbour count: one 512^2 plume with
@@ -179,7 +190,8 @@ def batched(device, steps, warmup, n_plumes=256):
             "interactions_per_s": rate,
             "plain_same_nbar": {"workload": "one 512^2 plume, h/dp 1.5, C4, FP32, graph replay",
                                 "neighbours_mean": rinter / ref.n, "interactions_per_s": plain},
-            "vs_plain_same_nbar": rate / plain}
+            "vs_plain_same_nbar": rate / plain,
+            "roofline": roofline_alu(2, inter, pms / pn, step_kernel_name(tuned), pn)}
 
 
 def fwd_adjoint(device):
@@ -229,30 +241,130 @@ def fwd_adjoint(device):
             "vs_plain": wall_fwd / wall_adj, "J": J, "grad": g}
 
 
-def single_3d(device, steps=10):
-    """One 3D plume, 128^3 particles, h = 2 dp (about 270 neighbours)."""
+def roofline_alu(dim, interactions, ms_per_launch, kernel, launches, profile=None, field=False):
+    """Roofline entry of a pair kernel bound by its plain FP32 arithmetic:
+    algorithmic flops of one launch (the interactions it evaluates times the
+    flops of one) over its mean HIP-event duration, against the published
+    FP32 vector peak; with the single-issue VALU fraction and, while the
+    kernel sources match a committed counter profile, its HBM bytes and cache
+    hit rates."""
+    fpi = FLOPS_PER_INTERACTION_FIELD[dim] if field else FLOPS_PER_INTERACTION[dim]
+    achieved = fpi * interactions / (ms_per_launch * 1e-3) / 1e12
+    out = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+           "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
+           "traffic": pair_profile(kernel, "traffic_bytes_per_launch", profile) if profile else None,
+           "kernel": kernel + " (update mode)", "avg_launch_ms": ms_per_launch, "launches": launches,
+           "flops_per_interaction": fpi, "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS}
+    if not field:
+        out["valu_issue_frac"] = valu_issue_frac(dim, interactions, ms_per_launch * 1e-3)
+    if profile:
+        out["l2_hit_rate"] = pair_profile(kernel, "l2_hit_rate", profile)
+        out["l1_hit_rate"] = pair_profile(kernel, "l1_hit_rate", profile)
+    return out
+
+
+def headline_3d(device, steps, warmup):
+    """The 3D plume (128^3 particles, h = 2 dp, FP32): autotuned launch shape,
+    `steps` steps replayed from the captured graph after `warmup` (the timed
+    region), then the same number of eager steps with HIP events around every
+    pair-kernel launch (the roofline)."""
     import numpy as np
     import torch
     from paper_2108_09488_amd import inputs as I
     from paper_2108_09488_amd.context import Context, params_from_spec
 
     s = I.config("cfg3")
-    c = Context([params_from_spec(s)], [s.n], device=device)
+    stream = torch.cuda.Stream(device=device)
+    c = Context([params_from_spec(s)], [s.n], device=device, stream=stream)
     x = s.positions()
     c.init(torch.from_numpy(x), torch.from_numpy(s.concentration(x).astype(np.float32))).build()
-    off, _ = c.neighbours()
-    inter = int(off[-1].item())
+    inter = int(c.neighbour_counts()[-1].item())
     tuned = c.autotune(reps=2)
-    c.step(2)
+    print(f"[bench] 3D plume built: {inter} interactions per step, tuning {tuned}", file=sys.stderr, flush=True)
+    c.step_graph(warmup)
     _sync()
     t0 = time.perf_counter()
-    c.step(steps)
+    c.step_graph(steps)
     _sync()
     wall = time.perf_counter() - t0
+    c.timing_start()
+    t1 = time.perf_counter()
+    c.step(steps)
+    _sync()
+    ewall = time.perf_counter() - t1
+    ms, n = c.timing_stop()
+    cells = c.info()["cells"]
     c.close()
-    return {"particles": s.n, "interactions_per_step": inter, "steps": steps, "tuning": tuned,
-            "ms_per_step": 1e3 * wall / steps, "interactions_per_s": inter * steps / wall,
-            "valu_issue_frac_of_step": valu_issue_frac(3, inter * steps, wall)}
+    kernel = step_kernel_name(tuned, dim=3)
+    return {"spec": s, "interactions_per_step": inter, "tuning": tuned, "wall": wall, "cells": cells,
+            "eager": {"ms_per_step": 1e3 * ewall / steps, "interactions_per_s": inter * steps / ewall,
+                      "pair_kernel_ms_per_step": ms / n},
+            "roofline": roofline_alu(3, inter, ms / n, kernel, n, profile=TRAFFIC_PROFILE_3D)}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_single_thread_sample(n_targets=30000):
+    """Child-process body: the oracle's right-hand side of the 3D plume at a
+    seeded sample of target particles on one thread; prints JSON."""
+    import numpy as np
+    import oracle as O
+    from paper_2108_09488_amd import inputs as I
+
+    s = I.config("cfg3")
+    x = s.positions()
+    C = s.concentration(x).astype(np.float32).astype(np.float64)
+    m = O.model_from_spec(s)
+    idx = np.sort(np.random.default_rng(3).choice(s.n, n_targets, replace=False))
+    t0 = time.perf_counter()
+    O.rhs(m, x, C, v_uniform=s.velocity(), mass=s.mass, rho=s.rho0, idx=idx)
+    wall = time.perf_counter() - t0
+    print(json.dumps({"targets": n_targets, "seconds": wall, "threads": O.num_threads()}))
+
+
+def cpu_baseline_3d(inter_per_step, budget_steps=2):
+    """The FP64 oracle on the host cores: whole explicit steps of the 3D plume
+    (cell list, pair sum, update) on every core, and the pair sum of a seeded
+    sample of targets on one thread (a child process with OMP_NUM_THREADS=1),
+    scaled by the sample's share of the step's interactions."""
+    import subprocess
+    import numpy as np
+    import oracle as O
+    from paper_2108_09488_amd import inputs as I
+
+    s = I.config("cfg3")
+    x = s.positions()
+    C = s.concentration(x).astype(np.float32).astype(np.float64)
+    m = O.model_from_spec(s)
+    t0 = time.perf_counter()
+    O.run(m, x, C, s.dt, budget_steps, v_uniform=s.velocity(), mass=s.mass, rho=s.rho0)
+    wall = time.perf_counter() - t0
+    out = {"value": inter_per_step * budget_steps / wall, "unit": "interactions/s", "cores": O.num_threads(),
+           "kind": "oracle", "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+           "sample": f"{budget_steps} explicit FP64 steps of the 128^3 plume on all host cores "
+                     f"({1e3 * wall / budget_steps:.0f} ms per step)"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    try:
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-single-thread"], env=env,
+                           capture_output=True, text=True, timeout=300)
+        st = json.loads(r.stdout.strip().splitlines()[-1])
+        # the sample's targets hold the step's mean neighbour count (seeded
+        # uniform draw over a near-uniform lattice)
+        rate = st["targets"] / s.n * inter_per_step / st["seconds"]
+        out["single_thread"] = {"value": rate, "unit": "interactions/s", "threads": st["threads"],
+                                "sample": f"the rhs of {st['targets']} seeded targets of the 128^3 plume, "
+                                          f"one thread ({st['seconds']:.2f} s, cell list included)"}
+    except Exception as e:  # the single-thread figure is context only
+        out["single_thread"] = {"error": str(e)[:200]}
+    return out
 
 
 def velocity_field(device, steps=50, warmup=3):
@@ -297,11 +409,8 @@ def velocity_field(device, steps=50, warmup=3):
     f = out["field"]
     f["vs_uniform"] = f["interactions_per_s"] / out["uniform"]["interactions_per_s"]
     out["fwd_adjoint"] = velocity_field_adjoint(device)
-    achieved = FLOPS_PER_INTERACTION_FIELD[2] * f["interactions_per_step"] / (f["pair_kernel_ms"] * 1e-3) / 1e12
-    f["roofline"] = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "flops_per_interaction": FLOPS_PER_INTERACTION_FIELD[2],
-                     "kernel": "k_pair_gen<2, float, 4, 0, 4> (update mode)"}
+    f["roofline"] = roofline_alu(2, f["interactions_per_step"], f["pair_kernel_ms"], "k_pair_gen<2, float, 4, 0, 4>",
+                                 steps, field=True)
     out["workload"] = ("cfg2 plume h/dp 2, alpha_L/alpha_T 10, 512^2 FP32, explicit Euler; "
                        "interactions counted at the initial positions")
     return out
@@ -401,53 +510,27 @@ def velocity_field_adjoint(device, steps=200, ckpt=20):
             "J": J, "grad": g}
 
 
-def cpu_baseline(cells, budget_s=20.0):
-    """The FP64 oracle on the host cores: one explicit step of each plume of
-    the sweep (full 512^2 size), repeated while within the time budget."""
-    import numpy as np
-    import oracle as O
-    from paper_2108_09488_amd import inputs as I
-
-    total_inter = 0
-    total_wall = 0.0
-    reps = 0
-    specs = [I.config(c) for c in cells]
-    prepared = []
-    for s in specs:
-        x = s.positions()
-        C = s.concentration(x).astype(np.float32).astype(np.float64)
-        m = O.model_from_spec(s)
-        off, _ = O.neighbours_cells(m, x)
-        prepared.append((s, m, x, C, int(off[-1])))
-    while total_wall < budget_s and reps < 3:
-        for s, m, x, C, inter in prepared:
-            t0 = time.perf_counter()
-            O.run(m, x, C, s.dt, 1, v_uniform=s.velocity(), mass=s.mass, rho=s.rho0)
-            total_wall += time.perf_counter() - t0
-            total_inter += inter
-        reps += 1
-    return {"value": total_inter / total_wall, "unit": "interactions/s", "cores": O.num_threads(),
-            "kind": "oracle",
-            "sample": f"{reps} explicit step(s) of each of the {len(cells)} 512^2 sweep plumes, FP64"}
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=50)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--no-extras", action="store_true", help="skip graph replay and batched runs")
-    ap.add_argument("--extras", default="batched,fwd_adjoint,single_3d,velocity_field,paper_scale",
+    ap.add_argument("--no-extras", action="store_true", help="skip every workload but the headline")
+    ap.add_argument("--extras", default="sweep,batched,fwd_adjoint,velocity_field,paper_scale",
                     help="comma-separated extras to run (unless --no-extras)")
     ap.add_argument("--cells", default="", help="comma-separated subset of the sweep plumes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
+    ap.add_argument("--cpu-single-thread", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_single_thread:  # child process of cpu_baseline_3d (no GPU use)
+        cpu_single_thread_sample()
+        return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the sweep and the "
-              "ensemble are single-GPU workloads here.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): every workload here is "
+              "a single-GPU workload, and no multi-GPU path is built.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -461,37 +544,45 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    cells = args.cells.split(",") if args.cells else list(I.CFG2_CELLS)
-    sweep = build_sweep(cells, device)
-    sweep["tuning"] = sweep["ctx"].autotune(reps=3)
-    inter_step = sum(sweep["interactions"])
-    print(f"[bench] sweep built: {len(cells)} plumes, {inter_step} interactions per step, "
-          f"tuning {sweep['tuning']}", file=sys.stderr, flush=True)
 
-    # timed region: every plume's captured step replayed from its HIP graph
-    wall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
-    value = inter_step * args.steps / wall
-    print(f"[bench] graph: {1e3 * wall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
-    # the same steps launched eagerly, with HIP events around every pair kernel
-    ewall, pair = time_sweep(sweep, args.steps, args.warmup, graph=False)
-    print(f"[bench] eager: {1e3 * ewall / args.steps:.3f} ms/step", file=sys.stderr, flush=True)
-    avg_ms = pair["ms_total"] / pair["launches"]
-    achieved = pair["flops"] / (pair["ms_total"] * 1e-3) / 1e12
-    extras = {"eager": {"ms_per_step": 1e3 * ewall / args.steps,
-                        "interactions_per_s": inter_step * args.steps / ewall,
-                        "pair_kernel_ms_per_step": pair["ms_total"] / args.steps}}
+    # the headline: the 3D plume, graph-replayed steps
+    h = headline_3d(device, args.steps, args.warmup)
+    inter3 = h["interactions_per_step"]
+    value = inter3 * args.steps / h["wall"]
+    print(f"[bench] 3D plume: {1e3 * h['wall'] / args.steps:.3f} ms/step (graph), pair kernel "
+          f"{1e3 * h['roofline']['avg_launch_ms']:.1f} us", file=sys.stderr, flush=True)
+    extras = {"eager": h["eager"]}
     want = set() if args.no_extras else set(args.extras.split(","))
+    if "sweep" in want:
+        cells = args.cells.split(",") if args.cells else list(I.CFG2_CELLS)
+        sweep = build_sweep(cells, device)
+        sweep["tuning"] = sweep["ctx"].autotune(reps=3)
+        inter_step = sum(sweep["interactions"])
+        wall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
+        ewall, pair = time_sweep(sweep, args.steps, args.warmup, graph=False)
+        sweep["ctx"].close()
+        kname = step_kernel_name(sweep["tuning"])
+        extras["sweep"] = {
+            "workload": "2D consistency sweep: 6 plumes x 512^2 particles, jitter 0.1 dp, Wendland C4, "
+                        "h/dp {1.3,2,3} x alpha_L/alpha_T {10,100}, FP32, explicit Euler, dt Eq. (10), "
+                        "one context",
+            "interactions_per_step": inter_step, "tuning": sweep["tuning"],
+            "per_plume": {n: {"interactions_per_step": i, "neighbours_mean": i / s.n}
+                          for n, i, s in zip(sweep["names"], sweep["interactions"], sweep["specs"])},
+            "ms_per_step": 1e3 * wall / args.steps, "interactions_per_s": inter_step * args.steps / wall,
+            "eager_ms_per_step": 1e3 * ewall / args.steps,
+            "roofline": roofline_alu(2, inter_step, pair["ms_total"] / pair["launches"], kname,
+                                     pair["launches"], profile=TRAFFIC_PROFILE)}
+        print(f"[bench] sweep: {1e3 * wall / args.steps:.3f} ms/step (graph)", file=sys.stderr, flush=True)
     if "batched" in want:
-        b = batched(device, steps=min(args.steps, 200), warmup=args.warmup)
-        b["vs_plain"] = b["interactions_per_s"] / value
+        b = batched(device, steps=200, warmup=args.warmup)
+        b["vs_plain"] = b["interactions_per_s"] / extras["sweep"]["interactions_per_s"] if "sweep" in extras else None
+        b["vs_plain_workload"] = "the six-plume 2D sweep context (graph replay)"
         extras["batched"] = b
         print(f"[bench] batched: {b['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if "fwd_adjoint" in want:
         extras["fwd_adjoint"] = fwd_adjoint(device)
         print(f"[bench] fwd+adjoint: {extras['fwd_adjoint']['ms_fwd_adjoint']:.1f} ms", file=sys.stderr, flush=True)
-    if "single_3d" in want:
-        extras["single_3d"] = single_3d(device)
-        print(f"[bench] 3D: {extras['single_3d']['ms_per_step']:.3f} ms/step", file=sys.stderr, flush=True)
     if "paper_scale" in want:
         extras["paper_scale"] = paper_scale(device)
     if "velocity_field" in want:
@@ -502,10 +593,8 @@ def main():
               f"{vf['uniform']['ms_per_step']:.3f} ms/step; fwd+adjoint "
               f"{vf['fwd_adjoint']['ms_fwd_adjoint']:.1f} ms vs fwd {vf['fwd_adjoint']['ms_fwd']:.1f} ms",
               file=sys.stderr, flush=True)
-    per_cell = {n: {"interactions_per_step": i, "neighbours_mean": i / s.n}
-                for n, i, s in zip(sweep["names"], sweep["interactions"], sweep["specs"])}
-    sweep["ctx"].close()
 
+    s3 = h["spec"]
     line = {
         "metric": "particle-neighbour interactions/s per ADE step (fwd, fwd+adjoint, batched) vs plain",
         "value": value,
@@ -513,32 +602,23 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * wall / args.steps,
+        "ms_per_step": 1e3 * h["wall"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "2D consistency sweep: 6 plumes x 512^2 particles, jitter 0.1 dp, "
-                               "Wendland C4, h/dp {1.3,2,3} x alpha_L/alpha_T {10,100}, FP32, "
-                               "explicit Euler, dt Eq. (10)",
-                   "plumes": cells, "interactions_per_step": inter_step, "per_plume": per_cell,
-                   "tuning": sweep["tuning"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_VECTOR_TFLOPS,
-                     "traffic": pair_traffic(step_kernel_name(sweep["tuning"])),
-                     "kernel": step_kernel_name(sweep["tuning"]) + " (update mode)", "avg_launch_ms": avg_ms,
-                     "launches": pair["launches"],
-                     "flops_per_interaction": FLOPS_PER_INTERACTION[2],
-                     "frac_of_nonpacked_peak": achieved / PEAK_FP32_NONPACKED_TFLOPS,
-                     "valu_issue_frac": valu_issue_frac(2, inter_step * pair["launches"], pair["ms_total"] * 1e-3),
-                     "l2_hit_rate": pair_profile(step_kernel_name(sweep["tuning"]), "l2_hit_rate"),
-                     "l1_hit_rate": pair_profile(step_kernel_name(sweep["tuning"]), "l1_hit_rate")},
+        "config": {"workload": "3D plume: 128^3 particles, jitter 0.1 dp, Wendland C4, h = 2 dp (support 4 dp), "
+                               "alpha_L 1e-2, alpha_T 1e-3, D_m 1e-6, v = (1, 0, 0), FP32 state, explicit Euler, "
+                               "dt 5e-5, graph-replayed steps",
+                   "particles": s3.n, "interactions_per_step": inter3,
+                   "neighbours_mean": inter3 / s3.n, "cells": h["cells"], "tuning": h["tuning"]},
+        "roofline": h["roofline"],
         "extras": extras,
     }
     if not args.no_cpu:
         print("[bench] cpu baseline ...", file=sys.stderr, flush=True)
-        line["cpu_baseline"] = cpu_baseline(cells)
+        line["cpu_baseline"] = cpu_baseline_3d(inter3)
     print(json.dumps(line))
 
 

@@ -41,8 +41,9 @@ struct PlumeDev {
     double ehat[3];         // unit flow direction e (x axis when |v| = 0)
     double pad3;
     // pair-term constants as the pair kernel uses them: Hu^2, 1/Hu, 5/Hu,
-    // A0, A1, E_x, E_y, E_z with A = A0 + A1 (E . x / r)^2; in 2D A1 is folded
-    // into E (A1 = 1, E = sqrt|a1| e, or its normal when a1 < 0)
+    // A0, S, E_x, E_y, E_z with the bracket A = A0 + S (E . x / r)^2,
+    // E = sqrt|a1| e, S = sign of a1 (in 2D always +1: a negative a1 is
+    // folded into A0 and E normal to the flow)
     double dterm[8];
     float fterm[8];         // the same in FP32
     double trD;             // trace of D

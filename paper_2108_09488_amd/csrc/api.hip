@@ -228,24 +228,22 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
         d.a1 = gamma * (q.alpha_L - q.alpha_T) * sp;
         for (int c = 0; c < 3; ++c) d.ehat[c] = (sp > 0) ? ((c < pl.dim) ? q.v[c] / sp : 0.0) : (c == 0 ? 1.0 : 0.0);
         {
-            // 2D: a0 + a1 (e.n)^2 = A0 + (E.n)^2 with E = sqrt(a1) e, or, for
-            // a1 < 0 (with (e.n)^2 + (e_perp.n)^2 = 1), A0 = a0 + a1 and
-            // E = sqrt(-a1) e_perp
-            double A0 = d.a0, A1 = d.a1, E[3] = {d.ehat[0], d.ehat[1], d.ehat[2]};
-            if (pl.dim == 2) {
-                const double sa = std::sqrt(std::fabs(d.a1));
-                if (d.a1 >= 0) {
-                    E[0] = sa * d.ehat[0];
-                    E[1] = sa * d.ehat[1];
-                } else {
+            // the bracket a0 + a1 (e.n)^2 as A0 + S (E.n)^2, S = +-1, with
+            // E = sqrt|a1| e; in 2D a negative a1 is turned into S = +1 by
+            // (e.n)^2 + (e_perp.n)^2 = 1: A0 = a0 + a1, E = sqrt(-a1) e_perp
+            const double sa = std::sqrt(std::fabs(d.a1));
+            double A0 = d.a0, S = 1.0, E[3] = {sa * d.ehat[0], sa * d.ehat[1], sa * d.ehat[2]};
+            if (d.a1 < 0) {
+                if (pl.dim == 2) {
                     A0 = d.a0 + d.a1;
                     E[0] = -sa * d.ehat[1];
                     E[1] = sa * d.ehat[0];
+                } else {
+                    S = -1.0;
                 }
-                E[2] = 0.0;
-                A1 = 1.0;
             }
-            const double t[8] = {Hu * Hu, 1.0 / Hu, 5.0 / Hu, A0, A1, E[0], E[1], E[2]};
+            if (pl.dim == 2) E[2] = 0.0;
+            const double t[8] = {Hu * Hu, 1.0 / Hu, 5.0 / Hu, A0, S, E[0], E[1], E[2]};
             for (int k = 0; k < 8; ++k) {
                 d.dterm[k] = t[k];
                 d.fterm[k] = (float)t[k];

@@ -10,11 +10,13 @@
 //     C2: W'(r)/r = -20 (B / H^2) (1 - q)^3,        q = r / H.
 // With D from Eq. (3) the bracket is a0 + a1 (e . x_ab / r)^2, e = v / |v|,
 // a0 = (Gamma - d)(alpha_T |v| + D_m) - (alpha_L - alpha_T)|v| and
-// a1 = Gamma (alpha_L - alpha_T)|v| (in 2D a1 is folded into e, see
-// PlumeDev::dterm).  Separations are taken in grid units
-// (L / 2^32) from the fixed-point positions; the bracket is scale free and
-// the constant factor V (W'(r)/r)/f(q) is applied once per particle
-// (PlumeDev::vphi).
+// a1 = Gamma (alpha_L - alpha_T)|v|; |a1| is folded into the direction,
+// E = sqrt|a1| e, so that the bracket is A0 +- (E . x_ab / r)^2 (see
+// PlumeDev::dterm).  Separations are taken in grid units (L / 2^32) from the
+// fixed-point positions; the bracket is scale free and the constant factor
+// V (W'(r)/r)/f(q) is applied once per particle (PlumeDev::vphi).  For C4
+// the kernel factor is evaluated as w^4 (w - 5/6 w^2) = (1 - q)^5 (1 + 5q) / 6
+// (w = 1 - q), the 6 going with that constant factor.
 //
 // Neighbour predicate (shared with the neighbour-list export): d = (int32)
 // (u_a - u_b) per component (the two's-complement wrap is the minimum image),
@@ -43,9 +45,15 @@ namespace ade {
 // kept only inside the support.  Outside it, and for r2 = 0 where the
 // reciprocal square root is infinite, the discarded value may be anything;
 // it is never added.
+// the constant the kernel factor of the pair term leaves out: its value at q = 0
+template <int KERN>
+constexpr double kPolyScale = (KERN == 4) ? 6.0 : 1.0;
+
+// the bracket is A0 + S (E . x / r)^2 with S = +-1 (PlumeDev::dterm; in 2D
+// S = +1 always)
 template <int DIM, typename real, int KERN>
 struct PairTerm {
-    real H2, invHu, invHu5, a0, a1, ex, ey, ez;
+    real H2, invHu, a0, sgn, ex, ey, ez;
     __device__ __forceinline__ void operator()(const Target& T, real Ca, uint32_t bx, uint32_t by,
                                                uint32_t bz, real Cb, real& acc) const {
         (*this)(T, Ca, bx, by, bz, Cb, true, acc);
@@ -71,9 +79,9 @@ struct PairTerm {
         // of a few ulps contributes a term below 1e-30 of the others)
         const real omq = fmar(-r, invHu, (real)1);
         real f;
-        if (KERN == 4) {
+        if (KERN == 4) {  // (1 - q)^5 (1 + 5q) / 6
             const real o2 = omq * omq;
-            f = o2 * o2 * omq * fmar(r, invHu5, (real)1);
+            f = (o2 * o2) * fmar((real)(-5.0 / 6.0), o2, omq);
         } else {
             f = omq * omq * omq;
         }
@@ -81,7 +89,7 @@ struct PairTerm {
         p = fmar(ey, dy, p);
         if (DIM == 3) p = fmar(ez, dz, p);
         const real pr = p * rinv;
-        const real A = (DIM == 2) ? fmar(pr, pr, a0) : fmar(a1 * pr, pr, a0);  // 2D: a1 folded into e
+        const real A = (DIM == 2) ? fmar(pr, pr, a0) : fmar(sgn * pr, pr, a0);
         const real w = inside ? A * f : (real)0;
         acc = fmar(w, Ca - Cb, acc);
     }
@@ -97,14 +105,14 @@ __device__ __forceinline__ PairTerm<DIM, real, KERN> make_term(const PlumeDev& P
     for (int k = 0; k < 8; ++k) c[k] = (sizeof(real) == 4) ? (real)P.fterm[k] : (real)P.dterm[k];
     t.H2 = c[0];
     t.invHu = c[1];
-    t.invHu5 = c[2];
     t.a0 = c[3];
-    t.a1 = c[4];
+    t.sgn = c[4];
     t.ex = c[5];
     t.ey = c[6];
     t.ez = c[7];
     return t;
 }
+
 
 template <typename real>
 struct Cand {
@@ -124,8 +132,8 @@ __device__ __forceinline__ Cand<real> unpack(const uint4& r) {
 // which the predicate rejects (r2 = 0).  So every load is unconditional, and
 // the loads of one batch stay in flight, in order, while the previous batch
 // is evaluated.
-template <int DIM, typename real, int KERN, int LANES, typename Fetch>
-__device__ __forceinline__ void walk_list(const PairTerm<DIM, real, KERN>& term, const Target& T,
+template <int LANES, typename Term, typename real, typename Fetch>
+__device__ __forceinline__ void walk_list(const Term& term, const Target& T,
                                           real Ca, uint32_t self, const uint2* list, uint32_t stride,
                                           uint32_t total, uint32_t lj, Fetch&& fetch, real& acc) {
     constexpr int B = Batch<LANES>::value;
@@ -186,15 +194,16 @@ __device__ __forceinline__ void walk_list(const PairTerm<DIM, real, KERN>& term,
 // (vphi * acc) in id order; half mode the half-step concentration (and its
 // candidate record); step mode updates C and x and hashes the moved particle
 // into the next build's cell counts.
-template <int DIM, typename real, int MODE>
+template <int DIM, typename real, int KERN, int MODE>
 __device__ __forceinline__ void finish_target(const PairLaunch& a, const PlumeDev& P, const Target& T, uint32_t i,
                                               real acc) {
     constexpr bool kRec = Rec<DIM, real>::kStageable;
+    constexpr double kS = kPolyScale<KERN>;
     if (MODE == kModeRhs) {
-        static_cast<real*>(a.out)[a.sid[i]] = (real)P.vphi * acc;
+        static_cast<real*>(a.out)[a.sid[i]] = (real)(kS * P.vphi) * acc;
         return;
     }
-    const real sc = (real)(a.scale * P.dt * P.vphi);
+    const real sc = (real)(a.scale * P.dt * P.vphi * kS);
     const real Cb = static_cast<const real*>(a.Cbase)[i];
     if (MODE == kModeHalf) {
         const real Ch = fmar(sc, acc, Cb);
@@ -250,36 +259,37 @@ __device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* _
 
     const Target T = make_target<DIM>(P, px[i], py[i], (DIM == 3) ? pz[i] : 0u);
     const real Ca = Cp[i];
-    const PairTerm<DIM, real, KERN> term = make_term<DIM, real, KERN>(P);
     real acc = (real)0;
 
-    // every lane of a target writes the same list (no cross-lane hand-over)
+    // the lanes of a target list its rows together (build_list)
     uint2* list = lds_list + lt;
     uint32_t total = 0;
     if (active) total = build_list<DIM, LANES>(P, a.cell_start, T, list, tpb);
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
-    if (kRec)
-        walk_list<DIM, real, KERN, LANES>(term, T, Ca, i, list, tpb, total, lj,
-                                          [&](uint32_t k) {
-                                              // 32-bit byte offset from a uniform base
-                                              return unpack<DIM, real>(*reinterpret_cast<const uint4*>(
-                                                  reinterpret_cast<const char*>(rec) + k));
-                                          },
-                                          acc);
-    else
-        walk_list<DIM, real, KERN, LANES>(
-            term, T, Ca, i, list, tpb, total, lj,
-            [&](uint32_t k) {
-                k /= kRecBytes;
-                return Cand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, Cp[k]};
-            },
-            acc);
+    auto walk = [&](const auto& term) {
+        if (kRec)
+            walk_list<LANES>(term, T, Ca, i, list, tpb, total, lj,
+                             [&](uint32_t k) {
+                                 // 32-bit byte offset from a uniform base
+                                 return unpack<DIM, real>(*reinterpret_cast<const uint4*>(
+                                     reinterpret_cast<const char*>(rec) + k));
+                             },
+                             acc);
+        else
+            walk_list<LANES>(term, T, Ca, i, list, tpb, total, lj,
+                             [&](uint32_t k) {
+                                 k /= kRecBytes;
+                                 return Cand<real>{px[k], py[k], (DIM == 3) ? pz[k] : 0u, Cp[k]};
+                             },
+                             acc);
+    };
+    walk(make_term<DIM, real, KERN>(P));
 
     // wavefront reduction over the lanes of a target (fixed order: deterministic)
     if (LANES >= 2) acc += __shfl_xor(acc, 1, kWave);
     if (LANES >= 4) acc += __shfl_xor(acc, 2, kWave);
     if (!active || lj != 0) return;
-    finish_target<DIM, real, MODE>(a, P, T, i, acc);
+    finish_target<DIM, real, KERN, MODE>(a, P, T, i, acc);
 }
 
 // ---------------------------------------------------------------------------
@@ -400,8 +410,8 @@ __device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_
 // more rounding, which can move a candidate across r = H only within a
 // rounding of it, where its term is below 1e-35 of a typical one (the
 // neighbour-set export keeps the exact predicate).
-template <int DIM, typename real, int KERN, typename Fetch>
-__device__ __forceinline__ void walk_pair(const PairTerm<DIM, real, KERN>& term, const Target& TA, const Target& TB,
+template <int DIM, typename Term, typename real, typename Fetch>
+__device__ __forceinline__ void walk_pair(const Term& term, const Target& TA, const Target& TB,
                                           real CA, real CB, uint32_t self, const uint2* list, uint32_t stride,
                                           uint32_t total, Fetch&& fetch, real& accA, real& accB) {
     const real bx = (real)(int32_t)(TB.ux - TA.ux);
@@ -451,7 +461,6 @@ __device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* 
     const Target TA = make_target<DIM>(P, px[iA], py[iA], (DIM == 3) ? pz[iA] : 0u);
     const Target TB = make_target<DIM>(P, px[iB], py[iB], (DIM == 3) ? pz[iB] : 0u);
     const real CA = Cp[iA], CB = Cp[iB];
-    const PairTerm<DIM, real, KERN> term = make_term<DIM, real, KERN>(P);
     real accA = (real)0, accB = (real)0;
 
     uint2* list = lds_list + threadIdx.x;
@@ -461,9 +470,10 @@ __device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* 
     if (merged) total = build_union<DIM>(P, a.cell_start, TA, TB, dy, dz, list, stride);
     else if (actA) total = build_list<DIM, 1>(P, a.cell_start, TA, list, stride);
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
-    walk_pair<DIM, real, KERN>(term, TA, TB, CA, CB, iA, list, stride, total, fetch, accA, accB);
-    if (actA) finish_target<DIM, real, MODE>(a, P, TA, iA, accA);
-    if (merged) finish_target<DIM, real, MODE>(a, P, TB, iB, accB);
+    const PairTerm<DIM, real, KERN> term = make_term<DIM, real, KERN>(P);
+    walk_pair<DIM>(term, TA, TB, CA, CB, iA, list, stride, total, fetch, accA, accB);
+    if (actA) finish_target<DIM, real, KERN, MODE>(a, P, TA, iA, accA);
+    if (merged) finish_target<DIM, real, KERN, MODE>(a, P, TB, iB, accB);
 
     // b of a pair that could not be merged walks its own list (a second walk
     // that only wavefronts holding such a pair enter)
@@ -475,8 +485,8 @@ __device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* 
     if (alone) total2 = build_list<DIM, 1>(P, a.cell_start, T2, list, stride);
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
     real acc2 = (real)0;
-    walk_list<DIM, real, KERN, 1>(term, T2, C2, iB, list, stride, total2, 0u, fetch, acc2);
-    if (alone) finish_target<DIM, real, MODE>(a, P, T2, iB, acc2);
+    walk_list<1>(term, T2, C2, iB, list, stride, total2, 0u, fetch, acc2);
+    if (alone) finish_target<DIM, real, KERN, MODE>(a, P, T2, iB, acc2);
 }
 
 // Eight wavefronts per SIMD for the FP32 kernels: at most 64 VGPRs and 100

@@ -29,6 +29,7 @@ FLOWS = [  # (dim, real_bytes, v, alpha_L, alpha_T, D_m)
     (2, 4, (-0.28, 0.96, 0.0), 2e-2, 2e-3, 0.0),
     (3, 4, (0.0, 0.0, 0.0), 1e-2, 1e-3, 1e-6),
     (3, 8, (0.48, 0.6, 0.64), 1e-3, 1e-2, 1e-6),
+    (3, 4, (0.48, -0.6, 0.64), 2e-3, 3e-2, 1e-6),
 ]
 
 
