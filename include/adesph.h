@@ -164,8 +164,12 @@ int ade_init_particles(ade_ctx *ctx, const double *d_x, const void *d_C);
  * the predictor moves it to x + rint((k + 1/2) u_a) - rint(k u_a), the cells
  * are rebuilt there for the corrector, and the corrector completes the step.
  * The pair sum
- * runs four lanes per target with a fixed launch shape; ade_set_tuning and
- * ade_autotune return ADE_EINVAL for such a context.  ade_adjoint takes it
+ * takes the launch shapes block {64, 128, 256} x lanes {1, 2, 4} (one target
+ * per group of lanes, no persistent grid; a new context starts with 4 lanes
+ * in the largest block whose lists fit), through ade_set_tuning or
+ * ade_autotune.  A 2D FP32 velocity-field context holds at most 2^27 - 256
+ * particles (its 32-byte candidate records take 32-bit byte offsets).
+ * ade_adjoint takes it
  * (Euler or ADE_PC): its checkpoints then hold the velocities and tensors
  * too, the recompute keeps every step's half-step state for the
  * predictor-corrector, and the gradient differentiates every pair's

@@ -272,7 +272,10 @@ class ADEMisfit(torch.autograd.Function):
     problem: dict with keys spec (PlumeSpec of the plume), x0 (float64 (dim, N)
     positions), C0 (initial concentrations), xs (float64 (dim, S) sensor
     points), obs (S observations), nsteps, ckpt_every, and optionally device.
-    The forward pass runs the adjoint too and keeps the gradient for backward.
+    When theta requires a gradient the forward pass runs the adjoint (forward,
+    recompute and reverse sweep) and keeps the gradient for backward;
+    otherwise it only steps the plume and interpolates at the sensors.  The
+    gradient comes back on theta's device and in its dtype.
     """
 
     @staticmethod
@@ -283,17 +286,26 @@ class ADEMisfit(torch.autograd.Function):
         spec.alpha_L, spec.alpha_T, spec.D_m = float(th[0]), float(th[1]), float(th[2])
         dev = problem.get("device", "cuda:0")
         x0 = torch.as_tensor(problem["x0"], dtype=torch.float64)
+        xs = torch.as_tensor(problem["xs"], dtype=torch.float64)
+        obs = torch.as_tensor(problem["obs"])
         c = Context([params_from_spec(spec)], [x0.shape[1]], device=dev)
         try:
             c.init(x0, torch.as_tensor(problem["C0"])).build()
-            J, g = c.adjoint(problem["nsteps"], problem["ckpt_every"], torch.as_tensor(problem["xs"]),
-                             torch.as_tensor(problem["obs"]))
+            if ctx.needs_input_grad[0]:
+                J, g = c.adjoint(problem["nsteps"], problem["ckpt_every"], xs, obs)
+            else:
+                c.step(problem["nsteps"])
+                Cs = c.sensor_interp(xs).double()
+                J = float(((Cs - obs.to(Cs.device, torch.float64)) ** 2).sum().item())
+                g = [0.0, 0.0, 0.0]
         finally:
             c.close()
         ctx.save_for_backward(torch.tensor(g, dtype=torch.float64))
-        return torch.tensor(J, dtype=torch.float64)
+        ctx.theta_meta = (theta.device, theta.dtype)
+        return torch.tensor(J, dtype=torch.float64, device=theta.device)
 
     @staticmethod
     def backward(ctx, gJ):
         (g,) = ctx.saved_tensors
-        return gJ * g.to(gJ.device), None
+        dev, dt = ctx.theta_meta
+        return (gJ.to(dev, torch.float64) * g.to(dev)).to(dt), None

@@ -154,6 +154,7 @@ struct GenLaunch {
     uint32_t ntiles;
     int list_cap;
     int lanes;              // lanes per target particle: 1, 2 or 4
+    int block;              // threads per workgroup: 64, 128 or 256 (its lists fit in LDS)
     StateArrays S, U;
     const uint32_t* cell_start;
     CellLists lists;

@@ -41,6 +41,15 @@ int tuning_list_cap(const Plan& pl, const ade_tuning& t) {
     return targets_of(t) == 2 ? std::max(pl.list_cap_pair, pl.list_cap) : pl.list_cap;
 }
 
+// launch shapes of the velocity-field kernel: one target per group of
+// lanes, no persistent grid
+bool gen_tuning_fits(const Plan& pl, const ade_tuning& t) {
+    if (t.block != 64 && t.block != 128 && t.block != 256) return false;
+    if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4) return false;
+    if (t.targets > 1 || t.persistent != 0) return false;
+    return (size_t)(t.block / t.lanes) * (size_t)pl.list_cap * 8u <= kPairLdsMax;
+}
+
 bool tuning_fits(const Plan& pl, const ade_tuning& t) {
     if (t.block != 64 && t.block != 128 && t.block != 256) return false;
     if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4) return false;
@@ -550,9 +559,8 @@ GenLaunch gen_args(ade_ctx* c, void* out) {
     g.tiles = c->pair_tiles;
     g.ntiles = c->plan.ntiles;
     g.list_cap = c->plan.list_cap;
-    // four lanes per target: on the 512^2 plume 49-51 us per update launch,
-    // against 52-53 (two lanes) and 54-56 (one)
-    g.lanes = 4;
+    g.lanes = c->tuning.lanes;
+    g.block = c->tuning.block;
     g.S = c->S;
     g.U = c->U;
     g.cell_start = c->cell_start;
@@ -636,6 +644,11 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
         delete c;
         return fail(ADE_EINVAL, "too many neighbour rows: the candidate lists do not fit in LDS");
     }
+    // its 32-byte candidate records (2D FP32) are addressed with 32-bit byte offsets
+    if (c->plan.general && c->plan.dim == 2 && c->plan.real_bytes == 4 && c->plan.N > 0x07ffff00) {
+        delete c;
+        return fail(ADE_EINVAL, "a 2D FP32 velocity-field context holds at most 2^27 - 256 particles");
+    }
     // default launch shape: the fewest lanes per particle that still give
     // the chip about 4 wavefronts per SIMD (4096 wavefronts of 64 lanes, i.e.
     // 2^18 lanes): two targets per lane from 2^19 particles on (the fastest
@@ -664,6 +677,11 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
             delete c;
             return fail(ADE_EINVAL, "too many neighbour rows: the candidate lists do not fit in LDS");
         }
+        // a velocity field: four lanes per target in the largest workgroup
+        // whose lists fit (its autotuner may choose otherwise)
+        if (c->plan.general)
+            for (int bb : {64, 128, 256})
+                if (gen_tuning_fits(c->plan, ade_tuning{bb, 4, 0, 0, 1})) c->tuning = ade_tuning{bb, 4, 0, 0, 1};
     }
     Bump b(d_ws);
     layout(b, c, c->plan);
@@ -881,11 +899,66 @@ static int clear_counts(ade_ctx* c) {
     return ADE_OK;
 }
 
+// The velocity-field kernel's autotuner: block x lanes, the step-mode kernel
+// timed as ade_autotune times the uniform-flow one.
+static int autotune_gen(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
+    const Plan& pl = c->plan;
+    const ade_tuning start = c->tuning;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    float best_ms = 0.f;
+    ade_tuning best_t = start;
+    bool have = false;
+    int rc = ADE_OK;
+    for (int lb : {1, 2, 4}) {
+        if ((flags & ADE_TUNE_KEEP_LANES) && lb != start.lanes) continue;
+        for (int bb : {64, 128, 256}) {
+            const ade_tuning cand{bb, lb, 0, 0, 1};
+            if (!gen_tuning_fits(pl, cand)) continue;
+            c->tuning = cand;
+            GenLaunch g = gen_args(c, nullptr);
+            g.ev0 = e0;
+            g.ev1 = e1;
+            float ms = 0.f;
+            for (int r = 0; r <= reps && !rc; ++r) {  // r = 0: warm-up
+                if (launch_pair_gen(pl.dim, pl.real_bytes, pl.kernel, kModeStep, g, c->stream) != hipSuccess ||
+                    (rc = clear_counts(c)) != ADE_OK) {
+                    if (!rc) rc = fail(ADE_EHIP, "autotune launch");
+                    break;
+                }
+                float one = 0.f;
+                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&one, e0, e1) != hipSuccess) {
+                    rc = fail(ADE_EHIP, "event synchronise");
+                    break;
+                }
+                if (r > 0) ms += one;
+            }
+            if (rc) break;
+            if (!have || ms < best_ms) {
+                best_ms = ms;
+                best_t = cand;
+                have = true;
+            }
+        }
+        if (rc) break;
+    }
+    const int rc_clear = clear_counts(c);
+    if (!rc) rc = rc_clear;
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    c->tuning = rc ? start : best_t;
+    drop_graph(c);
+    if (rc) return rc;
+    if (best) *best = best_t;
+    return ADE_OK;
+}
+
 int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     if (!c) return fail(ADE_EINVAL, "null ctx");
     if (reps < 1) return fail(ADE_EINVAL, "reps must be positive");
     if (!c->built) return fail(ADE_ESTATE, "ade_autotune before ade_build_cells");
-    if (c->plan.general) return fail(ADE_EINVAL, "a velocity-field context has a fixed launch shape");
+    if (c->plan.general) return autotune_gen(c, reps, flags, best);
     const Plan& pl = c->plan;
     const ade_tuning start = c->tuning;
     hipEvent_t e0, e1;
@@ -952,7 +1025,15 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
 
 int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
     if (!c || !t) return fail(ADE_EINVAL, "null argument");
-    if (c->plan.general) return fail(ADE_EINVAL, "a velocity-field context has a fixed launch shape");
+    if (c->plan.general) {
+        if (!gen_tuning_fits(c->plan, *t))
+            return fail(ADE_EINVAL, "a velocity-field context takes block 64, 128 or 256, lanes 1, 2 or 4, one "
+                                    "target per lane group, no persistent grid, and lists that fit in LDS");
+        c->tuning = *t;
+        c->tuning.targets = 1;
+        drop_graph(c);
+        return ADE_OK;
+    }
     if (t->block != 64 && t->block != 128 && t->block != 256)
         return fail(ADE_EINVAL, "block must be 64, 128 or 256");
     if (t->lanes != 1 && t->lanes != 2 && t->lanes != 4) return fail(ADE_EINVAL, "lanes must be 1, 2 or 4");

@@ -107,7 +107,10 @@ template <int DIM, typename real>
 __device__ __forceinline__ GPart<DIM, real> load_part(const StateArrays& S, uint32_t k) {
     GPart<DIM, real> p;
     if constexpr (DIM == 2 && sizeof(real) == 4) {
-        const uint4 a = S.grec[2 * (size_t)k], b = S.grec[2 * (size_t)k + 1];
+        // 32-bit byte offset from a uniform base (a velocity-field context in
+        // 2D FP32 holds fewer than 2^27 particles)
+        const char* base = reinterpret_cast<const char*>(S.grec) + (k << 5);
+        const uint4 a = *reinterpret_cast<const uint4*>(base), b = *reinterpret_cast<const uint4*>(base + 16);
         p.x = a.x;
         p.y = a.y;
         p.z = 0u;
@@ -202,9 +205,8 @@ __device__ __forceinline__ void walk_lanes(const uint2* list, uint32_t stride, u
     }
 }
 
-// A work item = blockDim.x / LANES consecutive targets of one tile (a
-// divisor of the tile, chosen so the candidate lists fit in LDS), LANES lanes
-// per target.
+// A work item = blockDim.x / LANES consecutive targets of one tile, LANES
+// lanes per target (the launch shape of the context's tuning).
 template <int DIM, typename real, int KERN, int MODE, int LANES>
 __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
     extern __shared__ uint2 lds_list[];
@@ -231,7 +233,7 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
     if (active) total = build_list<DIM, LANES>(P, g.cell_start, T, list, tpb);
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
 
-    const real H2 = h2_of<real>(P), invHu = (real)P.invHu;
+    const real invHu = (real)P.invHu;
     const real gam = (real)(DIM + 2);
     real disp = 0, conv = 0;
     auto fetch = [&](uint32_t k) { return load_part<DIM, real>(S, k / kRecBytes); };
@@ -239,37 +241,38 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
         const real dx = (real)(int32_t)(T.ux - c.x);
         const real dy = (real)(int32_t)(T.uy - c.y);
         const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - c.z) : (real)0;
-        real r2 = dx * dx;
-        r2 = fmar(dy, dy, r2);
+        const real dx2 = dx * dx, dy2 = dy * dy;
+        real r2 = dx2 + dy2;
         if (DIM == 3) r2 = fmar(dz, dz, r2);
-        const bool in = keep && r2 > (real)0 && r2 <= H2;
-        const real rinv = rsqrt_r(r2);
-        const real q = r2 * rinv * invHu;
-        real omq = (real)1 - q;
+        // the support is cut by the clamp of 1 - q at 0; r2 = 0 (the target
+        // itself, a padding slot, a coincident particle) by the select below.
+        // Two distinct positions are at least one grid unit apart, so the
+        // clamp of r2 at 1 changes nothing else and keeps every factor finite.
+        const bool in = keep && r2 > (real)0;
+        const real rinv = rsqrt_r(r2 > (real)1 ? r2 : (real)1);
+        real omq = fmar(-(r2 * rinv), invHu, (real)1);
         omq = omq > (real)0 ? omq : (real)0;
         real f;
-        if (KERN == 4) {
+        if (KERN == 4) {  // (1 - q)^5 (1 + 5q) / 6
             const real o2 = omq * omq;
-            f = o2 * o2 * omq * fmar((real)5, q, (real)1);
+            f = (o2 * o2) * fmar((real)(-5.0 / 6.0), o2, omq);
         } else {
             f = omq * omq * omq;
         }
-        // outside the support (and at r2 = 0) every factor below is finite
-        // and f = 0, so the terms vanish
         f = in ? f : (real)0;
-        const real ir2 = in ? rinv * rinv : (real)0;
+        const real ir2 = rinv * rinv;
         // the pair's harmonic-mean tensor h, divided by 4
         real quad, tr;
         if (DIM == 2) {
             const real hxx = hmean_diag(A.r[0], c.r[0]), hxy = hmean(A.r[1], c.r[1]);
             const real hyy = hmean_diag(A.r[2], c.r[2]);
-            quad = fmar(hxx * dx, dx, fmar((real)2 * hxy * dx, dy, hyy * dy * dy));
+            quad = fmar(hxx, dx2, fmar(hyy, dy2, (hxy + hxy) * (dx * dy)));
             tr = hxx + hyy;
         } else {
             const real hxx = hmean_diag(A.r[0], c.r[0]), hxy = hmean(A.r[1], c.r[1]), hxz = hmean(A.r[2], c.r[2]);
             const real hyy = hmean_diag(A.r[3], c.r[3]), hyz = hmean(A.r[4], c.r[4]);
             const real hzz = hmean_diag(A.r[5], c.r[5]);
-            quad = hxx * dx * dx + hyy * dy * dy + hzz * dz * dz +
+            quad = hxx * dx2 + hyy * dy2 + hzz * dz * dz +
                    (real)2 * (hxy * dx * dy + hxz * dx * dz + hyz * dy * dz);
             tr = hxx + hyy + hzz;
         }
@@ -293,8 +296,10 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
     if (!active || lj != 0) return;
 
     // 1/2 of the sum of Dcal terms = 2 disp (disp sums Dcal / 4); x_ab of the
-    // convective term is in grid units, L / 2^32 each
-    const real rhs = (real)P.vphi * fmar(A.C * (real)(P.L * (1.0 / 4294967296.0)), conv, (real)2 * disp);
+    // convective term is in grid units, L / 2^32 each; the kernel factor f
+    // left out its value at q = 0 (6 for C4)
+    constexpr double kS = (KERN == 4) ? 6.0 : 1.0;
+    const real rhs = (real)(kS * P.vphi) * fmar(A.C * (real)(P.L * (1.0 / 4294967296.0)), conv, (real)2 * disp);
     if (MODE == kModeRhs) {
         static_cast<real*>(g.out)[S.id[i]] = rhs;
         return;
@@ -566,8 +571,8 @@ hipError_t launch_setvel(int dim, int real_bytes, const PlumeDev* plumes, const 
 
 template <int DIM, typename real, int KERN, int LANES>
 static hipError_t launch_gen_l(int mode, const GenLaunch& g, hipStream_t s) {
-    uint32_t block = 256;  // the largest workgroup whose lists fit in LDS
-    while (block > 64 && (size_t)(block / LANES) * (size_t)g.list_cap * 8u > kPairLdsMax) block /= 2;
+    const uint32_t block = (uint32_t)g.block;
+    if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
     const size_t shm = (size_t)(block / LANES) * (size_t)g.list_cap * 8u;
     if (shm > kPairLdsMax) return hipErrorInvalidValue;
     if (DIM == 2 && sizeof(real) == 4 && !g.S.grec) return hipErrorInvalidValue;

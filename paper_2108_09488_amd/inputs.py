@@ -251,6 +251,12 @@ def config(name: str, **over) -> PlumeSpec:
         s = PlumeSpec(dim=2, n_side=side, L=2000.0, jitter=0.1, h_over_dp=HL * side / 2.0, kernel=4,
                       alpha_L=10.0, alpha_T=10.0 / ratio, D_m=0.0, v=(vv, vv, 0.0), sigma0=44.0,
                       centre=(1000.0, 1000.0, 1000.0), real_bytes=4, name=name)
+        # Eq. (10) with the smoothing length H/2, as for every problem here.
+        # With the table's h (the support radius H) the step would be 4x
+        # longer, beyond the 300-day run, and unstable: on a 150^2 lattice of
+        # the same H/L the operator's most negative eigenvalue gives
+        # dt lambda = -2.5, an amplification of 1.5 (Euler) and 1.6
+        # (predictor-corrector) per step.
         s.dt = eq10_dt(s)
         s.steps = int(math.ceil(300 * 86400.0 / s.dt))
     elif name == "cfg5":

@@ -111,6 +111,16 @@ def test_adjoint_dm_identity_and_autograd():
     g = theta.grad.numpy()
     assert np.isfinite(J.item()) and J.item() > 0
     assert g[2] == pytest.approx((g[0] + g[1]) / np.linalg.norm(spec.velocity()), rel=1e-4)
+    # theta on the GPU in FP32: the gradient comes back there, in FP32
+    th = torch.tensor([1e-2, 5e-3, 1e-6], dtype=torch.float32, device="cuda", requires_grad=True)
+    J2 = ADEMisfit.apply(th, prob)
+    J2.backward()
+    assert th.grad.device == th.device and th.grad.dtype == torch.float32
+    assert np.allclose(th.grad.cpu().numpy(), g, rtol=1e-3)
+    # without a gradient the forward pass alone gives the same misfit
+    with torch.no_grad():
+        J3 = ADEMisfit.apply(theta.detach(), prob)
+    assert J3.item() == pytest.approx(J.item(), rel=1e-6)
 
 
 @pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden adjoint values not generated")

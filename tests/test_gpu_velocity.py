@@ -362,13 +362,45 @@ def test_velocity_field_validation():
     with pytest.raises(_lib.AdeError) as e:  # after build
         ctx.set_velocities(v)
     assert e.value.code == _lib.ADE_ESTATE
-    for call in (lambda: ctx.set_tuning(), lambda: ctx.autotune()):
+    # launch shapes: one target per group of lanes, no persistent grid
+    for bad in (dict(block=128, lanes=1, targets=2), dict(block=256, lanes=4, persistent=64),
+                dict(block=96, lanes=4)):
         with pytest.raises(_lib.AdeError) as e:
-            call()
+            ctx.set_tuning(**bad)
         assert e.value.code == _lib.ADE_EINVAL
+    ctx.set_tuning(block=128, lanes=2)
+    assert (ctx.get_tuning()["block"], ctx.get_tuning()["lanes"]) == (128, 2)
+    t = ctx.autotune(reps=1)
+    assert t["lanes"] in (1, 2, 4) and t["targets"] == 1 and t["persistent"] == 0
     # init clears the velocities: build needs them again
     ctx.init(torch.from_numpy(x), torch.from_numpy(C))
     with pytest.raises(_lib.AdeError) as e:
         ctx.build()
     assert e.value.code == _lib.ADE_ESTATE
     ctx.close()
+
+
+def test_velocity_field_launch_shapes():
+    """Every launch shape of the velocity-field kernel gives the oracle's
+    right-hand side (FP32 1e-5, FP64 1e-12), and the same bits for the same
+    lanes per target whatever the workgroup size."""
+    for dim, rb, n_side in [(2, 4, 80), (2, 8, 48), (3, 4, 18)]:
+        spec = _spec(dim, rb, n_side, 4, 1.5)
+        v = _field(spec, quantise=False)
+        ctx, x, C = _ctx(spec, v)
+        r = O.rhs(O.model_from_spec(spec), x, C, v=v, mass=spec.mass, rho=spec.rho0)
+        by_lanes = {}
+        for lanes in (1, 2, 4):
+            for block in (64, 128, 256):
+                try:
+                    ctx.set_tuning(block=block, lanes=lanes)
+                except _lib.AdeError:
+                    continue  # lists do not fit in LDS at this shape
+                g = ctx.rhs().cpu().numpy()
+                assert _rel(g.astype(np.float64), r) < (1e-12 if rb == 8 else 1e-5), (dim, rb, block, lanes)
+                if lanes in by_lanes:
+                    assert np.array_equal(g, by_lanes[lanes]), (dim, rb, block, lanes)
+                else:
+                    by_lanes[lanes] = g
+        assert len(by_lanes) == 3
+        ctx.close()
