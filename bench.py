@@ -246,8 +246,8 @@ def roofline_alu(dim, interactions, ms_per_launch, kernel, launches, profile=Non
     algorithmic flops of one launch (the interactions it evaluates times the
     flops of one) over its mean HIP-event duration, against the published
     FP32 vector peak; with the single-issue VALU fraction and, while the
-    kernel sources match a committed counter profile, its HBM bytes and cache
-    hit rates."""
+    kernel sources match a committed counter profile, its HBM bytes, cache
+    hit rates and the share of the VALU issue slots it kept busy."""
     fpi = FLOPS_PER_INTERACTION_FIELD[dim] if field else FLOPS_PER_INTERACTION[dim]
     achieved = fpi * interactions / (ms_per_launch * 1e-3) / 1e12
     out = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
@@ -260,6 +260,8 @@ def roofline_alu(dim, interactions, ms_per_launch, kernel, launches, profile=Non
     if profile:
         out["l2_hit_rate"] = pair_profile(kernel, "l2_hit_rate", profile)
         out["l1_hit_rate"] = pair_profile(kernel, "l1_hit_rate", profile)
+        # measured share of the VALU issue slots the kernel used (counter run)
+        out["valu_slot_util"] = pair_profile(kernel, "valu_slot_util", profile)
     return out
 
 

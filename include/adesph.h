@@ -143,7 +143,11 @@ int ade_workspace_bytes(const ade_params *params, const int64_t *counts, int32_t
  * hipStream_t (NULL: the default stream).  *out receives the context.  A
  * context holds at most 2^28 - 256 particles in total (candidate records are
  * addressed with 32-bit byte offsets); larger ensembles take several
- * contexts. */
+ * contexts.  A plume of a multi-plume context evolves bit for bit as it does
+ * alone when both runs have the same cell grid (cell_rows, and cell_xsub
+ * where the context's cell tables would pass the 160 MiB budget, since the
+ * default x cells then widen for the whole context) and the same lanes and
+ * targets: the grid fixes the candidate order of every sum. */
 int ade_create(const ade_params *params, const int64_t *counts, int32_t nplumes, void *d_ws,
                size_t ws_bytes, void *stream, ade_ctx **out);
 
