@@ -14,6 +14,11 @@ __device__ __forceinline__ double fmar(double a, double b, double c) { return __
 __device__ __forceinline__ float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
 
+// x clamped to [0, 1] (NaN to 0): for FP32 the clamp bit of the instruction
+// that forms x
+__device__ __forceinline__ float clamp_unit(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+__device__ __forceinline__ double clamp_unit(double x) { return x > 0.0 ? (x < 1.0 ? x : 1.0) : 0.0; }
+
 template <typename real>
 __device__ __forceinline__ real h2_of(const PlumeDev& P) {
     return sizeof(real) == 4 ? (real)P.H2f : (real)P.H2d;

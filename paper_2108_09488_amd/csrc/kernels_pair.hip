@@ -50,10 +50,11 @@ template <int KERN>
 constexpr double kPolyScale = (KERN == 4) ? 6.0 : 1.0;
 
 // the bracket is A0 + S (E . x / r)^2 with S = +-1 (PlumeDev::dterm; in 2D
-// S = +1 always)
+// S = +1 always).  The term forms S times it, (E . x / r)^2 + S A0, and
+// finish_target multiplies the sum by S.
 template <int DIM, typename real, int KERN>
 struct PairTerm {
-    real H2, invHu, a0, sgn, ex, ey, ez;
+    real invHu, a0s, ex, ey, ez;
     __device__ __forceinline__ void operator()(const Target& T, real Ca, uint32_t bx, uint32_t by,
                                                uint32_t bz, real Cb, real& acc) const {
         (*this)(T, Ca, bx, by, bz, Cb, true, acc);
@@ -72,12 +73,15 @@ struct PairTerm {
         real r2 = dx * dx;
         r2 = fmar(dy, dy, r2);
         if (DIM == 3) r2 = fmar(dz, dz, r2);
-        const bool inside = keep && r2 > (real)0 && r2 <= H2;
+        // r2 = 0 (the target itself, a padding slot, a coincident particle)
+        // is cut by the select below; the support r <= H by the clamp of
+        // 1 - q at 0, which zeroes the kernel factor outside it (W is 0 at
+        // q = 1, so where the rounding of r puts 1 - q on the other side of 0
+        // the term is below 1e-28 of a typical one either way)
+        const bool inside = keep && r2 > (real)0;
         const real rinv = rsqrt_r(r2);
         const real r = r2 * rinv;
-        // 1 - q; inside the support up to the rounding of r (a negative value
-        // of a few ulps contributes a term below 1e-30 of the others)
-        const real omq = fmar(-r, invHu, (real)1);
+        const real omq = clamp_unit(fmar(-r, invHu, (real)1));
         real f;
         if (KERN == 4) {  // (1 - q)^5 (1 + 5q) / 6
             const real o2 = omq * omq;
@@ -89,7 +93,7 @@ struct PairTerm {
         p = fmar(ey, dy, p);
         if (DIM == 3) p = fmar(ez, dz, p);
         const real pr = p * rinv;
-        const real A = (DIM == 2) ? fmar(pr, pr, a0) : fmar(sgn * pr, pr, a0);
+        const real A = fmar(pr, pr, a0s);  // S times the bracket
         const real w = inside ? A * f : (real)0;
         acc = fmar(w, Ca - Cb, acc);
     }
@@ -103,10 +107,8 @@ __device__ __forceinline__ PairTerm<DIM, real, KERN> make_term(const PlumeDev& P
     real c[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) c[k] = (sizeof(real) == 4) ? (real)P.fterm[k] : (real)P.dterm[k];
-    t.H2 = c[0];
     t.invHu = c[1];
-    t.a0 = c[3];
-    t.sgn = c[4];
+    t.a0s = c[3] * c[4];
     t.ex = c[5];
     t.ey = c[6];
     t.ez = c[7];
@@ -138,11 +140,18 @@ __device__ __forceinline__ void walk_list(const Term& term, const Target& T,
                                           uint32_t total, uint32_t lj, Fetch&& fetch, real& acc) {
     constexpr int B = Batch<LANES>::value;
     // batches of the wavefront: the largest share of its lanes, in batches
-    uint32_t share = total > lj ? (total - lj + LANES - 1) / LANES : 0u;
+    const uint32_t own = total > lj ? (total - lj + LANES - 1) / LANES : 0u;
+    uint32_t share = own, least = own;
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
+        least = min(least, (uint32_t)__shfl_xor((int)least, o, kWave));
+    }
     const uint32_t nb = __builtin_amdgcn_readfirstlane((share + B - 1) / B);
     if (nb == 0) return;
+    // batches in which every lane of the wavefront still has records of its
+    // own: their slots need no end-of-list test
+    const uint32_t nfull = __builtin_amdgcn_readfirstlane(least / B);
 
     Cursor<LANES> cur;
     cur.b = lj * kRecBytes;
@@ -156,13 +165,24 @@ __device__ __forceinline__ void walk_list(const Term& term, const Target& T,
     // so both entries into the loop carry the same outstanding loads
     __builtin_amdgcn_s_waitcnt(0);
     Cand<real> c0[B], c1[B];
-    auto fill = [&](Cand<real>(&c)[B]) {
+    // fill batch `it`: past the full batches a slot beyond the lane's share
+    // re-reads the target's own record
+    auto fill = [&](Cand<real>(&c)[B], uint32_t it) {
         uint32_t idx[B];
+        if (it < nfull) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) {
-            idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
-            cur.b += Cursor<LANES>::kStep;
-            cur.settle();
+            for (int q = 0; q < B; ++q) {
+                idx[q] = cur.b;
+                cur.b += Cursor<LANES>::kStep;
+                cur.settle();
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
+                cur.b += Cursor<LANES>::kStep;
+                cur.settle();
+            }
         }
 #pragma unroll
         for (int q = 0; q < B; ++q) c[q] = fetch(idx[q]);
@@ -173,19 +193,19 @@ __device__ __forceinline__ void walk_list(const Term& term, const Target& T,
 #pragma unroll
         for (int q = 0; q < B; ++q) term(T, Ca, c[q].x, c[q].y, c[q].z, c[q].C, acc);
     };
-    fill(c0);
+    fill(c0, 0u);
     for (uint32_t it = 1;; it += 2) {
         if (it >= nb) {
             eval(c0);
             break;
         }
-        fill(c1);
+        fill(c1, it);
         eval(c0);
         if (it + 1 >= nb) {
             eval(c1);
             break;
         }
-        fill(c0);
+        fill(c0, it + 1);
         eval(c1);
     }
 }
@@ -198,7 +218,9 @@ template <int DIM, typename real, int KERN, int MODE>
 __device__ __forceinline__ void finish_target(const PairLaunch& a, const PlumeDev& P, const Target& T, uint32_t i,
                                               real acc) {
     constexpr bool kRec = Rec<DIM, real>::kStageable;
-    constexpr double kS = kPolyScale<KERN>;
+    // the kernel factor's constant and the bracket's sign S (the pair term
+    // sums S times the bracket)
+    const double kS = kPolyScale<KERN> * P.dterm[4];
     if (MODE == kModeRhs) {
         static_cast<real*>(a.out)[a.sid[i]] = (real)(kS * P.vphi) * acc;
         return;
