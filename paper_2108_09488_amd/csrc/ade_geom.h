@@ -59,42 +59,56 @@ __device__ __forceinline__ Target make_target(const PlumeDev& P, uint32_t ux, ui
     return t;
 }
 
-// Half-width w of the x window of a target in its neighbour row (oy, oz):
-// an upper bound of the chord of the search radius at the row's nearest
-// edge, or the search radius itself in the target's own row; false when the
-// row lies beyond the search radius.  The bound is conservative: the float
-// rounding of the distances is covered by relative slack on w^2 and an
-// absolute slack of 64 grid units on w.
+// Squared distance (grid units) from a target to the nearest edge of its
+// neighbour row (oy, oz), without branches: along each axis the distance is
+// oy - fy above the target's row, -oy - 1 + fy below it and 0 in it, which is
+// the largest of the three.
+template <int DIM>
+__device__ __forceinline__ float row_edge_d2(const PlumeDev& P, const Target& T, int oy, int oz) {
+    const float dy = fmaxf(fmaxf((float)oy - T.fy, (float)(-oy - 1) + T.fy), 0.f);
+    float dz = 0.f;
+    if (DIM == 3) dz = fmaxf(fmaxf((float)oz - T.fz, (float)(-oz - 1) + T.fz), 0.f);
+    return (dy * dy + dz * dz) * P.rowh2f;
+}
+
+// Half-width of the x window of a target in its neighbour row (oy, oz), as a
+// float in grid units: an upper bound of the chord of the search radius at
+// the row's nearest edge (the search radius itself in the target's own row,
+// where the bound exceeds hx and hx is taken); false when the row lies beyond
+// the search radius.  The bound is conservative: the float rounding of the
+// distances is covered by relative slack on w^2 and an absolute slack of 64
+// grid units on w.
+template <int DIM>
+__device__ __forceinline__ bool row_halfwidth_f(const PlumeDev& P, const Target& T, int oy, int oz, float& w) {
+    const float w2 = P.Hc2f * 1.000001f - row_edge_d2<DIM>(P, T, oy, oz) * 0.999999f;
+    // (w is meaningless, and unused, when the row is out of reach)
+    const float wf = __builtin_amdgcn_sqrtf(w2) * 1.000001f + 64.0f;
+    w = fminf(wf, (float)P.hx);
+    return w2 > 0.f;
+}
+
+// The same as a whole number of grid units (hx in the target's own row).
 template <int DIM>
 __device__ __forceinline__ bool row_halfwidth(const PlumeDev& P, const Target& T, int oy, int oz, uint32_t& w) {
-    float dy = 0.f, dz = 0.f;
-    if (oy > 0) dy = (float)oy - T.fy;
-    else if (oy < 0) dy = (float)(-oy - 1) + T.fy;
-    if (DIM == 3) {
-        if (oz > 0) dz = (float)oz - T.fz;
-        else if (oz < 0) dz = (float)(-oz - 1) + T.fz;
-    }
-    const float d2 = (dy * dy + dz * dz) * P.rowh2f;
-    w = P.hx;
-    if (d2 > 0.f) {
-        const float w2 = P.Hc2f * 1.000001f - d2 * 0.999999f;
-        if (w2 <= 0.f) return false;
-        const float wf = __builtin_amdgcn_sqrtf(w2) * 1.000001f + 64.0f;
-        w = wf < (float)P.hx ? (uint32_t)wf : P.hx;
-    }
-    return true;
+    const float w2 = P.Hc2f * 1.000001f - row_edge_d2<DIM>(P, T, oy, oz) * 0.999999f;
+    const float wf = __builtin_amdgcn_sqrtf(w2) * 1.000001f + 64.0f;
+    w = wf < (float)P.hx ? (uint32_t)wf : P.hx;
+    return w2 > 0.f;
 }
 
-// First cell of row (yy, zz) of a plume (row indices already wrapped).
+// First cell of row (yy, zz) of a plume (row indices already wrapped; the
+// plan keeps nr, nfx and nsub below 2^24, so zz * nr is a 24-bit multiply).
 __device__ __forceinline__ uint32_t row_base(const PlumeDev& P, int yy, int zz) {
-    return P.cbase + ((uint32_t)zz * P.nr + (uint32_t)yy) * P.nfx * P.nsub;
+    return P.cbase + (__umul24((uint32_t)zz, P.nr) + (uint32_t)yy) * (P.nfx * P.nsub);
 }
 
+// y in -nr .. 2 nr - 1 wrapped into 0 .. nr - 1 (as unsigned values, the
+// wrapped one is the smallest of y, y + nr and y - nr)
 __device__ __forceinline__ int wrap_row(const PlumeDev& P, int y) {
-    const int nr = (int)P.nr;
-    y += (y < 0) ? nr : 0;
-    y -= (y >= nr) ? nr : 0;
-    return y;
+    uint32_t u = (uint32_t)y;
+    u = min(u, u + P.nr);
+    u = min(u, u - P.nr);
+    return (int)u;
 }
 
 // Cells of row `row` under the x window [xlo, xhi] (fixed point, inclusive,
@@ -133,17 +147,16 @@ __device__ __forceinline__ uint32_t cell_start_at(const uint32_t* __restrict__ c
     return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(cs) + (k << 2));
 }
 
+// Row (oy, oz) relative to the target's own row, |oy|, |oz| <= R.
 template <int DIM>
-__device__ __forceinline__ RowRanges row_ranges(const PlumeDev& P, const uint32_t* __restrict__ cs,
-                                                const Target& T, int j, int span) {
+__device__ __forceinline__ RowRanges row_ranges_at(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                                   const Target& T, int oy, int oz) {
     RowRanges r{0u, 0u, 0u, 0u};
-    const int R = P.R;
-    const int oy = j % span - R, oz = (DIM == 3) ? j / span - R : 0;
-    uint32_t w;
-    if (!row_halfwidth<DIM>(P, T, oy, oz, w)) return r;
+    float w;
+    if (!row_halfwidth_f<DIM>(P, T, oy, oz, w)) return r;
     // the window [x - w, x + w] in x cells, widened by the slack: a superset
     // of the cells the exact window touches
-    const float wc = (float)w * P.cellx + P.cslack;
+    const float wc = fmar(w, P.cellx, P.cslack);
     const int nfx = (int)P.nfx, ns = (int)P.nsub;
     int clo = __float2int_rd(T.xc - wc), chi = __float2int_rd(T.xc + wc);
     int hi2 = -1;  // the low part [0, hi2] of a window that wraps around the seam
@@ -161,13 +174,34 @@ __device__ __forceinline__ RowRanges row_ranges(const PlumeDev& P, const uint32_
     const int yy = wrap_row(P, T.ry + oy);
     const int zz = (DIM == 3) ? wrap_row(P, T.rz + oz) : 0;
     const uint32_t row = row_base(P, yy, zz);
-    r.s0 = cell_start_at(cs, row + (uint32_t)(clo * ns));
-    r.e0 = cell_start_at(cs, row + (uint32_t)((chi + 1) * ns));
+    r.s0 = cell_start_at(cs, row + __umul24((uint32_t)clo, (uint32_t)ns));
+    r.e0 = cell_start_at(cs, row + __umul24((uint32_t)(chi + 1), (uint32_t)ns));
     if (hi2 >= 0) {
         r.s1 = cell_start_at(cs, row);
-        r.e1 = cell_start_at(cs, row + (uint32_t)((hi2 + 1) * ns));
+        r.e1 = cell_start_at(cs, row + __umul24((uint32_t)(hi2 + 1), (uint32_t)ns));
     }
     return r;
+}
+
+// Row number j (0 .. noff-1, oy fastest) of a target, span = 2R + 1.
+template <int DIM>
+__device__ __forceinline__ RowRanges row_ranges(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                                const Target& T, int j, int span) {
+    return row_ranges_at<DIM>(P, cs, T, j % span - P.R, (DIM == 3) ? j / span - P.R : 0);
+}
+
+// Steps a row offset (oy, oz) on by n rows in the order of row_ranges (oy
+// fastest), for n <= 2 span.
+__device__ __forceinline__ void next_row(int& oy, int& oz, int n, int R, int span) {
+    oy += n;
+    if (oy > R) {
+        oy -= span;
+        ++oz;
+    }
+    if (oy > R) {
+        oy -= span;
+        ++oz;
+    }
 }
 
 }  // namespace ade

@@ -8,7 +8,8 @@
 namespace ade {
 
 // ---------------------------------------------------------------------------
-// Candidate list of a target in LDS: entries (s_k, e_k), in bytes of the
+// Candidate list of a target in LDS (entry k at list[k * stride], a 24-bit
+// multiply: both factors are below the LDS size): entries (s_k, e_k), in bytes of the
 // 16-byte record array (a context holds fewer than 2^28 - 256 particles, so
 // offsets fit 32 bits with room for a cursor step past the end), each a
 // non-empty range [s_k, e_k) of the sorted order, touching ranges stored as
@@ -40,7 +41,7 @@ struct ListWriter {
             return;
         }
         if (pe != 0u) {
-            list[k * stride] = make_uint2(ps * kRecBytes, pe * kRecBytes);
+            list[__umul24(k, stride)] = make_uint2(ps * kRecBytes, pe * kRecBytes);
             total += pe - ps;
             ++k;
         }
@@ -49,19 +50,21 @@ struct ListWriter {
     }
     __device__ __forceinline__ uint32_t flush() {
         if (pe != 0u) {
-            list[k * stride] = make_uint2(ps * kRecBytes, pe * kRecBytes);
+            list[__umul24(k, stride)] = make_uint2(ps * kRecBytes, pe * kRecBytes);
             total += pe - ps;
             ++k;
         }
-        list[k * stride] = make_uint2(kListEndStart, kListEndEnd);
+        list[__umul24(k, stride)] = make_uint2(kListEndStart, kListEndEnd);
         return total;
     }
 };
 
-// Lane permutations inside a quad of lanes (full-rate DPP moves).
+// Lane permutations inside a quad of lanes (full-rate DPP moves).  Every
+// source lane is inside the quad, so with all lanes of the quad active no
+// lane keeps its previous value (none is given).
 template <int CTRL>
 __device__ __forceinline__ uint32_t quad_perm(uint32_t v) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xF, 0xF, false);
 }
 
 // The list as one lane builds it alone (every lane of a target builds the
@@ -69,16 +72,18 @@ __device__ __forceinline__ uint32_t quad_perm(uint32_t v) {
 template <int DIM>
 __device__ __forceinline__ uint32_t build_list_lane(const PlumeDev& P, const uint32_t* __restrict__ cs,
                                                     const Target& T, uint2* list, uint32_t stride) {
-    const int span = 2 * P.R + 1;
+    const int R = P.R, span = 2 * R + 1;
     const int noff = (DIM == 3) ? span * span : span;
     ListWriter w(list, stride);
+    int oy = -R, oz = -R;  // row j of the loop below
     // four rows at a time: their cell-start loads are in flight together
     for (int j = 0; j < noff; j += 4) {
         RowRanges r[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             r[q] = RowRanges{0u, 0u, 0u, 0u};
-            if (j + q < noff) r[q] = row_ranges<DIM>(P, cs, T, j + q, span);
+            if (j + q < noff) r[q] = row_ranges_at<DIM>(P, cs, T, oy, (DIM == 3) ? oz : 0);
+            next_row(oy, oz, 1, R, span);
         }
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -106,13 +111,18 @@ __device__ __forceinline__ uint32_t build_list_group(const PlumeDev& P, const ui
     constexpr int kPrev2 = 0x40;                    // [0,0,0,1]
     constexpr int kLast = (G == 4) ? 0xFF : 0xF5;  // [3,3,3,3] / [1,1,3,3]
     const uint32_t g = threadIdx.x & (G - 1);
-    const int span = 2 * P.R + 1;
+    const int R = P.R, span = 2 * R + 1;
     const int noff = (DIM == 3) ? span * span : span;
     uint32_t base = 0, total = 0;
     uint32_t pS = 0, pE = 0;  // main range of the row before the round (end 0: none)
+    // this lane's row j0 + g as offsets, stepped on by G rows a round (no
+    // division by span per row)
+    int oy = -R, oz = -R;
+    next_row(oy, oz, (int)g, R, span);
     for (int j0 = 0; j0 < noff; j0 += G) {
         RowRanges r{0u, 0u, 0u, 0u};
-        if (j0 + (int)g < noff) r = row_ranges<DIM>(P, cs, T, j0 + (int)g, span);
+        if (j0 + (int)g < noff) r = row_ranges_at<DIM>(P, cs, T, oy, (DIM == 3) ? oz : 0);
+        next_row(oy, oz, G, R, span);
         const bool hasL = r.e1 > r.s1, hasH = r.e0 > r.s0;
         const uint32_t hS = hasH ? r.s0 : 0u, hE = hasH ? r.e0 : 0u;
         // main range of the previous row
@@ -130,21 +140,21 @@ __device__ __forceinline__ uint32_t build_list_group(const PlumeDev& P, const ui
         const uint32_t first = base + incl - cnt;
         uint32_t pos = first;
         if (hasL && !mergeL) {
-            list[pos * stride] = make_uint2(r.s1 * kRecBytes, r.e1 * kRecBytes);
+            list[__umul24(pos, stride)] = make_uint2(r.s1 * kRecBytes, r.e1 * kRecBytes);
             ++pos;
         }
-        if (hasH) list[pos * stride] = make_uint2(r.s0 * kRecBytes, r.e0 * kRecBytes);
+        if (hasH) list[__umul24(pos, stride)] = make_uint2(r.s0 * kRecBytes, r.e0 * kRecBytes);
         // the previous row's entry, extended by a merged low part, is
         // rewritten after the round's entries (the LDS writes of a wavefront
         // take effect in program order)
         asm volatile("" ::: "memory");
-        if (mergeL) list[(first - 1u) * stride] = make_uint2(qS * kRecBytes, r.e1 * kRecBytes);
+        if (mergeL) list[__umul24(first - 1u, stride)] = make_uint2(qS * kRecBytes, r.e1 * kRecBytes);
         total += (r.e1 - r.s1) + (r.e0 - r.s0);
         base += quad_perm<kLast>(incl);
         pS = quad_perm<kLast>(hS);
         pE = quad_perm<kLast>(hE);
     }
-    list[base * stride] = make_uint2(kListEndStart, kListEndEnd);
+    list[__umul24(base, stride)] = make_uint2(kListEndStart, kListEndEnd);
     total += quad_perm<0xB1>(total);                // [1,0,3,2]
     if (G == 4) total += quad_perm<0x4E>(total);    // [2,3,0,1]
     return total;
