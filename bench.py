@@ -265,11 +265,19 @@ def roofline_alu(dim, interactions, ms_per_launch, kernel, launches, profile=Non
     return out
 
 
-def headline_3d(device, steps, warmup):
-    """The 3D plume (128^3 particles, h = 2 dp, FP32): autotuned launch shape,
-    `steps` steps replayed from the captured graph after `warmup` (the timed
-    region), then the same number of eager steps with HIP events around every
-    pair-kernel launch (the roofline)."""
+def parse_shape(text):
+    """A launch shape given as block,lanes,targets,xcd_group (None if empty)."""
+    if not text:
+        return None
+    b, l, t, x = (int(v) for v in text.split(","))
+    return {"block": b, "lanes": l, "targets": t, "xcd_group": x}
+
+
+def headline_3d(device, steps, warmup, shape=None):
+    """The 3D plume (128^3 particles, h = 2 dp, FP32): autotuned launch shape
+    (or the given one), `steps` steps replayed from the captured graph after
+    `warmup` (the timed region), then the same number of eager steps with HIP
+    events around every pair-kernel launch (the roofline)."""
     import numpy as np
     import torch
     from paper_2108_09488_amd import inputs as I
@@ -281,7 +289,11 @@ def headline_3d(device, steps, warmup):
     x = s.positions()
     c.init(torch.from_numpy(x), torch.from_numpy(s.concentration(x).astype(np.float32))).build()
     inter = int(c.neighbour_counts()[-1].item())
-    tuned = c.autotune(reps=2)
+    if shape:
+        c.set_tuning(**shape)
+        tuned = c.get_tuning()
+    else:
+        tuned = c.autotune(reps=2)
     print(f"[bench] 3D plume built: {inter} interactions per step, tuning {tuned}", file=sys.stderr, flush=True)
     c.step_graph(warmup)
     _sync()
@@ -525,6 +537,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size "
                          "reference for the HBM byte counters of a profiler run)")
+    ap.add_argument("--shape-3d", default="", metavar="B,L,T,X",
+                    help="launch shape of the 3D plume (block,lanes,targets,xcd_group) instead of "
+                         "the autotuner's, so that profiler runs see one kernel configuration")
+    ap.add_argument("--shape-sweep", default="", metavar="B,L,T,X",
+                    help="the same for the sweep context")
     ap.add_argument("--cpu-single-thread", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_single_thread:  # child process of cpu_baseline_3d (no GPU use)
@@ -548,7 +565,7 @@ def main():
         del src, dst
 
     # the headline: the 3D plume, graph-replayed steps
-    h = headline_3d(device, args.steps, args.warmup)
+    h = headline_3d(device, args.steps, args.warmup, parse_shape(args.shape_3d))
     inter3 = h["interactions_per_step"]
     value = inter3 * args.steps / h["wall"]
     print(f"[bench] 3D plume: {1e3 * h['wall'] / args.steps:.3f} ms/step (graph), pair kernel "
@@ -558,7 +575,11 @@ def main():
     if "sweep" in want:
         cells = args.cells.split(",") if args.cells else list(I.CFG2_CELLS)
         sweep = build_sweep(cells, device)
-        sweep["tuning"] = sweep["ctx"].autotune(reps=3)
+        if args.shape_sweep:
+            sweep["ctx"].set_tuning(**parse_shape(args.shape_sweep))
+            sweep["tuning"] = sweep["ctx"].get_tuning()
+        else:
+            sweep["tuning"] = sweep["ctx"].autotune(reps=3)
         inter_step = sum(sweep["interactions"])
         wall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
         ewall, pair = time_sweep(sweep, args.steps, args.warmup, graph=False)
