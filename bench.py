@@ -55,11 +55,14 @@ def valu_issue_frac(dim, interactions, seconds):
     return ISSUE_SLOTS_PER_INTERACTION[dim] * interactions / seconds / VALU_SLOTS_PER_S
 
 
-def step_kernel_name(tuning, dim=2):
-    """The update-mode pair kernel a launch shape runs (FP32, Wendland C4)."""
+def step_kernel_name(tuning, dim=2, coincident=False):
+    """The update-mode pair kernel a launch shape runs (FP32, Wendland C4;
+    the last template argument: whether it tests every candidate for r > 0,
+    which it does only in a context where two particles share a position)."""
+    zc = "true" if coincident else "false"
     if tuning.get("targets", 1) == 2:
-        return f"k_pair2<{dim}, float, 4, 0>"
-    return f"k_pair<{dim}, float, 4, 0, {tuning['lanes']}>"
+        return f"k_pair2<{dim}, float, 4, 0, {zc}>"
+    return f"k_pair<{dim}, float, 4, 0, {tuning['lanes']}, {zc}>"
 
 
 def pair_profile(kernel, key="traffic_bytes_per_launch", profile=None):
@@ -167,6 +170,7 @@ def batched(device, steps, warmup, n_plumes=256):
     _sync()
     pms, pn = ctx.timing_stop()
     n = ctx.N
+    coincident = ctx.coincident()
     ctx.close()
     # plain reference at the ensemble's neighbour count: one 512^2 plume with
     # h = 1.5 dp (the ensemble's smoothing length), the same kernel and jitter
@@ -191,7 +195,7 @@ def batched(device, steps, warmup, n_plumes=256):
             "plain_same_nbar": {"workload": "one 512^2 plume, h/dp 1.5, C4, FP32, graph replay",
                                 "neighbours_mean": rinter / ref.n, "interactions_per_s": plain},
             "vs_plain_same_nbar": rate / plain,
-            "roofline": roofline_alu(2, inter, pms / pn, step_kernel_name(tuned), pn)}
+            "roofline": roofline_alu(2, inter, pms / pn, step_kernel_name(tuned, coincident=coincident), pn)}
 
 
 def fwd_adjoint(device):
@@ -308,8 +312,9 @@ def headline_3d(device, steps, warmup, shape=None):
     ewall = time.perf_counter() - t1
     ms, n = c.timing_stop()
     cells = c.info()["cells"]
+    coincident = c.coincident()
     c.close()
-    kernel = step_kernel_name(tuned, dim=3)
+    kernel = step_kernel_name(tuned, dim=3, coincident=coincident)
     return {"spec": s, "interactions_per_step": inter, "tuning": tuned, "wall": wall, "cells": cells,
             "eager": {"ms_per_step": 1e3 * ewall / steps, "interactions_per_s": inter * steps / ewall,
                       "pair_kernel_ms_per_step": ms / n},
@@ -583,8 +588,9 @@ def main():
         inter_step = sum(sweep["interactions"])
         wall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
         ewall, pair = time_sweep(sweep, args.steps, args.warmup, graph=False)
+        coincident = sweep["ctx"].coincident()
         sweep["ctx"].close()
-        kname = step_kernel_name(sweep["tuning"])
+        kname = step_kernel_name(sweep["tuning"], coincident=coincident)
         extras["sweep"] = {
             "workload": "2D consistency sweep: 6 plumes x 512^2 particles, jitter 0.1 dp, Wendland C4, "
                         "h/dp {1.3,2,3} x alpha_L/alpha_T {10,100}, FP32, explicit Euler, dt Eq. (10), "

@@ -31,8 +31,9 @@
  *    owns every buffer; the library never allocates device memory.  Device
  *    buffers passed to ade_create must stay valid until ade_destroy.
  *  - All device work is enqueued on the HIP stream given to ade_create and is
- *    asynchronous, except where a host output (h_*, a saved state) or the
- *    finite check of ADE_CHECK_FINITE forces a synchronisation.
+ *    asynchronous, except where a host output (h_*, a saved state), the
+ *    finite check of ADE_CHECK_FINITE or the coincidence check of
+ *    ade_build_cells and ade_load_state forces a synchronisation.
  *  - Positions are SoA doubles, x[c * n + a] for component c of particle a.
  *    The library stores them as 32-bit fixed-point fractions of the box,
  *    u = round(x / L * 2^32) mod 2^32 (resolution L / 2^32): positions are
@@ -183,8 +184,19 @@ int ade_set_velocities(ade_ctx *ctx, const double *d_v);
 /* Cell-linked list: cell hash, counting sort by cell (stable, ordered by
  * particle id within a cell) and the cell-start table, then the particle
  * state is gathered into cell order.  Needed once after init; every step
- * rebuilds it. */
+ * rebuilds it.  For a uniform flow it also checks whether two particles of
+ * a plume share a position (and synchronises the stream for that): the sum
+ * of Eq. (4) leaves out pairs at r = 0, and when no two particles coincide
+ * the only candidate at r = 0 is a target's own record, whose term is zero,
+ * so the FP32 Wendland C4 pair kernels skip the test (results unchanged;
+ * every step keeps the relative positions of a plume's particles, so the
+ * check holds for the run).  ade_load_state repeats the check. */
 int ade_build_cells(ade_ctx *ctx);
+
+/* *out = 1 when two particles of a plume share a position (or the context
+ * has not been checked: before ade_build_cells, and always for
+ * ADE_VELOCITY_FIELD contexts), else 0. */
+int ade_coincident(const ade_ctx *ctx, int32_t *out);
 
 /* nsteps explicit steps (pair sum of Eqs. 4-5, update of C and x, rebuild).
  * With ADE_CHECK_FINITE on any plume of the context, the concentrations are

@@ -23,6 +23,7 @@ ERROR_NAMES = {0: "ADE_OK", -1: "ADE_EINVAL", -2: "ADE_EWORKSPACE", -3: "ADE_EHI
 
 # every entry point declared in include/adesph.h
 EXPORTS = ["ade_workspace_bytes", "ade_create", "ade_init_particles", "ade_set_velocities", "ade_build_cells",
+           "ade_coincident",
            "ade_step", "ade_step_graph", "ade_rhs", "ade_read_C", "ade_read_x", "ade_mass", "ade_conc_range",
            "ade_neighbours", "ade_sensor_interp", "ade_adjoint_workspace_bytes", "ade_adjoint",
            "ade_adjoint_noalloc", "ade_adjoint_noalloc_max_bytes",
@@ -91,6 +92,7 @@ def lib() -> ct.CDLL:
         "ade_set_tuning": [p, T],
         "ade_get_tuning": [p, T],
         "ade_info": [p, i32, pi64, pi64, pi64, pd, pi64],
+        "ade_coincident": [p, ct.POINTER(ct.c_int32)],
         "ade_state_bytes": [p, psz],
         "ade_save_state": [p, p, sz],
         "ade_load_state": [p, p, sz],

@@ -202,6 +202,14 @@ class Context:
                              ct.byref(st)))
         return {"n": n.value, "cells": c.value, "tiles": t.value, "dt": dt.value, "step": st.value}
 
+    def coincident(self) -> bool:
+        """Whether two particles of a plume share a position (or the context
+        has not been checked): the pair kernels then test every candidate
+        for r > 0."""
+        v = ct.c_int32()
+        check(lib().ade_coincident(self._h, ct.byref(v)))
+        return bool(v.value)
+
     def timing_start(self):
         """Start HIP-event timing of the pair kernel launches."""
         check(lib().ade_kernel_timing(self._h, 1, None, None))

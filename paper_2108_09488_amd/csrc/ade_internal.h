@@ -105,6 +105,9 @@ struct PairLaunch {
     int list_cap;           // candidate-list entries per target in LDS (list_cap_for)
     int persistent;         // 0: one workgroup per work item; > 0: that many workgroups loop
     uint32_t xcd_group;     // consecutive work items an XCD takes in turn (>= 1)
+    int zc;                 // 1: two distinct particles may share a position, so every
+                            // candidate is tested for r > 0; 0: the only candidate at
+                            // r = 0 is the target's own record (FP32 C4 kernels skip the test)
     const uint4* rec;       // candidate records (position + C of Cpair), or null: SoA reads
     const uint32_t* spos[3];
     const uint32_t* sid;
@@ -189,6 +192,8 @@ hipError_t launch_pair_gen(int dim, int real_bytes, int kernel, int mode, const 
 hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const PairLaunch& a,
                        int block, hipStream_t s);
 hipError_t launch_read_C(int real_bytes, StateArrays S, uint32_t N, void* out, hipStream_t s);
+hipError_t launch_coincident(int dim, const PlumeDev* plumes, const TileDev* tiles, uint32_t ntiles,
+                             StateArrays S, const uint32_t* cell_start, uint32_t* flag, hipStream_t s);
 hipError_t launch_read_x(int dim, const PlumeDev* plumes, const TileDev* tiles, uint32_t ntiles,
                          StateArrays S, uint32_t N, double* out, hipStream_t s);
 hipError_t launch_mass(int real_bytes, const PlumeDev* plumes, int nplumes, const TileDev* tiles,

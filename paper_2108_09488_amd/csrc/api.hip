@@ -524,6 +524,7 @@ PairLaunch pair_args(ade_ctx* c, int mode, const void* Cpair, const void* Cbase,
     a.list_cap = tuning_list_cap(c->plan, c->tuning);
     a.persistent = c->tuning.persistent;
     a.xcd_group = c->tuning.xcd_group > 0 ? (uint32_t)c->tuning.xcd_group : 32u;
+    a.zc = c->coincident ? 1 : 0;
     // candidate records carrying the concentrations the pair sum reads
     a.rec = (Cpair == c->aux) ? c->aux_rec : c->S.rec;
     a.out_rec = c->aux_rec;
@@ -723,6 +724,8 @@ int ade_init_particles(ade_ctx* c, const double* d_x, const void* d_C) {
     c->initialized = true;
     c->built = false;
     c->vel_set = false;
+    if (!c->coincident) drop_graph(c);
+    c->coincident = true;  // until the cell build checks the new positions
     return ADE_OK;
 }
 
@@ -738,6 +741,27 @@ int ade_set_velocities(ade_ctx* c, const double* d_v) {
     return ADE_OK;
 }
 
+// Whether two particles of a plume share a position, from the built cells
+// (synchronises the stream).  With a uniform flow every particle of a plume
+// moves by the same displacement, so the answer holds for the whole run; a
+// velocity-field context keeps its own kernels and is not checked.
+static int check_coincident(ade_ctx* c) {
+    const Plan& pl = c->plan;
+    bool found = true;
+    if (!pl.general) {
+        uint32_t h = 0;
+        HIPCHK(hipMemsetAsync(c->nonfinite, 0, sizeof(uint32_t), c->stream));
+        HIPCHK(launch_coincident(pl.dim, c->plumes, c->tiles, pl.ntiles, c->S, c->cell_start, c->nonfinite,
+                                 c->stream));
+        HIPCHK(hipMemcpyAsync(&h, c->nonfinite, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(hipStreamSynchronize(c->stream));
+        found = h != 0;
+    }
+    if (found != c->coincident) drop_graph(c);  // a captured step holds the other kernels
+    c->coincident = found;
+    return ADE_OK;
+}
+
 int ade_build_cells(ade_ctx* c) {
     if (!c) return fail(ADE_EINVAL, "null ctx");
     if (!c->initialized) return fail(ADE_ESTATE, "ade_build_cells before ade_init_particles");
@@ -747,6 +771,12 @@ int ade_build_cells(ade_ctx* c) {
     int rc = enqueue_build(c, 0);
     if (rc) return rc;
     c->built = true;
+    return check_coincident(c);
+}
+
+int ade_coincident(const ade_ctx* c, int32_t* out) {
+    if (!c || !out) return fail(ADE_EINVAL, "null argument");
+    *out = c->coincident ? 1 : 0;
     return ADE_OK;
 }
 
@@ -1202,7 +1232,7 @@ int ade_load_state(ade_ctx* c, const void* h_buf, size_t bytes) {
     c->initialized = true;
     c->built = true;
     c->vel_set = true;
-    return ADE_OK;
+    return check_coincident(c);
 }
 
 int ade_destroy(ade_ctx* c) {

@@ -66,6 +66,9 @@ struct ade_ctx {
     uint32_t* nonfinite = nullptr;  // finite check: set when a concentration is not finite
     uint32_t h_total = 0;  // host copy of N for the cell-start sentinel
     bool initialized = false, built = false;
+    // two particles of a plume share a position (the pair kernels then test
+    // every candidate for r > 0); true until a cell build has checked
+    bool coincident = true;
     bool vel_set = false;  // velocity field: ade_set_velocities called since init
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;

@@ -349,6 +349,35 @@ hipError_t launch_read_x(int dim, const PlumeDev* plumes, const TileDev* tiles, 
     return hipGetLastError();
 }
 
+// Coincident positions: any particle of the sorted state that shares its
+// position with another particle of its cell (two particles at one point are
+// in one cell) sets *flag.  Cells hold a few particles, so each particle
+// compares itself with the rest of its cell.
+template <int DIM>
+__global__ __launch_bounds__(kTile) void k_coincident(const PlumeDev* __restrict__ plumes,
+                                                     const TileDev* __restrict__ tiles, StateArrays S,
+                                                     const uint32_t* __restrict__ cell_start,
+                                                     uint32_t* __restrict__ flag) {
+    const TileDev t = tiles[blockIdx.x];
+    const uint32_t i = t.start + threadIdx.x;
+    if (i >= t.end) return;
+    const PlumeDev& P = plumes[t.plume];
+    const uint32_t ux = S.pos[0][i], uy = S.pos[1][i], uz = (DIM == 3) ? S.pos[2][i] : 0u;
+    const uint32_t key = cell_key<DIM>(P, ux, uy, uz);
+    const uint32_t e = cell_start[key + 1];
+    bool same = false;
+    for (uint32_t j = cell_start[key]; j < e; ++j)
+        same |= j != i && S.pos[0][j] == ux && S.pos[1][j] == uy && (DIM == 2 || S.pos[2][j] == uz);
+    if (same) *flag = 1u;
+}
+
+hipError_t launch_coincident(int dim, const PlumeDev* plumes, const TileDev* tiles, uint32_t ntiles,
+                             StateArrays S, const uint32_t* cell_start, uint32_t* flag, hipStream_t s) {
+    if (dim == 2) hipLaunchKernelGGL((k_coincident<2>), dim3(ntiles), dim3(kTile), 0, s, plumes, tiles, S, cell_start, flag);
+    else hipLaunchKernelGGL((k_coincident<3>), dim3(ntiles), dim3(kTile), 0, s, plumes, tiles, S, cell_start, flag);
+    return hipGetLastError();
+}
+
 hipError_t launch_mass(int real_bytes, const PlumeDev* plumes, int nplumes, const TileDev* tiles,
                        uint32_t ntiles, StateArrays S, double* partial, double* out,
                        hipStream_t s) {

@@ -52,7 +52,14 @@ constexpr double kPolyScale = (KERN == 4) ? 6.0 : 1.0;
 // the bracket is A0 + S (E . x / r)^2 with S = +-1 (PlumeDev::dterm; in 2D
 // S = +1 always).  The term forms S times it, (E . x / r)^2 + S A0, and
 // finish_target multiplies the sum by S.
-template <int DIM, typename real, int KERN>
+// ZC (zero separations): two distinct particles may share a position, so a
+// candidate at r = 0 is cut by a select.  Without ZC the only candidate at
+// r = 0 is the target's own record (a padding slot re-reads it): r^2 starts
+// from a tiny offset, which leaves every r^2 >= 1 (grid units) unchanged and
+// keeps the self term finite, and the self term is w (C_a - C_a) = 0 exactly.
+template <typename real>
+constexpr real kTinyR2 = sizeof(real) == 4 ? (real)9.094947017729282e-13 : (real)7.888609052210118e-31;  // 2^-40, 2^-100
+template <int DIM, typename real, int KERN, bool ZC>
 struct PairTerm {
     real invHu, a0s, ex, ey, ez;
     __device__ __forceinline__ void operator()(const Target& T, real Ca, uint32_t bx, uint32_t by,
@@ -70,15 +77,15 @@ struct PairTerm {
     }
     // the same from the separation (dx, dy, dz) = x_a - x_b in grid units
     __device__ __forceinline__ void sep(real dx, real dy, real dz, real Ca, real Cb, bool keep, real& acc) const {
-        real r2 = dx * dx;
+        real r2 = ZC ? dx * dx : fmar(dx, dx, kTinyR2<real>);
         r2 = fmar(dy, dy, r2);
         if (DIM == 3) r2 = fmar(dz, dz, r2);
-        // r2 = 0 (the target itself, a padding slot, a coincident particle)
-        // is cut by the select below; the support r <= H by the clamp of
-        // 1 - q at 0, which zeroes the kernel factor outside it (W is 0 at
-        // q = 1, so where the rounding of r puts 1 - q on the other side of 0
-        // the term is below 1e-28 of a typical one either way)
-        const bool inside = keep && r2 > (real)0;
+        // with ZC, r2 = 0 (the target itself, a padding slot, a coincident
+        // particle) is cut by the select below; the support r <= H by the
+        // clamp of 1 - q at 0, which zeroes the kernel factor outside it (W is
+        // 0 at q = 1, so where the rounding of r puts 1 - q on the other side
+        // of 0 the term is below 1e-28 of a typical one either way)
+        const bool inside = ZC ? (keep && r2 > (real)0) : keep;
         const real rinv = rsqrt_r(r2);
         const real r = r2 * rinv;
         const real omq = clamp_unit(fmar(-r, invHu, (real)1));
@@ -101,9 +108,9 @@ struct PairTerm {
 
 // the constants come from the plume table as they are (FP32 copies for FP32),
 // so they stay in scalar registers
-template <int DIM, typename real, int KERN>
-__device__ __forceinline__ PairTerm<DIM, real, KERN> make_term(const PlumeDev& P) {
-    PairTerm<DIM, real, KERN> t;
+template <int DIM, typename real, int KERN, bool ZC>
+__device__ __forceinline__ PairTerm<DIM, real, KERN, ZC> make_term(const PlumeDev& P) {
+    PairTerm<DIM, real, KERN, ZC> t;
     real c[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) c[k] = (sizeof(real) == 4) ? (real)P.fterm[k] : (real)P.dterm[k];
@@ -255,7 +262,7 @@ __device__ __forceinline__ void finish_target(const PairLaunch& a, const PlumeDe
 // One work item = `block / LANES` consecutive target particles of one tile.
 // The plume and tile tables come in as read-only, non-aliased kernel
 // arguments so that their workgroup-uniform reads go through the scalar unit.
-template <int DIM, typename real, int KERN, int MODE, int LANES>
+template <int DIM, typename real, int KERN, int MODE, int LANES, bool ZC>
 __device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* __restrict__ plumes,
                                           const TileDev* __restrict__ tiles, uint32_t w,
                                           uint2* lds_list) {
@@ -305,7 +312,7 @@ __device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* _
                              },
                              acc);
     };
-    walk(make_term<DIM, real, KERN>(P));
+    walk(make_term<DIM, real, KERN, ZC>(P));
 
     // wavefront reduction over the lanes of a target (fixed order: deterministic)
     if (LANES >= 2) acc += __shfl_xor(acc, 1, kWave);
@@ -450,7 +457,7 @@ __device__ __forceinline__ void walk_pair(const Term& term, const Target& TA, co
 
 // One work item = 2 * block consecutive target particles of one tile, two
 // per lane.
-template <int DIM, typename real, int KERN, int MODE>
+template <int DIM, typename real, int KERN, int MODE, bool ZC>
 __device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* __restrict__ plumes,
                                            const TileDev* __restrict__ tiles, uint32_t w, uint2* lds_list) {
     const uint32_t stride = (uint32_t)a.block;
@@ -492,7 +499,7 @@ __device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* 
     if (merged) total = build_union<DIM>(P, a.cell_start, TA, TB, dy, dz, list, stride);
     else if (actA) total = build_list<DIM, 1>(P, a.cell_start, TA, list, stride);
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
-    const PairTerm<DIM, real, KERN> term = make_term<DIM, real, KERN>(P);
+    const PairTerm<DIM, real, KERN, ZC> term = make_term<DIM, real, KERN, ZC>(P);
     walk_pair<DIM>(term, TA, TB, CA, CB, iA, list, stride, total, fetch, accA, accB);
     if (actA) finish_target<DIM, real, KERN, MODE>(a, P, TA, iA, accA);
     if (merged) finish_target<DIM, real, KERN, MODE>(a, P, TB, iB, accB);
@@ -514,14 +521,14 @@ __device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* 
 // Eight wavefronts per SIMD for the FP32 kernels: at most 64 VGPRs and 100
 // SGPRs (kernel arguments are re-read from the argument segment rather than
 // held across the candidate loop).
-template <int DIM, typename real, int KERN, int MODE, int LANES>
+template <int DIM, typename real, int KERN, int MODE, int LANES, bool ZC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 && DIM == 2 ? 8 : 1)))
 void k_pair(PairLaunch a, const PlumeDev* __restrict__ plumes,
                                               const TileDev* __restrict__ tiles, uint32_t nwork) {
     extern __shared__ uint2 lds_list[];
     if (a.persistent == 0) {
-        pair_item<DIM, real, KERN, MODE, LANES>(a, plumes, tiles, xcd_remap(blockIdx.x, gridDim.x, a.xcd_group),
-                                                lds_list);
+        pair_item<DIM, real, KERN, MODE, LANES, ZC>(a, plumes, tiles, xcd_remap(blockIdx.x, gridDim.x, a.xcd_group),
+                                                    lds_list);
         return;
     }
     // persistent grid: the k-th of the workgroups on XCD x takes every
@@ -533,19 +540,19 @@ void k_pair(PairLaunch a, const PlumeDev* __restrict__ plumes,
     for (uint32_t m = k;; m += per_x) {
         const uint32_t w = xcd_item(x, m, nwork, a.xcd_group);
         if (w >= nwork) break;
-        pair_item<DIM, real, KERN, MODE, LANES>(a, plumes, tiles, w, lds_list);
+        pair_item<DIM, real, KERN, MODE, LANES, ZC>(a, plumes, tiles, w, lds_list);
     }
 }
 
 // Two targets per lane: at most 128 threads (a work item holds 2 * block
 // targets of a 256-particle tile); six wavefronts per SIMD for 2D FP32 (the
 // lane carries both targets through the walk).
-template <int DIM, typename real, int KERN, int MODE>
+template <int DIM, typename real, int KERN, int MODE, bool ZC>
 __global__ __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(sizeof(real) == 4 && DIM == 2 ? 6 : 1)))
 void k_pair2(PairLaunch a, const PlumeDev* __restrict__ plumes, const TileDev* __restrict__ tiles, uint32_t nwork) {
     extern __shared__ uint2 lds_list[];
     if (a.persistent == 0) {
-        pair_item2<DIM, real, KERN, MODE>(a, plumes, tiles, xcd_remap(blockIdx.x, gridDim.x, a.xcd_group), lds_list);
+        pair_item2<DIM, real, KERN, MODE, ZC>(a, plumes, tiles, xcd_remap(blockIdx.x, gridDim.x, a.xcd_group), lds_list);
         return;
     }
     const uint32_t nx = 8, x = blockIdx.x % nx, k = blockIdx.x / nx;
@@ -553,7 +560,7 @@ void k_pair2(PairLaunch a, const PlumeDev* __restrict__ plumes, const TileDev* _
     for (uint32_t m = k;; m += per_x) {
         const uint32_t w = xcd_item(x, m, nwork, a.xcd_group);
         if (w >= nwork) break;
-        pair_item2<DIM, real, KERN, MODE>(a, plumes, tiles, w, lds_list);
+        pair_item2<DIM, real, KERN, MODE, ZC>(a, plumes, tiles, w, lds_list);
     }
 }
 
@@ -600,7 +607,7 @@ __global__ __launch_bounds__(kTile) void k_nbr(const PlumeDev* __restrict__ plum
     if (!fill) offsets[me] = k;
 }
 
-template <int DIM, typename real, int KERN, int LANES>
+template <int DIM, typename real, int KERN, int LANES, bool ZC>
 static void launch_pair_l(int mode, const PairLaunch& a, hipStream_t s) {
     const uint32_t tpb = (uint32_t)a.block / LANES;
     const uint32_t nwork = a.ntiles * (kTile / tpb);
@@ -609,16 +616,16 @@ static void launch_pair_l(int mode, const PairLaunch& a, hipStream_t s) {
     const uint32_t grid = (c.persistent > 0) ? max(8u, min(nwork, (uint32_t)c.persistent)) : nwork;
     dim3 g(grid), b(a.block);
     const size_t shm = pair_lds_bytes(a.block, LANES, a.list_cap);
-    auto kern = (mode == kModeStep)   ? k_pair<DIM, real, KERN, kModeStep, LANES>
-                : (mode == kModeHalf) ? k_pair<DIM, real, KERN, kModeHalf, LANES>
-                                      : k_pair<DIM, real, KERN, kModeRhs, LANES>;
+    auto kern = (mode == kModeStep)   ? k_pair<DIM, real, KERN, kModeStep, LANES, ZC>
+                : (mode == kModeHalf) ? k_pair<DIM, real, KERN, kModeHalf, LANES, ZC>
+                                      : k_pair<DIM, real, KERN, kModeRhs, LANES, ZC>;
     if (c.ev0)  // timed launch: the events carry the kernel's own start and end stamps
         hipExtLaunchKernelGGL(kern, g, b, (uint32_t)shm, s, c.ev0, c.ev1, 0u, c, c.plumes, c.tiles, nwork);
     else
         hipLaunchKernelGGL(kern, g, b, shm, s, c, c.plumes, c.tiles, nwork);
 }
 
-template <int DIM, typename real, int KERN>
+template <int DIM, typename real, int KERN, bool ZC>
 static void launch_pair_2(int mode, const PairLaunch& a, hipStream_t s) {
     const uint32_t tpb = 2u * (uint32_t)a.block;
     const uint32_t nwork = a.ntiles * (kTile / tpb);
@@ -627,21 +634,34 @@ static void launch_pair_2(int mode, const PairLaunch& a, hipStream_t s) {
     const uint32_t grid = (c.persistent > 0) ? max(8u, min(nwork, (uint32_t)c.persistent)) : nwork;
     dim3 g(grid), b(a.block);
     const size_t shm = pair_lds_bytes(a.block, 1, a.list_cap);
-    auto kern = (mode == kModeStep)   ? k_pair2<DIM, real, KERN, kModeStep>
-                : (mode == kModeHalf) ? k_pair2<DIM, real, KERN, kModeHalf>
-                                      : k_pair2<DIM, real, KERN, kModeRhs>;
+    auto kern = (mode == kModeStep)   ? k_pair2<DIM, real, KERN, kModeStep, ZC>
+                : (mode == kModeHalf) ? k_pair2<DIM, real, KERN, kModeHalf, ZC>
+                                      : k_pair2<DIM, real, KERN, kModeRhs, ZC>;
     if (c.ev0)
         hipExtLaunchKernelGGL(kern, g, b, (uint32_t)shm, s, c.ev0, c.ev1, 0u, c, c.plumes, c.tiles, nwork);
     else
         hipLaunchKernelGGL(kern, g, b, shm, s, c, c.plumes, c.tiles, nwork);
 }
 
+template <int DIM, typename real, int KERN, bool ZC>
+static void launch_pair_z(int mode, const PairLaunch& a, hipStream_t s) {
+    if (a.targets == 2) launch_pair_2<DIM, real, KERN, ZC>(mode, a, s);
+    else if (a.lanes == 4) launch_pair_l<DIM, real, KERN, 4, ZC>(mode, a, s);
+    else if (a.lanes == 2) launch_pair_l<DIM, real, KERN, 2, ZC>(mode, a, s);
+    else launch_pair_l<DIM, real, KERN, 1, ZC>(mode, a, s);
+}
+
+// the kernels without the r > 0 test exist for FP32 and Wendland C4 (the
+// FP32 problems); everything else tests every candidate
 template <int DIM, typename real, int KERN>
 static void launch_pair_t(int mode, const PairLaunch& a, hipStream_t s) {
-    if (a.targets == 2) launch_pair_2<DIM, real, KERN>(mode, a, s);
-    else if (a.lanes == 4) launch_pair_l<DIM, real, KERN, 4>(mode, a, s);
-    else if (a.lanes == 2) launch_pair_l<DIM, real, KERN, 2>(mode, a, s);
-    else launch_pair_l<DIM, real, KERN, 1>(mode, a, s);
+    if constexpr (sizeof(real) == 4 && KERN == 4) {
+        if (!a.zc) {
+            launch_pair_z<DIM, real, KERN, false>(mode, a, s);
+            return;
+        }
+    }
+    launch_pair_z<DIM, real, KERN, true>(mode, a, s);
 }
 
 hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const PairLaunch& a,

@@ -263,3 +263,38 @@ def test_concentration_range_per_plume():
             assert got[p, 0] == C[off:off + s.n].min() and got[p, 1] == C[off:off + s.n].max()
             off += s.n
     ens.close()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_coincident_particles(dim):
+    """Distinct particles at one position: the sum of Eq. (4) leaves such
+    pairs out (r = 0).  The cell build finds them, so the context keeps the
+    pair kernels that test every candidate for r > 0, and the rhs and a few
+    FP32 steps match the oracle; the same plume without them is reported
+    free of coincidences (and its kernels skip the test)."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    base = "cfg1" if dim == 2 else "cfg3"
+    spec = I.config(base, n_side=48 if dim == 2 else 14, real_bytes=4, kernel=4, h_over_dp=1.5,
+                    jitter=0.1, dt=2.0 ** -14)
+    x = spec.positions()
+    C = spec.concentration(x).astype(np.float32).astype(np.float64)
+    xc = x.copy()
+    xc[:, 500:510] = x[:, 10:20]  # ten particles moved onto ten others (their C differ)
+    assert np.any(C[500:510] != C[10:20])
+    m = O.model_from_spec(spec)
+    for pos, coincident in ((x, False), (xc, True)):
+        print(f"[case] coincident particles dim={dim} planted={coincident}", flush=True)
+        ctx = Context([params_from_spec(spec)], [spec.n])
+        ctx.init(torch.from_numpy(pos), torch.from_numpy(C))
+        assert ctx.coincident()  # unchecked before the cell build
+        ctx.build()
+        assert ctx.coincident() == coincident
+        g = ctx.rhs().double().cpu().numpy()
+        r = O.rhs(m, pos, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+        assert _rel(g, r) < 1e-5
+        steps = 6
+        ctx.step(steps)
+        Cg = ctx.read_C().double().cpu().numpy()
+        _, Co, _ = O.run(m, pos, C, spec.dt, steps, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
+        assert _rel(Cg, Co) < 1e-5
+        ctx.close()
