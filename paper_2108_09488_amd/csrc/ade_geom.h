@@ -111,28 +111,6 @@ __device__ __forceinline__ int wrap_row(const PlumeDev& P, int y) {
     return (int)u;
 }
 
-// Cells of row `row` under the x window [xlo, xhi] (fixed point, inclusive,
-// xhi - xlo < 2^32 - one cell width as an unsigned difference): k0 .. k1,
-// and k2 .. k3 when the window wraps around the periodic seam (k2 > k3
-// marks it empty).  Whole x cells, every sub-row of each.
-__device__ __forceinline__ void window_cells(const PlumeDev& P, uint32_t row, uint32_t xlo, uint32_t xhi,
-                                             uint32_t& k0, uint32_t& k1, uint32_t& k2, uint32_t& k3) {
-    const uint32_t nfx = P.nfx, ns = P.nsub;
-    const uint32_t clo = __umulhi(xlo, nfx);
-    const uint32_t chi = __umulhi(xhi, nfx);
-    if (clo <= chi) {
-        k0 = row + clo * ns;
-        k1 = row + chi * ns + ns - 1u;
-        k2 = 1u;
-        k3 = 0u;
-    } else {
-        k0 = row + clo * ns;
-        k1 = row + nfx * ns - 1u;
-        k2 = row;
-        k3 = row + chi * ns + ns - 1u;
-    }
-}
-
 // Sorted-index ranges of row number j (0 .. noff-1, oy fastest) of a target:
 // [s0, e0) the cells of its x window, and when the window wraps around the
 // periodic x seam [s1, e1) its low part at the start of the row ([s0, e0)
@@ -147,18 +125,25 @@ __device__ __forceinline__ uint32_t cell_start_at(const uint32_t* __restrict__ c
     return *reinterpret_cast<const uint32_t*>(reinterpret_cast<const char*>(cs) + (k << 2));
 }
 
-// Row (oy, oz) relative to the target's own row, |oy|, |oz| <= R.
-template <int DIM>
-__device__ __forceinline__ RowRanges row_ranges_at(const PlumeDev& P, const uint32_t* __restrict__ cs,
-                                                   const Target& T, int oy, int oz) {
+// Sorted-index ranges of the x cells floor(lo) .. floor(hi) of the row whose
+// first cell is `row`, the window given in x cells (float, slack included,
+// hi - lo < 2 nfx and -nfx <= lo, hi < 2 nfx: a window around a point of the
+// box), taken around the periodic seam: [s0, e0) and, when the window wraps,
+// its low part [s1, e1) at the start of the row; a window of a whole row or
+// more takes the whole row.
+__device__ __forceinline__ RowRanges window_ranges(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                                   uint32_t row, float lo, float hi) {
     RowRanges r{0u, 0u, 0u, 0u};
-    float w;
-    if (!row_halfwidth_f<DIM>(P, T, oy, oz, w)) return r;
-    // the window [x - w, x + w] in x cells, widened by the slack: a superset
-    // of the cells the exact window touches
-    const float wc = fmar(w, P.cellx, P.cslack);
-    const int nfx = (int)P.nfx, ns = (int)P.nsub;
-    int clo = __float2int_rd(T.xc - wc), chi = __float2int_rd(T.xc + wc);
+    const int nfx = (int)P.nfx;
+    const uint32_t ns = P.nsub;
+    int clo = __float2int_rd(lo), chi = __float2int_rd(hi);
+    if (chi < 0) {  // the whole window left of the seam
+        clo += nfx;
+        chi += nfx;
+    } else if (clo >= nfx) {  // the whole window right of it
+        clo -= nfx;
+        chi -= nfx;
+    }
     int hi2 = -1;  // the low part [0, hi2] of a window that wraps around the seam
     if (chi - clo + 1 >= nfx) {
         clo = 0;
@@ -171,16 +156,28 @@ __device__ __forceinline__ RowRanges row_ranges_at(const PlumeDev& P, const uint
         hi2 = chi - nfx;
         chi = nfx - 1;
     }
-    const int yy = wrap_row(P, T.ry + oy);
-    const int zz = (DIM == 3) ? wrap_row(P, T.rz + oz) : 0;
-    const uint32_t row = row_base(P, yy, zz);
-    r.s0 = cell_start_at(cs, row + __umul24((uint32_t)clo, (uint32_t)ns));
-    r.e0 = cell_start_at(cs, row + __umul24((uint32_t)(chi + 1), (uint32_t)ns));
+    r.s0 = cell_start_at(cs, row + __umul24((uint32_t)clo, ns));
+    r.e0 = cell_start_at(cs, row + __umul24((uint32_t)(chi + 1), ns));
     if (hi2 >= 0) {
         r.s1 = cell_start_at(cs, row);
-        r.e1 = cell_start_at(cs, row + __umul24((uint32_t)(hi2 + 1), (uint32_t)ns));
+        r.e1 = cell_start_at(cs, row + __umul24((uint32_t)(hi2 + 1), ns));
     }
     return r;
+}
+
+// Row (oy, oz) relative to the target's own row, |oy|, |oz| <= R.
+template <int DIM>
+__device__ __forceinline__ RowRanges row_ranges_at(const PlumeDev& P, const uint32_t* __restrict__ cs,
+                                                   const Target& T, int oy, int oz) {
+    RowRanges r{0u, 0u, 0u, 0u};
+    float w;
+    if (!row_halfwidth_f<DIM>(P, T, oy, oz, w)) return r;
+    // the window [x - w, x + w] in x cells, widened by the slack: a superset
+    // of the cells the exact window touches
+    const float wc = fmar(w, P.cellx, P.cslack);
+    const int yy = wrap_row(P, T.ry + oy);
+    const int zz = (DIM == 3) ? wrap_row(P, T.rz + oz) : 0;
+    return window_ranges(P, cs, row_base(P, yy, zz), T.xc - wc, T.xc + wc);
 }
 
 // Row number j (0 .. noff-1, oy fastest) of a target, span = 2R + 1.

@@ -361,53 +361,42 @@ __device__ __forceinline__ bool pair_rows(const PlumeDev& P, const Target& A, co
     return close && span + 1 <= nr && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
 }
 
-// Sorted-index ranges of row number j of a pair's rows: (s1, e1) is the low
-// part of a row cut by the seam (empty otherwise), (s0, e0) the rest.
+// Sorted-index ranges of the pair's row (oy, oz), offsets from a's row:
+// (s1, e1) is the low part of a row cut by the seam (empty otherwise), (s0,
+// e0) the rest.  The arc is the smallest one holding the windows of the
+// targets that reach the row, taken in x cells in a's frame (b at A.xc +
+// dxc, dxc = (x_b - x_a) in x cells), with the slack of row_ranges_at.
 template <int DIM>
 __device__ __forceinline__ RowRanges union_row(const PlumeDev& P, const uint32_t* __restrict__ cs, const Target& A,
-                                               const Target& B, int dy, int dz, int j) {
-    RowRanges r{0u, 0u, 0u, 0u};
+                                               const Target& B, float dxc, int dy, int dz, int oy, int oz) {
     const int R = P.R;
-    const int ny = 2 * R + 1 + (dy != 0 ? 1 : 0);
-    const int oy = j % ny + min(0, dy) - R;
-    const int oz = (DIM == 3) ? j / ny + min(0, dz) - R : 0;
-    uint32_t wa = 0, wb = 0;
-    const bool ra = abs(oy) <= R && abs(oz) <= R && row_halfwidth<DIM>(P, A, oy, oz, wa);
-    const bool rb = abs(oy - dy) <= R && abs(oz - dz) <= R && row_halfwidth<DIM>(P, B, oy - dy, oz - dz, wb);
-    if (!ra && !rb) return r;
-    // the arc in a's frame: [lo, hi] relative to A.ux
-    const int64_t d = (int32_t)(B.ux - A.ux);
-    int64_t lo = ra ? -(int64_t)wa : d - (int64_t)wb;
-    int64_t hi = ra ? (int64_t)wa : d + (int64_t)wb;
+    float wa = 0.f, wb = 0.f;
+    const bool ra = abs(oy) <= R && abs(oz) <= R && row_halfwidth_f<DIM>(P, A, oy, oz, wa);
+    const bool rb = abs(oy - dy) <= R && abs(oz - dz) <= R && row_halfwidth_f<DIM>(P, B, oy - dy, oz - dz, wb);
+    if (!ra && !rb) return RowRanges{0u, 0u, 0u, 0u};
+    const float wac = fmar(wa, P.cellx, P.cslack), wbc = fmar(wb, P.cellx, P.cslack);
+    const float xb = A.xc + dxc;
+    float lo = ra ? A.xc - wac : xb - wbc;
+    float hi = ra ? A.xc + wac : xb + wbc;
     if (ra && rb) {
-        lo = min(lo, d - (int64_t)wb);
-        hi = max(hi, d + (int64_t)wb);
+        lo = fminf(lo, xb - wbc);
+        hi = fmaxf(hi, xb + wbc);
     }
-    const uint32_t row = row_base(P, wrap_row(P, A.ry + oy), (DIM == 3) ? wrap_row(P, A.rz + oz) : 0);
-    uint32_t k0, k1, k2, k3;
-    if (hi - lo >= (int64_t)4294967296ll - (int64_t)(4294967296ull / P.nfx) - 2) {  // the whole row
-        k0 = row;
-        k1 = row + P.nfx * P.nsub - 1u;
-        k2 = 1u;
-        k3 = 0u;
-    } else {
-        window_cells(P, row, A.ux + (uint32_t)lo, A.ux + (uint32_t)hi, k0, k1, k2, k3);
-    }
-    r.s0 = cs[k0];
-    r.e0 = cs[k1 + 1];
-    if (k2 <= k3) {
-        r.s1 = cs[k2];
-        r.e1 = cs[k3 + 1];
-    }
-    return r;
+    const int yy = wrap_row(P, A.ry + oy);
+    const int zz = (DIM == 3) ? wrap_row(P, A.rz + oz) : 0;
+    return window_ranges(P, cs, row_base(P, yy, zz), lo, hi);
 }
 
 template <int DIM>
 __device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_t* __restrict__ cs, const Target& A,
                                                 const Target& B, int dy, int dz, uint2* list, uint32_t stride) {
-    const int ny = 2 * P.R + 1 + (dy != 0 ? 1 : 0);
-    const int nz = (DIM == 3) ? 2 * P.R + 1 + (dz != 0 ? 1 : 0) : 1;
+    const int R = P.R;
+    const int ny = 2 * R + 1 + (dy != 0 ? 1 : 0);
+    const int nz = (DIM == 3) ? 2 * R + 1 + (dz != 0 ? 1 : 0) : 1;
     const int nrows = ny * nz;
+    const int oy0 = min(0, dy) - R, oy1 = oy0 + ny - 1;
+    int oy = oy0, oz = (DIM == 3) ? min(0, dz) - R : 0;  // the row of j, stepped on (oy fastest)
+    const float dxc = (float)(int32_t)(B.ux - A.ux) * P.cellx;
     ListWriter w(list, stride);
     // two rows at a time: their cell-start loads are in flight together
     for (int j = 0; j < nrows; j += 2) {
@@ -415,7 +404,11 @@ __device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             r[q] = RowRanges{0u, 0u, 0u, 0u};
-            if (j + q < nrows) r[q] = union_row<DIM>(P, cs, A, B, dy, dz, j + q);
+            if (j + q < nrows) r[q] = union_row<DIM>(P, cs, A, B, dxc, dy, dz, oy, oz);
+            if (++oy > oy1) {
+                oy = oy0;
+                ++oz;
+            }
         }
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
