@@ -188,9 +188,10 @@ int ade_set_velocities(ade_ctx *ctx, const double *d_v);
  * a plume share a position (and synchronises the stream for that): the sum
  * of Eq. (4) leaves out pairs at r = 0, and when no two particles coincide
  * the only candidate at r = 0 is a target's own record, whose term is zero,
- * so the FP32 Wendland C4 pair kernels skip the test (results unchanged;
- * every step keeps the relative positions of a plume's particles, so the
- * check holds for the run).  ade_load_state repeats the check. */
+ * so the FP32 Wendland C4 pair kernels skip the test (the same sums but for
+ * a rounding of r^2 where it sits on a tie; every step keeps the relative
+ * positions of a plume's particles, so the check holds for the run).
+ * ade_load_state repeats the check. */
 int ade_build_cells(ade_ctx *ctx);
 
 /* *out = 1 when two particles of a plume share a position (or the context

@@ -55,7 +55,9 @@ constexpr double kPolyScale = (KERN == 4) ? 6.0 : 1.0;
 // ZC (zero separations): two distinct particles may share a position, so a
 // candidate at r = 0 is cut by a select.  Without ZC the only candidate at
 // r = 0 is the target's own record (a padding slot re-reads it): r^2 starts
-// from a tiny offset, which leaves every r^2 >= 1 (grid units) unchanged and
+// from a tiny offset (2^-40 in FP32), far below half a unit in the last place
+// of any r^2 >= 1 (grid units), so it changes such an r^2 only where the
+// exact sum sits on a rounding tie (then by one unit in the last place); it
 // keeps the self term finite, and the self term is w (C_a - C_a) = 0 exactly.
 template <typename real>
 constexpr real kTinyR2 = sizeof(real) == 4 ? (real)9.094947017729282e-13 : (real)7.888609052210118e-31;  // 2^-40, 2^-100
