@@ -18,10 +18,12 @@
 // the kernel factor is evaluated as w^4 (w - 5/6 w^2) = (1 - q)^5 (1 + 5q) / 6
 // (w = 1 - q), the 6 going with that constant factor.
 //
-// Neighbour predicate (shared with the neighbour-list export): d = (int32)
-// (u_a - u_b) per component (the two's-complement wrap is the minimum image),
-// converted to the working precision, r2 = d_x d_x, r2 = fma(d_y, d_y, r2)
-// [, r2 = fma(d_z, d_z, r2)], pair iff 0 < r2 <= H_u^2 (inclusive support).
+// Neighbour predicate (the neighbour-list export applies it exactly): d =
+// (int32)(u_a - u_b) per component (the two's-complement wrap is the minimum
+// image), converted to the working precision, r2 = d_x d_x, r2 = fma(d_y,
+// d_y, r2) [, r2 = fma(d_z, d_z, r2)], pair iff 0 < r2 <= H_u^2 (inclusive
+// support).  The pair sum imposes r <= H through the kernel factor, which is
+// 0 at q = 1 (clamp of 1 - q at 0), and r > 0 as PairTerm describes.
 //
 // Candidates: particles are sorted by (row, x cell), rows being a grid of
 // height >= Hc / R in y (and z).  For each of the (2R+1)^(d-1) rows around a
@@ -40,11 +42,9 @@
 
 namespace ade {
 
-// One candidate: predicate and pair term, evaluated without a branch (the
-// lanes of a wavefront almost never all fail the predicate together) and
-// kept only inside the support.  Outside it, and for r2 = 0 where the
-// reciprocal square root is infinite, the discarded value may be anything;
-// it is never added.
+// One candidate: the pair term, evaluated without a branch (the lanes of a
+// wavefront almost never all fail the predicate together); the kernel factor
+// vanishes outside the support, and a candidate at r = 0 adds nothing.
 // the constant the kernel factor of the pair term leaves out: its value at q = 0
 template <int KERN>
 constexpr double kPolyScale = (KERN == 4) ? 6.0 : 1.0;
