@@ -204,16 +204,22 @@ struct Cursor {
 // ranges, fetched B at a time with the next batch in flight while the
 // current one is evaluated; slots past the end of the list re-read record
 // `self` and are passed to eval with keep = false.  The wavefront runs as
-// many batches as its longest list needs.
+// many batches as its longest list needs; in the batches where every lane
+// still has records, the slots need no end-of-list test and eval gets
+// keep = true as a constant.
 template <int B, typename Fetch, typename Eval>
 __device__ __forceinline__ void walk_stream(const uint2* list, uint32_t stride, uint32_t total, uint32_t self,
                                             Fetch&& fetch, Eval&& eval) {
     using CandT = decltype(fetch(0u));
-    uint32_t share = total;
+    uint32_t share = total, least = total;
 #pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
+        least = min(least, (uint32_t)__shfl_xor((int)least, o, kWave));
+    }
     const uint32_t nb = __builtin_amdgcn_readfirstlane((share + B - 1) / B);
     if (nb == 0) return;
+    const uint32_t nfull = __builtin_amdgcn_readfirstlane(least / B);
     Cursor<1> cur;
     cur.b = 0;
     cur.e = 0;
@@ -223,35 +229,49 @@ __device__ __forceinline__ void walk_stream(const uint2* list, uint32_t stride, 
     cur.settle();
     __builtin_amdgcn_s_waitcnt(0);
     CandT c0[B], c1[B];
-    auto fill = [&](CandT(&c)[B]) {
+    auto fill = [&](CandT(&c)[B], uint32_t it) {
         uint32_t idx[B];
+        if (it < nfull) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) {
-            idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
-            cur.b += Cursor<1>::kStep;
-            cur.settle();
+            for (int q = 0; q < B; ++q) {
+                idx[q] = cur.b;
+                cur.b += Cursor<1>::kStep;
+                cur.settle();
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < B; ++q) {
+                idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
+                cur.b += Cursor<1>::kStep;
+                cur.settle();
+            }
         }
 #pragma unroll
         for (int q = 0; q < B; ++q) c[q] = fetch(idx[q]);
         __builtin_amdgcn_sched_barrier(0);
     };
     auto run = [&](const CandT(&c)[B], uint32_t batch) {
+        if (batch < nfull) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) eval(c[q], batch * B + q < total);
+            for (int q = 0; q < B; ++q) eval(c[q], true);
+        } else {
+#pragma unroll
+            for (int q = 0; q < B; ++q) eval(c[q], batch * B + q < total);
+        }
     };
-    fill(c0);
+    fill(c0, 0u);
     for (uint32_t it = 1;; it += 2) {
         if (it >= nb) {
             run(c0, it - 1);
             break;
         }
-        fill(c1);
+        fill(c1, it);
         run(c0, it - 1);
         if (it + 1 >= nb) {
             run(c1, it);
             break;
         }
-        fill(c0);
+        fill(c0, it + 1);
         run(c1, it);
     }
 }
