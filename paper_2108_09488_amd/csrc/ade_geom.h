@@ -97,9 +97,10 @@ __device__ __forceinline__ bool row_halfwidth(const PlumeDev& P, const Target& T
 }
 
 // First cell of row (yy, zz) of a plume (row indices already wrapped; the
-// plan keeps nr, nfx and nsub below 2^24, so zz * nr is a 24-bit multiply).
+// plan keeps nr, nfx and nsub, the rows of a plume and the cells of a row
+// below 2^24, so both products are 24-bit multiplies).
 __device__ __forceinline__ uint32_t row_base(const PlumeDev& P, int yy, int zz) {
-    return P.cbase + (__umul24((uint32_t)zz, P.nr) + (uint32_t)yy) * (P.nfx * P.nsub);
+    return P.cbase + __umul24(__umul24((uint32_t)zz, P.nr) + (uint32_t)yy, P.nfx * P.nsub);
 }
 
 // y in -nr .. 2 nr - 1 wrapped into 0 .. nr - 1 (as unsigned values, the

@@ -204,9 +204,11 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
             nfx = std::max(nfx, std::floor(1.0 / side));
             nsub = std::max(1.0, std::floor(1.0 / nr / side));
         }
-        // the kernels index x cells and sub-rows with 24-bit multiplies
+        // the kernels index x cells, sub-rows and rows with 24-bit multiplies
         if (nfx >= 16777216.0 || nsub >= 16777216.0 || nr >= 16777216.0)
             return fail(ADE_EINVAL, "plume %d: more than 2^24 cells along an axis", p);
+        if (nfx * nsub >= 16777216.0 || std::pow(nr, pl.dim - 1) >= 16777216.0)
+            return fail(ADE_EINVAL, "plume %d: more than 2^24 cells in a row or rows in the plume", p);
         d.nr = (uint32_t)nr;
         d.nfx = (uint32_t)nfx;
         d.nsub = (uint32_t)nsub;
