@@ -61,7 +61,7 @@ def lib() -> ct.CDLL:
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2108_09488_amd.build` "
                           "(the HIP library has no fallback)")
     L = ct.CDLL(LIB_PATH)
     p, i32, i64, sz = ct.c_void_p, ct.c_int32, ct.c_int64, ct.c_size_t
