@@ -18,6 +18,10 @@ __device__ __forceinline__ double rsqrt_r(double x) { return 1.0 / sqrt(x); }
 // that forms x
 __device__ __forceinline__ float clamp_unit(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
 __device__ __forceinline__ double clamp_unit(double x) { return x > 0.0 ? (x < 1.0 ? x : 1.0) : 0.0; }
+// max(x, 0) of an x <= 1 (1 - q with q >= 0; NaN to 0): for FP32 the clamp
+// bit of the instruction that forms x, one compare and select for FP64
+__device__ __forceinline__ float pos_unit(float x) { return __builtin_amdgcn_fmed3f(x, 0.0f, 1.0f); }
+__device__ __forceinline__ double pos_unit(double x) { return x > 0.0 ? x : 0.0; }
 
 template <typename real>
 __device__ __forceinline__ real h2_of(const PlumeDev& P) {

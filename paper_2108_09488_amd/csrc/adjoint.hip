@@ -45,7 +45,7 @@ namespace ade {
 template <typename real, int KERN>
 __device__ __forceinline__ real kernel_shape(real q) {
     real omq = (real)1 - q;
-    omq = omq > (real)0 ? omq : (real)0;
+    omq = pos_unit(omq);
     const real o2 = omq * omq;
     if (KERN == 4) return o2 * o2 * o2 * fmar(q, fmar((real)(35.0 / 3.0), q, (real)6), (real)1);
     return o2 * o2 * fmar((real)4, q, (real)1);
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(256) void k_adjoint(const PlumeDev* __restrict__ pl
         const real rinv = rsqrt_r(r2);
         const real q = r2 * rinv * invHu;
         real omq = (real)1 - q;
-        omq = omq > (real)0 ? omq : (real)0;
+        omq = pos_unit(omq);
         real f;
         if (KERN == 4) {
             const real o2 = omq * omq;

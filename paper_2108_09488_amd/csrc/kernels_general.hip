@@ -251,7 +251,7 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
         const bool in = keep && r2 > (real)0;
         const real rinv = rsqrt_r(r2 > (real)1 ? r2 : (real)1);
         real omq = fmar(-(r2 * rinv), invHu, (real)1);
-        omq = omq > (real)0 ? omq : (real)0;
+        omq = pos_unit(omq);
         real f;
         if (KERN == 4) {  // (1 - q)^5 (1 + 5q) / 6
             const real o2 = omq * omq;
@@ -443,7 +443,7 @@ __global__ __launch_bounds__(256) void k_adjoint_gen(AdjGenLaunch g) {
         const real rinv = rsqrt_r(r2);
         const real q = r2 * rinv * invHu;
         real omq = (real)1 - q;
-        omq = omq > (real)0 ? omq : (real)0;
+        omq = pos_unit(omq);
         real f;
         if (KERN == 4) {
             const real o2 = omq * omq;
