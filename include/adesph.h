@@ -92,10 +92,11 @@ typedef struct {
                            1..4; 0 = default (2, or 4 for more than 2000
                            expected neighbours per particle)                */
     int32_t cell_xsub;  /* cell grid: cells per support radius along x,
-                           1..16; 0 = default (8 in 2D, 12 for a 2D plume
-                           of 80 or more expected neighbours, 16 in 3D;
-                           fewer, down to 3, when a context's cell tables
-                           would pass 160 MiB at 40 bytes per cell)         */
+                           1..32; 0 = default (8 in 2D, 12 for a 2D plume
+                           of 80 or more expected neighbours, 16 in 3D, 28
+                           for a 3D plume of 200 or more; fewer, down to 3,
+                           when a context's cell tables would pass 160 MiB
+                           at 40 bytes per cell)                            */
     int32_t reserved;   /* must be 0                                         */
 } ade_params;
 

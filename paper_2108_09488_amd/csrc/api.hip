@@ -153,8 +153,8 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
         if (q.alpha_L < 0 || q.alpha_T < 0 || q.D_m < 0)
             return fail(ADE_EINVAL, "plume %d: dispersivities and D_m must be >= 0", p);
         if (!(q.rho0 > 0) || !(q.mass > 0)) return fail(ADE_EINVAL, "plume %d: rho0 and mass must be positive", p);
-        if (q.cell_rows < 0 || q.cell_rows > 4 || q.cell_xsub < 0 || q.cell_xsub > 16)
-            return fail(ADE_EINVAL, "plume %d: cell_rows in 0..4, cell_xsub in 0..16", p);
+        if (q.cell_rows < 0 || q.cell_rows > 4 || q.cell_xsub < 0 || q.cell_xsub > 32)
+            return fail(ADE_EINVAL, "plume %d: cell_rows in 0..4, cell_xsub in 0..32", p);
 
         PlumeDev d;
         std::memset(&d, 0, sizeof d);
@@ -175,13 +175,21 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
         // the row work (measured: -6% and -8.5% on the 10^6 and 4x10^6
         // paper-scale problems)
         const int rsub = q.cell_rows ? q.cell_rows : (nbar > 2000.0 ? 4 : 2);
-        // a 2D plume of many neighbours does enough pair work per cell that
+        // a plume of many neighbours does enough pair work per cell that
         // narrower x cells (fewer candidates per neighbour) outweigh the
-        // extra cells: H/12 from 80 expected neighbours when the tables fit
-        // (measured on the sweep: its h/dp = 3 plumes, 111 neighbours, take
-        // the pair kernel from 115 to 108.6 us; at 46 neighbours H/12 is slower)
-        const int xsub = q.cell_xsub ? q.cell_xsub
-                                     : (pl.dim == 2 && auto_xsub == 8 && nbar >= 80.0 ? 12 : auto_xsub);
+        // extra cells when the tables fit.  2D: H/12 from 80 expected
+        // neighbours (measured on the sweep: its h/dp = 3 plumes, 111
+        // neighbours, take the pair kernel from 115 to 108.6 us; at 46
+        // neighbours H/12 is slower).  3D: H/28 from 200 (the 128^3 plume, 256
+        // neighbours: 0.99 -> 0.96 ms per graph-replayed step; 96^3 at the
+        // same h: 0.466 -> 0.434 ms; 137 neighbours even, 74 slower), H/16
+        // below.
+        int xsub = q.cell_xsub;
+        if (!xsub) {
+            xsub = auto_xsub;
+            if (pl.dim == 2 && auto_xsub == 8 && nbar >= 80.0) xsub = 12;
+            if (pl.dim == 3 && auto_xsub == 28 && nbar < 200.0) xsub = 16;
+        }
         const double cap = std::max(8.0 * (double)counts[p], 4096.0);
         double nr = std::floor(kTwo32 * rsub / Hc);
         double nfx = std::floor(kTwo32 * xsub / Hc);
@@ -329,7 +337,8 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
 
 // Default x cells per support radius: 8 in 2D, 16 in 3D, where the pencil
 // windows gain more from the narrower cells (the 128^3 plume: 1.19 ms per
-// step against 1.22 at H/8).  A context's cell tables (count, start and an
+// step against 1.22 at H/8), and narrower still for plumes of many
+// neighbours (plan_grid).  A context's cell tables (count, start and an
 // 8-id bucket: 40 bytes per cell) are read and written by every build pass.
 // Past the chip's 256 MB last-level cache (the Infinity Cache) they go to
 // HBM on every pass, so the default x cells of a context whose tables would
@@ -340,10 +349,12 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
 constexpr double kCellTableBudget = 160.0 * 1048576.0;
 
 int plan_build(const ade_params* params, const int64_t* counts, int32_t nplumes, Plan& pl) {
-    static const int k2d[] = {8, 6, 4, 3}, k3d[] = {16, 12, 8, 6, 4, 3};
+    // 3D: H/28 for plumes of 200 or more expected neighbours and H/16 for
+    // the rest, then all at H/16, H/12, ... while the tables do not fit
+    static const int k2d[] = {8, 6, 4, 3}, k3d[] = {28, 16, 12, 8, 6, 4, 3};
     const bool three = params && nplumes > 0 && params[0].dim == 3;
     const int* xs = three ? k3d : k2d;
-    const int nxs = three ? 6 : 4;
+    const int nxs = three ? 7 : 4;
     int rc = plan_grid(params, counts, nplumes, pl, xs[0]);
     bool any_auto = false;
     for (int p = 0; !rc && p < nplumes; ++p) any_auto = any_auto || params[p].cell_xsub == 0;

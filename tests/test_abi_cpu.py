@@ -121,8 +121,8 @@ def test_default_x_cells_coarsen_for_large_cell_tables():
     """A context whose default cell tables (40 bytes per cell) would pass
     160 MiB gets coarser x cells: the 256-plume ensemble (9.6M cells at H/8)
     is sized as with H/3 cells, the six-plume sweep (2M cells) as with H/8
-    (H/12 for its plumes of 111 neighbours), the 128^3 plume as with its 3D default of H/16, and an explicit cell_xsub
-    is kept."""
+    (H/12 for its plumes of 111 neighbours), the 128^3 plume (256 neighbours) as with H/28 and a 3D plume of
+    137 neighbours as with H/16 (the 3D defaults), and an explicit cell_xsub is kept."""
     from paper_2108_09488_amd.context import workspace_bytes
 
     def ws(specs, xsub=0):
@@ -135,5 +135,7 @@ def test_default_x_cells_coarsen_for_large_cell_tables():
     mixed = workspace_bytes([params_from_spec(s, cell_xsub=12 if s.h_over_dp == 3.0 else 8) for s in sweep],
                             [s.n for s in sweep])
     assert ws(sweep) == mixed > ws(sweep, 8)
-    cube = [I.config("cfg3")]  # 3D: H/16 by default
-    assert ws(cube) == ws(cube, 16) > ws(cube, 8)
+    cube = [I.config("cfg3")]  # 3D, 256 neighbours: H/28 by default
+    assert ws(cube) == ws(cube, 28) > ws(cube, 16) > ws(cube, 8)
+    thin = [I.config("cfg3", h_over_dp=1.6)]  # 3D, 137 neighbours: H/16
+    assert ws(thin) == ws(thin, 16) < ws(thin, 28)
