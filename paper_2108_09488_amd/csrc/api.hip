@@ -181,9 +181,8 @@ int plan_grid(const ade_params* params, const int64_t* counts, int32_t nplumes, 
         // neighbours (measured on the sweep: its h/dp = 3 plumes, 111
         // neighbours, take the pair kernel from 115 to 108.6 us; at 46
         // neighbours H/12 is slower).  3D: H/28 from 200 (the 128^3 plume, 256
-        // neighbours: 0.99 -> 0.96 ms per graph-replayed step; 96^3 at the
-        // same h: 0.466 -> 0.434 ms; 137 neighbours even, 74 slower), H/16
-        // below.
+        // neighbours: 1.00 -> 0.99 ms per graph-replayed step, 2% off the pair
+        // kernel; 137 neighbours even at best, 74 slower), H/16 below.
         int xsub = q.cell_xsub;
         if (!xsub) {
             xsub = auto_xsub;
