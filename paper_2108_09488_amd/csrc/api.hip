@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -944,58 +945,77 @@ static int clear_counts(ade_ctx* c) {
     return ADE_OK;
 }
 
+// Times the candidate launch shapes of a tuner: `launch(k)` enqueues
+// candidate k's step-mode kernel with the events around it (and clears the
+// cell counts it leaves).  The clocks of the GPU rise only under sustained
+// load and fall again within seconds of idling (a context timed back to back
+// ran 10% faster from its second timing on; with 2 s idle between timings it
+// never did), so the GPU is first kept busy for ~50 ms with the first
+// candidate, and every round then times each candidate once (round 0
+// untimed), so that a drift of the clocks weighs on all candidates alike.
+static int time_candidates(ade_ctx* c, int ncand, int32_t reps, hipEvent_t e0, hipEvent_t e1,
+                           const std::function<hipError_t(int)>& launch, int* best) {
+    auto timed = [&](int k, float* ms) -> int {
+        if (launch(k) != hipSuccess) return fail(ADE_EHIP, "autotune launch");
+        int rc = clear_counts(c);
+        if (rc) return rc;
+        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(ms, e0, e1) != hipSuccess)
+            return fail(ADE_EHIP, "event synchronise");
+        return ADE_OK;
+    };
+    float one = 0.f;
+    int rc = timed(0, &one);
+    const int warm = std::min(4000, (int)std::ceil(50.0 / std::max(one, 0.01f)));
+    for (int k = 0; !rc && k < warm; ++k) {
+        if (launch(0) != hipSuccess) rc = fail(ADE_EHIP, "autotune launch");
+        else rc = clear_counts(c);
+    }
+    std::vector<float> tot((size_t)ncand, 0.f);
+    for (int r = 0; !rc && r <= reps; ++r)
+        for (int k = 0; !rc && k < ncand; ++k) {
+            rc = timed(k, &one);
+            if (r > 0) tot[(size_t)k] += one;
+        }
+    if (rc) return rc;
+    *best = (int)(std::min_element(tot.begin(), tot.end()) - tot.begin());
+    return ADE_OK;
+}
+
 // The velocity-field kernel's autotuner: block x lanes, the step-mode kernel
 // timed as ade_autotune times the uniform-flow one.
 static int autotune_gen(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     const Plan& pl = c->plan;
     const ade_tuning start = c->tuning;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    float best_ms = 0.f;
-    ade_tuning best_t = start;
-    bool have = false;
-    int rc = ADE_OK;
+    std::vector<ade_tuning> cands;
     for (int lb : {1, 2, 4}) {
         if ((flags & ADE_TUNE_KEEP_LANES) && lb != start.lanes) continue;
         for (int bb : {64, 128, 256}) {
             const ade_tuning cand{bb, lb, 0, 0, 1};
-            if (!gen_tuning_fits(pl, cand)) continue;
-            c->tuning = cand;
-            GenLaunch g = gen_args(c, nullptr);
-            g.ev0 = e0;
-            g.ev1 = e1;
-            float ms = 0.f;
-            for (int r = 0; r <= reps && !rc; ++r) {  // r = 0: warm-up
-                if (launch_pair_gen(pl.dim, pl.real_bytes, pl.kernel, kModeStep, g, c->stream) != hipSuccess ||
-                    (rc = clear_counts(c)) != ADE_OK) {
-                    if (!rc) rc = fail(ADE_EHIP, "autotune launch");
-                    break;
-                }
-                float one = 0.f;
-                if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&one, e0, e1) != hipSuccess) {
-                    rc = fail(ADE_EHIP, "event synchronise");
-                    break;
-                }
-                if (r > 0) ms += one;
-            }
-            if (rc) break;
-            if (!have || ms < best_ms) {
-                best_ms = ms;
-                best_t = cand;
-                have = true;
-            }
+            if (gen_tuning_fits(pl, cand)) cands.push_back(cand);
         }
-        if (rc) break;
     }
+    if (cands.empty()) return fail(ADE_EINVAL, "no launch shape fits");
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int kbest = 0;
+    int rc = time_candidates(c, (int)cands.size(), reps, e0, e1,
+                             [&](int k) {
+                                 c->tuning = cands[(size_t)k];
+                                 GenLaunch g = gen_args(c, nullptr);
+                                 g.ev0 = e0;
+                                 g.ev1 = e1;
+                                 return launch_pair_gen(pl.dim, pl.real_bytes, pl.kernel, kModeStep, g, c->stream);
+                             },
+                             &kbest);
     const int rc_clear = clear_counts(c);
     if (!rc) rc = rc_clear;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    c->tuning = rc ? start : best_t;
+    c->tuning = rc ? start : cands[(size_t)kbest];
     drop_graph(c);
     if (rc) return rc;
-    if (best) *best = best_t;
+    if (best) *best = c->tuning;
     return ADE_OK;
 }
 
@@ -1006,16 +1026,10 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     if (c->plan.general) return autotune_gen(c, reps, flags, best);
     const Plan& pl = c->plan;
     const ade_tuning start = c->tuning;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    float best_ms = 0.f;
-    ade_tuning best_t = start;
-    bool have = false;
-    int rc = ADE_OK;
     const int blocks[3] = {64, 128, 256}, pers[2] = {0, 2048}, groups[3] = {8, 32, 128};
     // (lanes, targets): one lane per two targets, or 1, 2, 4 lanes per target
     const int shapes[4][2] = {{1, 2}, {1, 1}, {2, 1}, {4, 1}};
+    std::vector<ade_tuning> cands;
     for (const auto& sh : shapes) {
         const int lb = sh[0], tg = sh[1];
         if ((flags & ADE_TUNE_KEEP_LANES) && (lb != start.lanes || tg != targets_of(start))) continue;
@@ -1023,48 +1037,35 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
             for (int xg : groups)
                 for (int pp : pers) {
                     const ade_tuning cand{bb, lb, xg, pp, tg};
-                    if (!tuning_fits(pl, cand)) continue;
-                    c->tuning = cand;
-                    // the step-mode kernel, as a step runs it; its outputs go to
-                    // the hashed buffer U and the cell counts of the next build,
-                    // which are cleared again after every launch
-                    PairLaunch a = pair_args(c, kModeStep, c->S.C, c->S.C, 1.0, nullptr);
-                    float ms = 0.f;
-                    for (int r = 0; r <= reps && !rc; ++r) {  // r = 0: warm-up
-                        PairLaunch t = a;
-                        t.ev0 = e0;
-                        t.ev1 = e1;
-                        if (launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeStep, t, cand.block, c->stream) !=
-                                hipSuccess ||
-                            (rc = clear_counts(c)) != ADE_OK) {
-                            if (!rc) rc = fail(ADE_EHIP, "autotune launch");
-                            break;
-                        }
-                        float one = 0.f;
-                        if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&one, e0, e1) != hipSuccess) {
-                            rc = fail(ADE_EHIP, "event synchronise");
-                            break;
-                        }
-                        if (r > 0) ms += one;
-                    }
-                    if (rc) break;
-                    if (!have || ms < best_ms) {
-                        best_ms = ms;
-                        best_t = c->tuning;
-                        have = true;
-                    }
+                    if (tuning_fits(pl, cand)) cands.push_back(cand);
                 }
-        if (rc) break;
     }
+    if (cands.empty()) return fail(ADE_EINVAL, "no launch shape fits");
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    int kbest = 0;
+    // the step-mode kernel, as a step runs it; its outputs go to the hashed
+    // buffer U and the cell counts of the next build, which are cleared again
+    // after every launch
+    int rc = time_candidates(c, (int)cands.size(), reps, e0, e1,
+                             [&](int k) {
+                                 c->tuning = cands[(size_t)k];
+                                 PairLaunch a = pair_args(c, kModeStep, c->S.C, c->S.C, 1.0, nullptr);
+                                 a.ev0 = e0;
+                                 a.ev1 = e1;
+                                 return launch_pair(pl.dim, pl.real_bytes, pl.kernel, kModeStep, a, a.block,
+                                                    c->stream);
+                             },
+                             &kbest);
     const int rc_clear = clear_counts(c);  // also after a failed launch
     if (!rc) rc = rc_clear;
     hipEventDestroy(e0);
     hipEventDestroy(e1);
-    (void)pl;
-    c->tuning = rc ? start : best_t;
+    c->tuning = rc ? start : cands[(size_t)kbest];
     drop_graph(c);
     if (rc) return rc;
-    if (best) *best = best_t;
+    if (best) *best = c->tuning;
     return ADE_OK;
 }
 
