@@ -60,6 +60,11 @@ def step_kernel_name(tuning, dim=2, coincident=False):
     the last template argument: whether it tests every candidate for r > 0,
     which it does only in a context where two particles share a position)."""
     zc = "true" if coincident else "false"
+    if tuning.get("targets", 1) == 2 and tuning["lanes"] == 4:
+        # two targets a quad (3D, no coincident particles; else one a quad)
+        if dim == 3 and not coincident:
+            return "k_pair42<3, float, 4, 0, false>"
+        return f"k_pair<{dim}, float, 4, 0, 4, {zc}>"
     if tuning.get("targets", 1) == 2:
         return f"k_pair2<{dim}, float, 4, 0, {zc}>"
     return f"k_pair<{dim}, float, 4, 0, {tuning['lanes']}, {zc}>"

@@ -160,6 +160,67 @@ __device__ __forceinline__ uint32_t build_list_group(const PlumeDev& P, const ui
     return total;
 }
 
+// The same cooperative build over any block of ny x nz rows starting at row
+// offsets (oy0, oz0) (oy fastest), the ranges of row (oy, oz) given by
+// rows(oy, oz): for two neighbouring targets served by the four lanes of a
+// quad, whose rows are union_row's arcs (G = 4).
+template <typename RowFn>
+__device__ __forceinline__ uint32_t build_rows_quad(RowFn&& rows, int ny, int nz, int oy0, int oz0, uint2* list,
+                                                    uint32_t stride) {
+    constexpr int G = 4;
+    constexpr int kPrev = 0x90, kPrev2 = 0x40, kLast = 0xFF;  // as in build_list_group, G = 4
+    const uint32_t g = threadIdx.x & (G - 1);
+    const int nrows = ny * nz, oy1 = oy0 + ny - 1;
+    auto step = [&](int& oy, int& oz, int n) {  // n <= 2 ny
+        oy += n;
+        if (oy > oy1) {
+            oy -= ny;
+            ++oz;
+        }
+        if (oy > oy1) {
+            oy -= ny;
+            ++oz;
+        }
+    };
+    uint32_t base = 0, total = 0;
+    uint32_t pS = 0, pE = 0;  // main range of the row before the round (end 0: none)
+    int oy = oy0, oz = oz0;
+    step(oy, oz, (int)g);
+    for (int j0 = 0; j0 < nrows; j0 += G) {
+        RowRanges r{0u, 0u, 0u, 0u};
+        if (j0 + (int)g < nrows) r = rows(oy, oz);
+        step(oy, oz, G);
+        const bool hasL = r.e1 > r.s1, hasH = r.e0 > r.s0;
+        const uint32_t hS = hasH ? r.s0 : 0u, hE = hasH ? r.e0 : 0u;
+        uint32_t qS = quad_perm<kPrev>(hS), qE = quad_perm<kPrev>(hE);
+        if (g == 0) {
+            qS = pS;
+            qE = pE;
+        }
+        const bool mergeL = hasL && qE != 0u && qE == r.s1;
+        const uint32_t cnt = ((hasL && !mergeL) ? 1u : 0u) + (hasH ? 1u : 0u);
+        uint32_t incl = cnt + (quad_perm<kPrev>(cnt) & (g >= 1 ? ~0u : 0u));
+        incl += quad_perm<kPrev2>(incl) & (g >= 2 ? ~0u : 0u);
+        const uint32_t first = base + incl - cnt;
+        uint32_t pos = first;
+        if (hasL && !mergeL) {
+            list[__umul24(pos, stride)] = make_uint2(r.s1 * kRecBytes, r.e1 * kRecBytes);
+            ++pos;
+        }
+        if (hasH) list[__umul24(pos, stride)] = make_uint2(r.s0 * kRecBytes, r.e0 * kRecBytes);
+        asm volatile("" ::: "memory");
+        if (mergeL) list[__umul24(first - 1u, stride)] = make_uint2(qS * kRecBytes, r.e1 * kRecBytes);
+        total += (r.e1 - r.s1) + (r.e0 - r.s0);
+        base += quad_perm<kLast>(incl);
+        pS = quad_perm<kLast>(hS);
+        pE = quad_perm<kLast>(hE);
+    }
+    list[__umul24(base, stride)] = make_uint2(kListEndStart, kListEndEnd);
+    total += quad_perm<0xB1>(total);
+    total += quad_perm<0x4E>(total);
+    return total;
+}
+
 template <int DIM, int LANES>
 __device__ __forceinline__ uint32_t build_list(const PlumeDev& P, const uint32_t* __restrict__ cs,
                                                const Target& T, uint2* list, uint32_t stride) {

@@ -55,7 +55,10 @@ bool tuning_fits(const Plan& pl, const ade_tuning& t) {
     if (t.block != 64 && t.block != 128 && t.block != 256) return false;
     if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4) return false;
     if (t.targets != 0 && t.targets != 1 && t.targets != 2) return false;
-    if (targets_of(t) == 2 && (t.lanes != 1 || 2 * t.block > kTile)) return false;
+    // two targets: a lane each (block <= 128), or a quad each (3D FP32)
+    if (targets_of(t) == 2 && !((t.lanes == 1 && 2 * t.block <= kTile) ||
+                                (t.lanes == 4 && pl.dim == 3 && pl.real_bytes == 4)))
+        return false;
     return pair_lds_bytes(t.block, t.lanes, tuning_list_cap(pl, t)) <= kPairLdsMax;
 }
 
@@ -1027,8 +1030,9 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     const Plan& pl = c->plan;
     const ade_tuning start = c->tuning;
     const int blocks[3] = {64, 128, 256}, pers[2] = {0, 2048}, groups[3] = {8, 32, 128};
-    // (lanes, targets): one lane per two targets, or 1, 2, 4 lanes per target
-    const int shapes[4][2] = {{1, 2}, {1, 1}, {2, 1}, {4, 1}};
+    // (lanes, targets): one lane per two targets, 1, 2, 4 lanes per target, or
+    // four lanes per two targets (3D FP32; tuning_fits drops it elsewhere)
+    const int shapes[5][2] = {{1, 2}, {1, 1}, {2, 1}, {4, 1}, {4, 2}};
     std::vector<ade_tuning> cands;
     for (const auto& sh : shapes) {
         const int lb = sh[0], tg = sh[1];
@@ -1084,8 +1088,9 @@ int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
         return fail(ADE_EINVAL, "block must be 64, 128 or 256");
     if (t->lanes != 1 && t->lanes != 2 && t->lanes != 4) return fail(ADE_EINVAL, "lanes must be 1, 2 or 4");
     if (t->targets < 0 || t->targets > 2) return fail(ADE_EINVAL, "targets must be 0, 1 or 2");
-    if (targets_of(*t) == 2 && (t->lanes != 1 || t->block > 128))
-        return fail(ADE_EINVAL, "two targets per lane need lanes = 1 and block <= 128");
+    if (targets_of(*t) == 2 && !((t->lanes == 1 && t->block <= 128) ||
+                                 (t->lanes == 4 && c->plan.dim == 3 && c->plan.real_bytes == 4)))
+        return fail(ADE_EINVAL, "two targets need lanes = 1 and block <= 128, or lanes = 4 in 3D FP32");
     if (t->xcd_group < 0 || t->xcd_group > 4096) return fail(ADE_EINVAL, "xcd_group in 0..4096");
     if (!tuning_fits(c->plan, *t))
         return fail(ADE_EINVAL, "candidate lists of %d lists per workgroup need %zu bytes of LDS (max %zu)",

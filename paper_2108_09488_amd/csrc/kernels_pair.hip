@@ -143,11 +143,10 @@ __device__ __forceinline__ Cand<real> unpack(const uint4& r) {
 // which the predicate rejects (r2 = 0).  So every load is unconditional, and
 // the loads of one batch stay in flight, in order, while the previous batch
 // is evaluated.
-template <int LANES, typename Term, typename real, typename Fetch>
-__device__ __forceinline__ void walk_list(const Term& term, const Target& T,
-                                          real Ca, uint32_t self, const uint2* list, uint32_t stride,
-                                          uint32_t total, uint32_t lj, Fetch&& fetch, real& acc) {
-    constexpr int B = Batch<LANES>::value;
+template <int LANES, int B, typename Fetch, typename Eval>
+__device__ __forceinline__ void walk_list_fn(uint32_t self, const uint2* list, uint32_t stride, uint32_t total,
+                                             uint32_t lj, Fetch&& fetch, Eval&& evalrec) {
+    using CandT = decltype(fetch(0u));
     // batches of the wavefront: the largest share of its lanes, in batches
     const uint32_t own = total > lj ? (total - lj + LANES - 1) / LANES : 0u;
     uint32_t share = own, least = own;
@@ -173,22 +172,25 @@ __device__ __forceinline__ void walk_list(const Term& term, const Target& T,
     // nothing older than the first batch is in flight when the loop starts,
     // so both entries into the loop carry the same outstanding loads
     __builtin_amdgcn_s_waitcnt(0);
-    Cand<real> c0[B], c1[B];
+    CandT c0[B], c1[B];
+    bool k0[B], k1[B];  // false: a padding slot
     // fill batch `it`: past the full batches a slot beyond the lane's share
     // re-reads the target's own record
-    auto fill = [&](Cand<real>(&c)[B], uint32_t it) {
+    auto fill = [&](CandT(&c)[B], bool(&keep)[B], uint32_t it) {
         uint32_t idx[B];
         if (it < nfull) {
 #pragma unroll
             for (int q = 0; q < B; ++q) {
                 idx[q] = cur.b;
+                keep[q] = true;
                 cur.b += Cursor<LANES>::kStep;
                 cur.settle();
             }
         } else {
 #pragma unroll
             for (int q = 0; q < B; ++q) {
-                idx[q] = cur.b < cur.e ? cur.b : self * kRecBytes;
+                keep[q] = cur.b < cur.e;
+                idx[q] = keep[q] ? cur.b : self * kRecBytes;
                 cur.b += Cursor<LANES>::kStep;
                 cur.settle();
             }
@@ -198,25 +200,47 @@ __device__ __forceinline__ void walk_list(const Term& term, const Target& T,
         // keep the loads here, ahead of the evaluation they overlap with
         __builtin_amdgcn_sched_barrier(0);
     };
-    auto eval = [&](const Cand<real>(&c)[B]) {
+    auto eval = [&](const CandT(&c)[B], const bool(&keep)[B], uint32_t it) {
+        if (it < nfull) {
 #pragma unroll
-        for (int q = 0; q < B; ++q) term(T, Ca, c[q].x, c[q].y, c[q].z, c[q].C, acc);
+            for (int q = 0; q < B; ++q) evalrec(c[q], true);
+        } else {
+#pragma unroll
+            for (int q = 0; q < B; ++q) evalrec(c[q], keep[q]);
+        }
     };
-    fill(c0, 0u);
+    fill(c0, k0, 0u);
     for (uint32_t it = 1;; it += 2) {
         if (it >= nb) {
-            eval(c0);
+            eval(c0, k0, it - 1);
             break;
         }
-        fill(c1, it);
-        eval(c0);
+        fill(c1, k1, it);
+        eval(c0, k0, it - 1);
         if (it + 1 >= nb) {
-            eval(c1);
+            eval(c1, k1, it);
             break;
         }
-        fill(c0, it + 1);
-        eval(c1);
+        fill(c0, k0, it + 1);
+        eval(c1, k1, it);
     }
+}
+
+// Walk a target's list: every lane evaluates its share of the concatenated
+// ranges in batches of B records.  The wavefront runs as many batches as its
+// longest share needs (a uniform count, from the list totals); a slot past
+// the end of a lane's share re-reads the target's own record (index self),
+// which the predicate rejects (r2 = 0).  So every load is unconditional, and
+// the loads of one batch stay in flight, in order, while the previous batch
+// is evaluated.  (walk_list_fn is the same walk with any evaluation of a
+// record.)
+template <int LANES, typename Term, typename real, typename Fetch>
+__device__ __forceinline__ void walk_list(const Term& term, const Target& T,
+                                          real Ca, uint32_t self, const uint2* list, uint32_t stride,
+                                          uint32_t total, uint32_t lj, Fetch&& fetch, real& acc) {
+    walk_list_fn<LANES, Batch<LANES>::value>(self, list, stride, total, lj, fetch, [&](const Cand<real>& c, bool) {
+        term(T, Ca, c.x, c.y, c.z, c.C, acc);
+    });
 }
 
 // The end of a target's pair sum acc: rhs mode writes the right-hand side
@@ -513,6 +537,119 @@ __device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* 
     if (alone) finish_target<DIM, real, KERN, MODE>(a, P, T2, iB, acc2);
 }
 
+// ---------------------------------------------------------------------------
+// Two neighbouring targets served by the four lanes of a quad (3D FP32, no
+// coincident particles).  The quad lists the union of the two targets' row
+// windows together (build_rows_quad over union_row), its lanes walk the list
+// as four lanes walk one target's (two records a lane a batch), and every
+// record is evaluated for both targets, b's separation formed from a's as in
+// walk_pair.  A wavefront holding a pair that pair_rows does not merge walks
+// each target's own list instead, in two passes (the other target's offset
+// then put 2^31 grid units away, so that its terms vanish), through the same
+// walk.  Padding slots re-read a's record (the pass target's), which adds
+// nothing for it; b keeps only the slots below the lane's share.
+// ---------------------------------------------------------------------------
+template <int DIM, typename real, int KERN, int MODE, bool ZC>
+__device__ __forceinline__ void pair_item42(const PairLaunch& a, const PlumeDev* __restrict__ plumes,
+                                            const TileDev* __restrict__ tiles, uint32_t w, uint2* lds_list) {
+    const uint32_t nq = (uint32_t)a.block / 4u;  // quads (lists) per workgroup
+    const uint32_t tpb = 2u * nq;                // targets per workgroup
+    const uint32_t subs = kTile / tpb;
+    const TileDev t = tiles[w / subs];
+    const uint32_t i0 = t.start + (w % subs) * tpb;
+    if (i0 >= t.end) return;  // whole workgroup: ragged last tile
+    const uint32_t i1 = min(t.end, i0 + tpb);
+    const PlumeDev P = plumes[t.plume];
+    const uint32_t lq = threadIdx.x / 4u, lj = threadIdx.x % 4u;
+    // past the end of a ragged tile a quad keeps a copy of a valid target
+    // (its sums are discarded)
+    const uint32_t ia = i0 + 2u * lq, ib = ia + 1u;
+    const bool actA = ia < i1, actB = ib < i1;
+    const uint32_t iA = actA ? ia : i0, iB = actB ? ib : iA;
+
+    const uint32_t* __restrict__ px = a.spos[0];
+    const uint32_t* __restrict__ py = a.spos[1];
+    const uint32_t* __restrict__ pz = a.spos[2];
+    const real* __restrict__ Cp = static_cast<const real*>(a.Cpair);
+    const uint4* __restrict__ rec = a.rec;
+    auto fetch = [&](uint32_t k) {
+        return unpack<DIM, real>(*reinterpret_cast<const uint4*>(reinterpret_cast<const char*>(rec) + k));
+    };
+    auto target = [&](uint32_t k) { return make_target<DIM>(P, px[k], py[k], (DIM == 3) ? pz[k] : 0u); };
+    int pry = 0, prz = 0;
+    const bool close = pair_rows<DIM>(P, target(iA), target(iB), pry, prz);
+    const bool merged = __builtin_amdgcn_ballot_w64(!close) == 0ull;  // the whole wavefront
+    uint2* list = lds_list + lq;
+    const PairTerm<DIM, real, KERN, ZC> term = make_term<DIM, real, KERN, ZC>(P);
+    real accA = (real)0, accB = (real)0;
+    const int npass = merged ? 1 : 2;
+    for (int pass = 0; pass < npass; ++pass) {
+        // the pass's pair: (a, b), or (a, a) and then (b, b), every step of
+        // the walk the same; the targets are read per pass, so that no more
+        // than their indices lives across the passes
+        const bool second = pass == 1;
+        const uint32_t k0 = second ? iB : iA, k1 = merged ? iB : k0;
+        const Target T0 = target(k0), T1 = target(k1);
+        const real C0 = Cp[k0], C1 = Cp[k1];
+        const int ry = merged ? pry : 0, rz = merged ? prz : 0;
+        const real bx = (real)(int32_t)(T1.ux - T0.ux);
+        const real by = (real)(int32_t)(T1.uy - T0.uy);
+        const real bz = (DIM == 3) ? (real)(int32_t)(T1.uz - T0.uz) : (real)0;
+        uint32_t total = 0;
+        if (actA && !(second && !actB)) {  // the same for the four lanes of a quad
+            const int R = P.R;
+            const int ny = 2 * R + 1 + (ry != 0 ? 1 : 0);
+            const int nz = (DIM == 3) ? 2 * R + 1 + (rz != 0 ? 1 : 0) : 1;
+            const float dxc = (float)(int32_t)(T1.ux - T0.ux) * P.cellx;
+            total = build_rows_quad(
+                [&](int oy, int oz) { return union_row<DIM>(P, a.cell_start, T0, T1, dxc, ry, rz, oy, oz); }, ny, nz,
+                min(0, ry) - R, (DIM == 3) ? min(0, rz) - R : 0, list, nq);
+        } else {
+            list[0] = make_uint2(kListEndStart, kListEndEnd);
+        }
+        real acc0 = (real)0, acc1 = (real)0;
+        walk_list_fn<4, 2>(k0, list, nq, total, lj, fetch, [&](const Cand<real>& c, bool keep) {
+            const real dx = (real)(int32_t)(T0.ux - c.x);
+            const real dy = (real)(int32_t)(T0.uy - c.y);
+            const real dz = (DIM == 3) ? (real)(int32_t)(T0.uz - c.z) : (real)0;
+            term.sep(dx, dy, dz, C0, c.C, true, acc0);
+            term.sep(dx + bx, dy + by, dz + bz, C1, c.C, keep, acc1);
+        });
+        if (second) {
+            accB = acc0;
+        } else {
+            accA = acc0;
+            accB = acc1;
+        }
+    }
+    // the quad's partial sums (fixed order: deterministic); lane 0 finishes
+    // a, lane 1 b
+    accA += __shfl_xor(accA, 1, kWave);
+    accA += __shfl_xor(accA, 2, kWave);
+    accB += __shfl_xor(accB, 1, kWave);
+    accB += __shfl_xor(accB, 2, kWave);
+    if (lj == 0 && actA) finish_target<DIM, real, KERN, MODE>(a, P, target(iA), iA, accA);
+    if (lj == 1 && actB) finish_target<DIM, real, KERN, MODE>(a, P, target(iB), iB, accB);
+}
+
+template <int DIM, typename real, int KERN, int MODE, bool ZC>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pair42(PairLaunch a, const PlumeDev* __restrict__ plumes,
+                                                const TileDev* __restrict__ tiles, uint32_t nwork) {
+    extern __shared__ uint2 lds_list[];
+    if (a.persistent == 0) {
+        pair_item42<DIM, real, KERN, MODE, ZC>(a, plumes, tiles, xcd_remap(blockIdx.x, gridDim.x, a.xcd_group),
+                                               lds_list);
+        return;
+    }
+    const uint32_t nx = 8, x = blockIdx.x % nx, k = blockIdx.x / nx;
+    const uint32_t per_x = (gridDim.x + nx - 1 - x) / nx;
+    for (uint32_t m = k;; m += per_x) {
+        const uint32_t w = xcd_item(x, m, nwork, a.xcd_group);
+        if (w >= nwork) break;
+        pair_item42<DIM, real, KERN, MODE, ZC>(a, plumes, tiles, w, lds_list);
+    }
+}
+
 // Eight wavefronts per SIMD for the FP32 kernels: at most 64 VGPRs and 100
 // SGPRs (kernel arguments are re-read from the argument segment rather than
 // held across the candidate loop).
@@ -639,8 +776,31 @@ static void launch_pair_2(int mode, const PairLaunch& a, hipStream_t s) {
 }
 
 template <int DIM, typename real, int KERN, bool ZC>
+static void launch_pair_42(int mode, const PairLaunch& a, hipStream_t s) {
+    const uint32_t tpb = (uint32_t)a.block / 2u;
+    const uint32_t nwork = a.ntiles * (kTile / tpb);
+    PairLaunch c = a;
+    if (nwork < 8) c.persistent = 0;
+    const uint32_t grid = (c.persistent > 0) ? max(8u, min(nwork, (uint32_t)c.persistent)) : nwork;
+    dim3 g(grid), b(a.block);
+    const size_t shm = pair_lds_bytes(a.block, 4, a.list_cap);
+    auto kern = (mode == kModeStep)   ? k_pair42<DIM, real, KERN, kModeStep, ZC>
+                : (mode == kModeHalf) ? k_pair42<DIM, real, KERN, kModeHalf, ZC>
+                                      : k_pair42<DIM, real, KERN, kModeRhs, ZC>;
+    if (c.ev0)
+        hipExtLaunchKernelGGL(kern, g, b, (uint32_t)shm, s, c.ev0, c.ev1, 0u, c, c.plumes, c.tiles, nwork);
+    else
+        hipLaunchKernelGGL(kern, g, b, shm, s, c, c.plumes, c.tiles, nwork);
+}
+
+template <int DIM, typename real, int KERN, bool ZC>
 static void launch_pair_z(int mode, const PairLaunch& a, hipStream_t s) {
-    if (a.targets == 2) launch_pair_2<DIM, real, KERN, ZC>(mode, a, s);
+    if (a.targets == 2 && a.lanes == 4) {
+        // two targets a quad: 3D FP32 without coincident particles, else one
+        // target a quad
+        if constexpr (DIM == 3 && sizeof(real) == 4 && !ZC) launch_pair_42<DIM, real, KERN, ZC>(mode, a, s);
+        else launch_pair_l<DIM, real, KERN, 4, ZC>(mode, a, s);
+    } else if (a.targets == 2) launch_pair_2<DIM, real, KERN, ZC>(mode, a, s);
     else if (a.lanes == 4) launch_pair_l<DIM, real, KERN, 4, ZC>(mode, a, s);
     else if (a.lanes == 2) launch_pair_l<DIM, real, KERN, 2, ZC>(mode, a, s);
     else launch_pair_l<DIM, real, KERN, 1, ZC>(mode, a, s);
@@ -664,7 +824,8 @@ hipError_t launch_pair(int dim, int real_bytes, int kernel, int mode, const Pair
     (void)block;
     if (a.block <= 0 || a.block > kTile || kTile % a.block != 0) return hipErrorInvalidValue;
     if (a.lanes != 1 && a.lanes != 2 && a.lanes != 4) return hipErrorInvalidValue;
-    if (a.targets != 1 && (a.targets != 2 || a.lanes != 1 || 2 * a.block > kTile)) return hipErrorInvalidValue;
+    if (a.targets != 1 && (a.targets != 2 || !((a.lanes == 1 && 2 * a.block <= kTile) || a.lanes == 4)))
+        return hipErrorInvalidValue;
     if (a.list_cap < 3 || pair_lds_bytes(a.block, a.lanes, a.list_cap) > kPairLdsMax) return hipErrorInvalidValue;
     if (dim == 2) {
         if (real_bytes == 4) {

@@ -30,6 +30,8 @@ def test_shapes_and_kernel_labels():
     assert b.parse_shape("256,4,1,128") == {"block": 256, "lanes": 4, "targets": 1, "xcd_group": 128}
     assert b.step_kernel_name({"lanes": 4, "targets": 1}, dim=3) == "k_pair<3, float, 4, 0, 4, false>"
     assert b.step_kernel_name({"lanes": 1, "targets": 2}, coincident=True) == "k_pair2<2, float, 4, 0, true>"
+    assert b.step_kernel_name({"lanes": 4, "targets": 2}, dim=3) == "k_pair42<3, float, 4, 0, false>"
+    assert b.step_kernel_name({"lanes": 4, "targets": 2}, dim=3, coincident=True) == "k_pair<3, float, 4, 0, 4, true>"
 
 
 def test_roofline_arithmetic():

@@ -282,13 +282,18 @@ def test_coincident_particles(dim):
     xc[:, 500:510] = x[:, 10:20]  # ten particles moved onto ten others (their C differ)
     assert np.any(C[500:510] != C[10:20])
     m = O.model_from_spec(spec)
-    for pos, coincident in ((x, False), (xc, True)):
-        print(f"[case] coincident particles dim={dim} planted={coincident}", flush=True)
+    # in 3D also with two targets a quad (which a context with coincident
+    # particles runs as one target a quad)
+    shapes = [None] + ([dict(block=64, lanes=4, targets=2)] if dim == 3 else [])
+    for (pos, coincident), shape in [(pc, sh) for pc in ((x, False), (xc, True)) for sh in shapes]:
+        print(f"[case] coincident particles dim={dim} planted={coincident} shape={shape}", flush=True)
         ctx = Context([params_from_spec(spec)], [spec.n])
         ctx.init(torch.from_numpy(pos), torch.from_numpy(C))
         assert ctx.coincident()  # unchecked before the cell build
         ctx.build()
         assert ctx.coincident() == coincident
+        if shape:
+            ctx.set_tuning(**shape)
         g = ctx.rhs().double().cpu().numpy()
         r = O.rhs(m, pos, C, v_uniform=spec.velocity(), mass=spec.mass, rho=spec.rho0)
         assert _rel(g, r) < 1e-5
