@@ -632,6 +632,9 @@ __device__ __forceinline__ void pair_item42(const PairLaunch& a, const PlumeDev*
     if (lj == 1 && actB) finish_target<DIM, real, KERN, MODE>(a, P, target(iB), iB, accB);
 }
 
+// Six wavefronts per SIMD: at most 80 VGPRs (101 without the bound, four
+// wavefronts).  A few addresses of the targets' state then spill to scratch
+// outside the walk (72 bytes a lane, written and read once per work item).
 template <int DIM, typename real, int KERN, int MODE, bool ZC>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pair42(PairLaunch a, const PlumeDev* __restrict__ plumes,
                                                 const TileDev* __restrict__ tiles, uint32_t nwork) {
