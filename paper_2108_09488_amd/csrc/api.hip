@@ -55,9 +55,8 @@ bool tuning_fits(const Plan& pl, const ade_tuning& t) {
     if (t.block != 64 && t.block != 128 && t.block != 256) return false;
     if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4) return false;
     if (t.targets != 0 && t.targets != 1 && t.targets != 2) return false;
-    // two targets: a lane each (block <= 128), or a quad each (3D FP32)
-    if (targets_of(t) == 2 && !((t.lanes == 1 && 2 * t.block <= kTile) ||
-                                (t.lanes == 4 && pl.dim == 3 && pl.real_bytes == 4)))
+    // two targets: a lane each (block <= 128), or a quad each (FP32)
+    if (targets_of(t) == 2 && !((t.lanes == 1 && 2 * t.block <= kTile) || (t.lanes == 4 && pl.real_bytes == 4)))
         return false;
     return pair_lds_bytes(t.block, t.lanes, tuning_list_cap(pl, t)) <= kPairLdsMax;
 }
@@ -674,14 +673,19 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
     // 2^18 lanes): two targets per lane from 2^19 particles on (the fastest
     // shape on the 2D sweep), one lane per target from 2^18, two lanes from
     // 2^17, else four; then the next shapes whose candidate lists fit in LDS.
-    // Plumes of thousands of neighbours per particle take four lanes per
-    // target: the 16 targets of a wavefront then walk nearly the same
-    // candidate ranges and share their cache lines (the autotuner's choice on
-    // the 10^6-particle, 31k-neighbour problem).
+    // Plumes of thousands of neighbours per particle, and 3D plumes, take
+    // four lanes per target, or in FP32 four lanes per two neighbouring
+    // targets: the targets of a wavefront then walk nearly the same candidate
+    // ranges and share their cache lines, and a pair of targets shares every
+    // record it fetches (the autotuner's choice on the 10^6-particle,
+    // 31k-neighbour problem: 19.3 ms per pair launch against 22.8 ms for one
+    // target a quad; on the 128^3 plume 0.88-0.90 ms against 0.90-0.92).
     {
         const int64_t N = c->plan.N;
-        const ade_tuning first = c->plan.nbar_max > 2000.0 ? ade_tuning{128, 4, 128, 0, 1}
-                                 : N >= (1 << 19)          ? ade_tuning{64, 1, 0, 0, 2}
+        const bool quads = c->plan.nbar_max > 2000.0 || c->plan.dim == 3;
+        const int qtargets = c->plan.real_bytes == 4 ? 2 : 1;
+        const ade_tuning first = quads ? ade_tuning{c->plan.dim == 3 ? 64 : 128, 4, 128, 0, qtargets}
+                                 : N >= (1 << 19) ? ade_tuning{64, 1, 0, 0, 2}
                                  : N >= (1 << 18) ? ade_tuning{256, 1, 0, 0, 1}
                                  : N >= (1 << 17) ? ade_tuning{256, 2, 0, 0, 1}
                                                   : ade_tuning{256, 4, 0, 0, 1};
@@ -1031,7 +1035,7 @@ int ade_autotune(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     const ade_tuning start = c->tuning;
     const int blocks[3] = {64, 128, 256}, pers[2] = {0, 2048}, groups[3] = {8, 32, 128};
     // (lanes, targets): one lane per two targets, 1, 2, 4 lanes per target, or
-    // four lanes per two targets (3D FP32; tuning_fits drops it elsewhere)
+    // four lanes per two targets (FP32; tuning_fits drops it for FP64)
     const int shapes[5][2] = {{1, 2}, {1, 1}, {2, 1}, {4, 1}, {4, 2}};
     std::vector<ade_tuning> cands;
     for (const auto& sh : shapes) {
@@ -1088,9 +1092,8 @@ int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
         return fail(ADE_EINVAL, "block must be 64, 128 or 256");
     if (t->lanes != 1 && t->lanes != 2 && t->lanes != 4) return fail(ADE_EINVAL, "lanes must be 1, 2 or 4");
     if (t->targets < 0 || t->targets > 2) return fail(ADE_EINVAL, "targets must be 0, 1 or 2");
-    if (targets_of(*t) == 2 && !((t->lanes == 1 && t->block <= 128) ||
-                                 (t->lanes == 4 && c->plan.dim == 3 && c->plan.real_bytes == 4)))
-        return fail(ADE_EINVAL, "two targets need lanes = 1 and block <= 128, or lanes = 4 in 3D FP32");
+    if (targets_of(*t) == 2 && !((t->lanes == 1 && t->block <= 128) || (t->lanes == 4 && c->plan.real_bytes == 4)))
+        return fail(ADE_EINVAL, "two targets need lanes = 1 and block <= 128, or lanes = 4 in FP32");
     if (t->xcd_group < 0 || t->xcd_group > 4096) return fail(ADE_EINVAL, "xcd_group in 0..4096");
     if (!tuning_fits(c->plan, *t))
         return fail(ADE_EINVAL, "candidate lists of %d lists per workgroup need %zu bytes of LDS (max %zu)",

@@ -799,9 +799,9 @@ static void launch_pair_42(int mode, const PairLaunch& a, hipStream_t s) {
 template <int DIM, typename real, int KERN, bool ZC>
 static void launch_pair_z(int mode, const PairLaunch& a, hipStream_t s) {
     if (a.targets == 2 && a.lanes == 4) {
-        // two targets a quad: 3D FP32 without coincident particles, else one
+        // two targets a quad: FP32 without coincident particles, else one
         // target a quad
-        if constexpr (DIM == 3 && sizeof(real) == 4 && !ZC) launch_pair_42<DIM, real, KERN, ZC>(mode, a, s);
+        if constexpr (sizeof(real) == 4 && !ZC) launch_pair_42<DIM, real, KERN, ZC>(mode, a, s);
         else launch_pair_l<DIM, real, KERN, 4, ZC>(mode, a, s);
     } else if (a.targets == 2) launch_pair_2<DIM, real, KERN, ZC>(mode, a, s);
     else if (a.lanes == 4) launch_pair_l<DIM, real, KERN, 4, ZC>(mode, a, s);
