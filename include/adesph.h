@@ -114,15 +114,19 @@ typedef struct {
  * holding the candidates of both, 8 * (P * (S + 3) + 2) bytes per lane with
  * S = 2R+1 rows and P = 1 (2D) or S + 1 (3D) planes, and evaluates every
  * candidate it loads for both targets, halving the candidate loads per pair
- * evaluated.  The summation order, and so the last bits of the result,
- * depend on lanes and targets and on nothing else here.  A new context starts
- * with the fewest lanes per particle that keep about 4 wavefronts per SIMD:
- * block 64 with two targets per lane from 2^19 particles on, else 256
- * threads with 1 (from 2^18), 2 (from 2^17) or 4 lanes per target; a
- * context with a plume of more than 2000 expected neighbours per particle
- * starts with block 128, 4 lanes per target, xcd_group 128; when the lists
- * do not fit, the first of {256,2}, {256,4}, {128,4}, {64,4} lanes per
- * target that does. */
+ * evaluated.  In FP32, targets = 2 with lanes = 4 gives the four lanes of a
+ * quad two consecutive targets: they list the candidates of both together
+ * (the same bytes per quad as a lane's two-target list) and evaluate every
+ * candidate for both.  The summation order, and so the last bits of the
+ * result, depend on lanes and targets and on nothing else here.  A new
+ * context starts with the fewest lanes per particle that keep about 4
+ * wavefronts per SIMD: block 64 with two targets per lane from 2^19
+ * particles on, else 256 threads with 1 (from 2^18), 2 (from 2^17) or 4
+ * lanes per target; a 3D context, or one with a plume of more than 2000
+ * expected neighbours per particle, starts with 4 lanes per two targets in
+ * FP32 (block 64 in 3D, 128 in 2D) or per target in FP64, xcd_group 128;
+ * when the lists do not fit, the first of {256,2}, {256,4}, {128,4}, {64,4}
+ * lanes per target, or block 64 with two targets per lane, that does. */
 typedef struct {
     int32_t block;          /* threads per workgroup: 64, 128 or 256          */
     int32_t lanes;          /* lanes per target particle: 1, 2 or 4           */
@@ -170,10 +174,12 @@ int ade_init_particles(ade_ctx *ctx, const double *d_x, const void *d_C);
  * the predictor moves it to x + rint((k + 1/2) u_a) - rint(k u_a), the cells
  * are rebuilt there for the corrector, and the corrector completes the step.
  * The pair sum
- * takes the launch shapes block {64, 128, 256} x lanes {1, 2, 4} (one target
- * per group of lanes, no persistent grid; a new context starts with 4 lanes
- * in the largest block whose lists fit), through ade_set_tuning or
- * ade_autotune.  A 2D FP32 velocity-field context holds at most 2^27 - 256
+ * takes the launch shapes block {64, 128, 256} x lanes {1, 2, 4} with one
+ * target per group of lanes, and in 2D FP32 also four lanes per two targets
+ * (targets = 2), no persistent grid, through ade_set_tuning or ade_autotune.
+ * A new context starts with 4 lanes per target in the largest block whose
+ * lists fit, or in 2D FP32 with a plume of more than 2000 expected
+ * neighbours per particle with block 128 and four lanes per two targets.  A 2D FP32 velocity-field context holds at most 2^27 - 256
  * particles (its 32-byte candidate records take 32-bit byte offsets).
  * ade_adjoint takes it
  * (Euler or ADE_PC): its checkpoints then hold the velocities and tensors
@@ -291,8 +297,9 @@ int ade_kernel_timing(ade_ctx *ctx, int32_t mode, double *h_ms, int64_t *h_count
  * kernel's own start and end on the context's stream; the kernel's outputs
  * go to the step's scratch buffers and the next build's cell counts, which
  * are cleared after every launch) over the launch shapes block {64,128,256} x (lanes,
- * targets) {(1,2), (1,1), (2,1), (4,1)} x persistent {0, 8 workgroups per CU}
- * x xcd_group {8, 32, 128} that are valid and fit the LDS limit, keeps the
+ * targets) {(1,2), (1,1), (2,1), (4,1), (4,2)} x persistent {0, 8 workgroups
+ * per CU} x xcd_group {8, 32, 128} that are valid and fit the LDS limit (a
+ * velocity-field context: block x (lanes, targets) only), keeps the
  * fastest in the context and returns it in *best (may be NULL).  With
  * ADE_TUNE_KEEP_LANES the current lanes and targets are kept, so results stay
  * bitwise identical to the untuned context.  Needs built cells; does not

@@ -156,7 +156,8 @@ struct GenLaunch {
     const TileDev* tiles;
     uint32_t ntiles;
     int list_cap;
-    int lanes;              // lanes per target particle: 1, 2 or 4
+    int lanes;              // lanes per target particle: 1, 2 or 4 (per two targets: 4)
+    int targets;            // targets per group of lanes: 1, or 2 (four lanes, 2D FP32)
     int block;              // threads per workgroup: 64, 128 or 256 (its lists fit in LDS)
     StateArrays S, U;
     const uint32_t* cell_start;

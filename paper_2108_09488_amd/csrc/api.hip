@@ -43,12 +43,13 @@ int tuning_list_cap(const Plan& pl, const ade_tuning& t) {
 }
 
 // launch shapes of the velocity-field kernel: one target per group of
-// lanes, no persistent grid
+// lanes, or in 2D FP32 two targets per quad; no persistent grid
 bool gen_tuning_fits(const Plan& pl, const ade_tuning& t) {
     if (t.block != 64 && t.block != 128 && t.block != 256) return false;
     if (t.lanes != 1 && t.lanes != 2 && t.lanes != 4) return false;
-    if (t.targets > 1 || t.persistent != 0) return false;
-    return (size_t)(t.block / t.lanes) * (size_t)pl.list_cap * 8u <= kPairLdsMax;
+    if (t.targets < 0 || t.targets > 2 || t.persistent != 0) return false;
+    if (targets_of(t) == 2 && !(t.lanes == 4 && pl.dim == 2 && pl.real_bytes == 4)) return false;
+    return pair_lds_bytes(t.block, t.lanes, tuning_list_cap(pl, t)) <= kPairLdsMax;
 }
 
 bool tuning_fits(const Plan& pl, const ade_tuning& t) {
@@ -577,8 +578,9 @@ GenLaunch gen_args(ade_ctx* c, void* out) {
     g.plumes = c->plumes;
     g.tiles = c->pair_tiles;
     g.ntiles = c->plan.ntiles;
-    g.list_cap = c->plan.list_cap;
+    g.list_cap = tuning_list_cap(c->plan, c->tuning);
     g.lanes = c->tuning.lanes;
+    g.targets = targets_of(c->tuning);
     g.block = c->tuning.block;
     g.S = c->S;
     g.U = c->U;
@@ -702,10 +704,17 @@ int ade_create(const ade_params* params, const int64_t* counts, int32_t nplumes,
             return fail(ADE_EINVAL, "too many neighbour rows: the candidate lists do not fit in LDS");
         }
         // a velocity field: four lanes per target in the largest workgroup
-        // whose lists fit (its autotuner may choose otherwise)
-        if (c->plan.general)
+        // whose lists fit, or in 2D FP32 for plumes of thousands of
+        // neighbours four lanes per two targets, block 128 (10^6 particles,
+        // 31k neighbours: 44 against 64 ms per update launch; on the 512^2
+        // plumes of 46 and 111 neighbours the same as, or 3% slower than,
+        // one target a quad).  Its autotuner may choose otherwise.
+        if (c->plan.general) {
             for (int bb : {64, 128, 256})
                 if (gen_tuning_fits(c->plan, ade_tuning{bb, 4, 0, 0, 1})) c->tuning = ade_tuning{bb, 4, 0, 0, 1};
+            const ade_tuning q{128, 4, 0, 0, 2};
+            if (c->plan.nbar_max > 2000.0 && gen_tuning_fits(c->plan, q)) c->tuning = q;
+        }
     }
     Bump b(d_ws);
     layout(b, c, c->plan);
@@ -988,16 +997,17 @@ static int time_candidates(ade_ctx* c, int ncand, int32_t reps, hipEvent_t e0, h
     return ADE_OK;
 }
 
-// The velocity-field kernel's autotuner: block x lanes, the step-mode kernel
+// The velocity-field kernel's autotuner: block x (lanes, targets), the step-mode kernel
 // timed as ade_autotune times the uniform-flow one.
 static int autotune_gen(ade_ctx* c, int32_t reps, int32_t flags, ade_tuning* best) {
     const Plan& pl = c->plan;
     const ade_tuning start = c->tuning;
     std::vector<ade_tuning> cands;
-    for (int lb : {1, 2, 4}) {
-        if ((flags & ADE_TUNE_KEEP_LANES) && lb != start.lanes) continue;
+    const int shapes[4][2] = {{1, 1}, {2, 1}, {4, 1}, {4, 2}};  // lanes, targets
+    for (const auto& sh : shapes) {
+        if ((flags & ADE_TUNE_KEEP_LANES) && (sh[0] != start.lanes || sh[1] != targets_of(start))) continue;
         for (int bb : {64, 128, 256}) {
-            const ade_tuning cand{bb, lb, 0, 0, 1};
+            const ade_tuning cand{bb, sh[0], 0, 0, sh[1]};
             if (gen_tuning_fits(pl, cand)) cands.push_back(cand);
         }
     }
@@ -1082,9 +1092,10 @@ int ade_set_tuning(ade_ctx* c, const ade_tuning* t) {
     if (c->plan.general) {
         if (!gen_tuning_fits(c->plan, *t))
             return fail(ADE_EINVAL, "a velocity-field context takes block 64, 128 or 256, lanes 1, 2 or 4, one "
-                                    "target per lane group, no persistent grid, and lists that fit in LDS");
+                                    "target per lane group (or two per quad in 2D FP32), no persistent grid, "
+                                    "and lists that fit in LDS");
         c->tuning = *t;
-        c->tuning.targets = 1;
+        c->tuning.targets = targets_of(*t);
         drop_graph(c);
         return ADE_OK;
     }

@@ -11,7 +11,9 @@
 // own velocities, each on the exact fixed-point schedule of the uniform case
 // (displacement rint((k+1) u_a) - rint(k u_a) at step k, u_a = dt v_a / L
 // 2^32), and are hashed and counted into the next build's cells as there.
-// Four lanes per target walk the target's candidate list (ade_walk.h).  Each
+// One, two or four lanes per target walk the target's candidate list
+// (ade_walk.h), or in 2D FP32 the four lanes of a quad walk the merged list of
+// two neighbouring targets and evaluate every record for both.  Each
 // particle carries the reciprocals of its tensor components, so a harmonic
 // mean costs one add and one reciprocal; in 2D FP32 a candidate is one
 // 32-byte record, elsewhere it is read from the structure-of-arrays state.
@@ -205,96 +207,64 @@ __device__ __forceinline__ void walk_lanes(const uint2* list, uint32_t stride, u
     }
 }
 
-// A work item = blockDim.x / LANES consecutive targets of one tile, LANES
-// lanes per target (the launch shape of the context's tuning).
-template <int DIM, typename real, int KERN, int MODE, int LANES>
-__global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
-    extern __shared__ uint2 lds_list[];
+// The pair term of Eqs. (4)-(5) between target A and candidate c at the
+// separation (dx, dy, dz) = x_a - x_c in grid units: disp gains Dcal_ac / 4
+// f (C_a - C_c) and conv f (v_a - v_c) . x_ac, with f the kernel factor
+// W'(r)/r short of its constant (keep false: the slot adds nothing).
+template <int DIM, typename real, int KERN>
+__device__ __forceinline__ void gen_term(const GPart<DIM, real>& A, const GPart<DIM, real>& c, real dx, real dy,
+                                         real dz, bool keep, real invHu, real gam, real& disp, real& conv) {
+    const real dx2 = dx * dx, dy2 = dy * dy;
+    real r2 = dx2 + dy2;
+    if (DIM == 3) r2 = fmar(dz, dz, r2);
+    // the support is cut by the clamp of 1 - q at 0; r2 = 0 (the target
+    // itself, a padding slot, a coincident particle) by the select below.
+    // Two distinct positions are at least one grid unit apart, so the
+    // clamp of r2 at 1 changes nothing else and keeps every factor finite.
+    const bool in = keep && r2 > (real)0;
+    const real rinv = rsqrt_r(r2 > (real)1 ? r2 : (real)1);
+    real omq = fmar(-(r2 * rinv), invHu, (real)1);
+    omq = pos_unit(omq);
+    real f;
+    if (KERN == 4) {  // (1 - q)^5 (1 + 5q) / 6
+        const real o2 = omq * omq;
+        f = (o2 * o2) * fmar((real)(-5.0 / 6.0), o2, omq);
+    } else {
+        f = omq * omq * omq;
+    }
+    f = in ? f : (real)0;
+    const real ir2 = rinv * rinv;
+    // the pair's harmonic-mean tensor h, divided by 4
+    real quad, tr;
+    if (DIM == 2) {
+        const real hxx = hmean_diag(A.r[0], c.r[0]), hxy = hmean(A.r[1], c.r[1]);
+        const real hyy = hmean_diag(A.r[2], c.r[2]);
+        quad = fmar(hxx, dx2, fmar(hyy, dy2, (hxy + hxy) * (dx * dy)));
+        tr = hxx + hyy;
+    } else {
+        const real hxx = hmean_diag(A.r[0], c.r[0]), hxy = hmean(A.r[1], c.r[1]), hxz = hmean(A.r[2], c.r[2]);
+        const real hyy = hmean_diag(A.r[3], c.r[3]), hyz = hmean(A.r[4], c.r[4]);
+        const real hzz = hmean_diag(A.r[5], c.r[5]);
+        quad = hxx * dx2 + hyy * dy2 + hzz * dz * dz + (real)2 * (hxy * dx * dy + hxz * dx * dz + hyz * dy * dz);
+        tr = hxx + hyy + hzz;
+    }
+    const real dcal = fmar(gam * quad, ir2, -tr);  // Dcal / 4
+    disp = fmar(dcal * f, A.C - c.C, disp);
+    real vx = (A.v[0] - c.v[0]) * dx;
+    vx = fmar(A.v[1] - c.v[1], dy, vx);
+    if (DIM == 3) vx = fmar(A.v[DIM - 1] - c.v[DIM - 1], dz, vx);
+    conv = fmar(f, vx, conv);
+}
+
+// The end of target i's pair sums (disp: the Dcal / 4 terms, conv: the
+// convective ones): rhs mode writes the right-hand side in id order; the
+// other modes update C, move the particle on its own schedule and hash it
+// into the next build's cell counts.
+template <int DIM, typename real, int KERN, int MODE>
+__device__ __forceinline__ void gen_finish(const GenLaunch& g, const PlumeDev& P, const Target& T,
+                                           const GPart<DIM, real>& A, uint32_t i, real disp, real conv) {
     constexpr int NT = GenDims<DIM>::kT;
-    const uint32_t tpb = blockDim.x / LANES, subs = kTile / tpb;
-    const TileDev t = g.tiles[blockIdx.x / subs];
-    const uint32_t i0 = t.start + (blockIdx.x % subs) * tpb;
-    if (i0 >= t.end) return;  // whole workgroup: ragged last tile
-    const uint32_t i1 = min(t.end, i0 + tpb);
-    const PlumeDev P = g.plumes[t.plume];
-    const uint32_t lt = threadIdx.x / LANES, lj = threadIdx.x % LANES;
-    // lanes past the end of a ragged tile stay in the walk (the wavefront
-    // reductions need every lane) with an empty list and target i0
-    const bool active = i0 + lt < i1;
-    const uint32_t i = active ? i0 + lt : i0;
-
     const StateArrays& S = g.S;
-    const GPart<DIM, real> A = load_part<DIM, real>(S, i);
-    const Target T = make_target<DIM>(P, A.x, A.y, A.z);
-
-    // every lane of a target writes the same list
-    uint2* list = lds_list + lt;
-    uint32_t total = 0;
-    if (active) total = build_list<DIM, LANES>(P, g.cell_start, T, list, tpb);
-    else list[0] = make_uint2(kListEndStart, kListEndEnd);
-
-    const real invHu = (real)P.invHu;
-    const real gam = (real)(DIM + 2);
-    real disp = 0, conv = 0;
-    auto fetch = [&](uint32_t k) { return load_part<DIM, real>(S, k / kRecBytes); };
-    auto eval = [&](const GPart<DIM, real>& c, bool keep) {
-        const real dx = (real)(int32_t)(T.ux - c.x);
-        const real dy = (real)(int32_t)(T.uy - c.y);
-        const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - c.z) : (real)0;
-        const real dx2 = dx * dx, dy2 = dy * dy;
-        real r2 = dx2 + dy2;
-        if (DIM == 3) r2 = fmar(dz, dz, r2);
-        // the support is cut by the clamp of 1 - q at 0; r2 = 0 (the target
-        // itself, a padding slot, a coincident particle) by the select below.
-        // Two distinct positions are at least one grid unit apart, so the
-        // clamp of r2 at 1 changes nothing else and keeps every factor finite.
-        const bool in = keep && r2 > (real)0;
-        const real rinv = rsqrt_r(r2 > (real)1 ? r2 : (real)1);
-        real omq = fmar(-(r2 * rinv), invHu, (real)1);
-        omq = pos_unit(omq);
-        real f;
-        if (KERN == 4) {  // (1 - q)^5 (1 + 5q) / 6
-            const real o2 = omq * omq;
-            f = (o2 * o2) * fmar((real)(-5.0 / 6.0), o2, omq);
-        } else {
-            f = omq * omq * omq;
-        }
-        f = in ? f : (real)0;
-        const real ir2 = rinv * rinv;
-        // the pair's harmonic-mean tensor h, divided by 4
-        real quad, tr;
-        if (DIM == 2) {
-            const real hxx = hmean_diag(A.r[0], c.r[0]), hxy = hmean(A.r[1], c.r[1]);
-            const real hyy = hmean_diag(A.r[2], c.r[2]);
-            quad = fmar(hxx, dx2, fmar(hyy, dy2, (hxy + hxy) * (dx * dy)));
-            tr = hxx + hyy;
-        } else {
-            const real hxx = hmean_diag(A.r[0], c.r[0]), hxy = hmean(A.r[1], c.r[1]), hxz = hmean(A.r[2], c.r[2]);
-            const real hyy = hmean_diag(A.r[3], c.r[3]), hyz = hmean(A.r[4], c.r[4]);
-            const real hzz = hmean_diag(A.r[5], c.r[5]);
-            quad = hxx * dx2 + hyy * dy2 + hzz * dz * dz +
-                   (real)2 * (hxy * dx * dy + hxz * dx * dz + hyz * dy * dz);
-            tr = hxx + hyy + hzz;
-        }
-        const real dcal = fmar(gam * quad, ir2, -tr);  // Dcal / 4
-        disp = fmar(dcal * f, A.C - c.C, disp);
-        real vx = (A.v[0] - c.v[0]) * dx;
-        vx = fmar(A.v[1] - c.v[1], dy, vx);
-        if (DIM == 3) vx = fmar(A.v[DIM - 1] - c.v[DIM - 1], dz, vx);
-        conv = fmar(f, vx, conv);
-    };
-    walk_lanes<LANES, kGenBatch>(list, tpb, total, lj, i, fetch, eval);
-    // the lanes of a target combine their sums (fixed order: deterministic)
-    if (LANES >= 2) {
-        disp += __shfl_xor(disp, 1, kWave);
-        conv += __shfl_xor(conv, 1, kWave);
-    }
-    if (LANES >= 4) {
-        disp += __shfl_xor(disp, 2, kWave);
-        conv += __shfl_xor(conv, 2, kWave);
-    }
-    if (!active || lj != 0) return;
-
     // 1/2 of the sum of Dcal terms = 2 disp (disp sums Dcal / 4); x_ab of the
     // convective term is in grid units, L / 2^32 each; the kernel factor f
     // left out its value at q = 0 (6 for C4)
@@ -340,6 +310,158 @@ __global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
     const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
     U.key[i] = key;
     enlist(g.lists, key, id);
+}
+
+// A work item = blockDim.x / LANES consecutive targets of one tile, LANES
+// lanes per target (the launch shape of the context's tuning).
+template <int DIM, typename real, int KERN, int MODE, int LANES>
+__global__ __launch_bounds__(256) void k_pair_gen(GenLaunch g) {
+    extern __shared__ uint2 lds_list[];
+    const uint32_t tpb = blockDim.x / LANES, subs = kTile / tpb;
+    const TileDev t = g.tiles[blockIdx.x / subs];
+    const uint32_t i0 = t.start + (blockIdx.x % subs) * tpb;
+    if (i0 >= t.end) return;  // whole workgroup: ragged last tile
+    const uint32_t i1 = min(t.end, i0 + tpb);
+    const PlumeDev P = g.plumes[t.plume];
+    const uint32_t lt = threadIdx.x / LANES, lj = threadIdx.x % LANES;
+    // lanes past the end of a ragged tile stay in the walk (the wavefront
+    // reductions need every lane) with an empty list and target i0
+    const bool active = i0 + lt < i1;
+    const uint32_t i = active ? i0 + lt : i0;
+
+    const StateArrays& S = g.S;
+    const GPart<DIM, real> A = load_part<DIM, real>(S, i);
+    const Target T = make_target<DIM>(P, A.x, A.y, A.z);
+
+    // every lane of a target writes the same list
+    uint2* list = lds_list + lt;
+    uint32_t total = 0;
+    if (active) total = build_list<DIM, LANES>(P, g.cell_start, T, list, tpb);
+    else list[0] = make_uint2(kListEndStart, kListEndEnd);
+
+    const real invHu = (real)P.invHu;
+    const real gam = (real)(DIM + 2);
+    real disp = 0, conv = 0;
+    auto fetch = [&](uint32_t k) { return load_part<DIM, real>(S, k / kRecBytes); };
+    auto eval = [&](const GPart<DIM, real>& c, bool keep) {
+        const real dx = (real)(int32_t)(T.ux - c.x);
+        const real dy = (real)(int32_t)(T.uy - c.y);
+        const real dz = (DIM == 3) ? (real)(int32_t)(T.uz - c.z) : (real)0;
+        gen_term<DIM, real, KERN>(A, c, dx, dy, dz, keep, invHu, gam, disp, conv);
+    };
+    walk_lanes<LANES, kGenBatch>(list, tpb, total, lj, i, fetch, eval);
+    // the lanes of a target combine their sums (fixed order: deterministic)
+    if (LANES >= 2) {
+        disp += __shfl_xor(disp, 1, kWave);
+        conv += __shfl_xor(conv, 1, kWave);
+    }
+    if (LANES >= 4) {
+        disp += __shfl_xor(disp, 2, kWave);
+        conv += __shfl_xor(conv, 2, kWave);
+    }
+    if (!active || lj != 0) return;
+    gen_finish<DIM, real, KERN, MODE>(g, P, T, A, i, disp, conv);
+}
+
+// Two neighbouring targets a and b served by the four lanes of a quad (2D
+// FP32), as the uniform-flow kernel's quads serve them: the quad lists the
+// union of the two targets' row windows (build_rows_quad over union_row), its
+// lanes walk that list two records a lane a batch, and every record is
+// evaluated for both targets, b's separation formed from a's as
+// (x_b - x_a) + (x_a - x_c).  Each fetched record and each step of the cursor
+// serve two pair terms, and the two terms' reciprocal chains are independent.
+// A wavefront holding a pair that pair_rows does not merge walks each
+// target's own list, in two passes.  Padding slots re-read the pass target's
+// own record (r2 = 0 for it); b keeps only the slots below the lane's share.
+template <int DIM, typename real, int KERN, int MODE>
+__global__ __launch_bounds__(256) void k_pair_gen42(GenLaunch g) {
+    extern __shared__ uint2 lds_list[];
+    const uint32_t nq = blockDim.x / 4u;  // quads (lists) per workgroup
+    const uint32_t tpb = 2u * nq, subs = kTile / tpb;
+    const TileDev t = g.tiles[blockIdx.x / subs];
+    const uint32_t i0 = t.start + (blockIdx.x % subs) * tpb;
+    if (i0 >= t.end) return;  // whole workgroup: ragged last tile
+    const uint32_t i1 = min(t.end, i0 + tpb);
+    const PlumeDev P = g.plumes[t.plume];
+    const uint32_t lq = threadIdx.x / 4u, lj = threadIdx.x % 4u;
+    // past the end of a ragged tile a quad keeps a copy of a valid target
+    // (its sums are discarded)
+    const uint32_t ia = i0 + 2u * lq, ib = ia + 1u;
+    const bool actA = ia < i1, actB = ib < i1;
+    const uint32_t iA = actA ? ia : i0, iB = actB ? ib : iA;
+
+    const StateArrays& S = g.S;
+    auto target = [&](uint32_t k) {
+        return make_target<DIM>(P, S.pos[0][k], S.pos[1][k], (DIM == 3) ? S.pos[2][k] : 0u);
+    };
+    int pry = 0, prz = 0;
+    const bool close = pair_rows<DIM>(P, target(iA), target(iB), pry, prz);
+    const bool merged = __builtin_amdgcn_ballot_w64(!close) == 0ull;  // the whole wavefront
+    uint2* list = lds_list + lq;
+    const real invHu = (real)P.invHu;
+    const real gam = (real)(DIM + 2);
+    auto fetch = [&](uint32_t k) { return load_part<DIM, real>(S, k / kRecBytes); };
+    real dispA = 0, convA = 0, dispB = 0, convB = 0;
+    const int npass = merged ? 1 : 2;
+    for (int pass = 0; pass < npass; ++pass) {
+        // the pass's pair: (a, b), or (a, a) and then (b, b)
+        const bool second = pass == 1;
+        const uint32_t k0 = second ? iB : iA, k1 = merged ? iB : k0;
+        const GPart<DIM, real> A0 = load_part<DIM, real>(S, k0), A1 = load_part<DIM, real>(S, k1);
+        const Target T0 = make_target<DIM>(P, A0.x, A0.y, A0.z), T1 = make_target<DIM>(P, A1.x, A1.y, A1.z);
+        const int ry = merged ? pry : 0, rz = merged ? prz : 0;
+        const real bx = (real)(int32_t)(T1.ux - T0.ux);
+        const real by = (real)(int32_t)(T1.uy - T0.uy);
+        const real bz = (DIM == 3) ? (real)(int32_t)(T1.uz - T0.uz) : (real)0;
+        uint32_t total = 0;
+        if (actA && !(second && !actB)) {  // the same for the four lanes of a quad
+            const int R = P.R;
+            const int ny = 2 * R + 1 + (ry != 0 ? 1 : 0);
+            const int nz = (DIM == 3) ? 2 * R + 1 + (rz != 0 ? 1 : 0) : 1;
+            const float dxc = (float)(int32_t)(T1.ux - T0.ux) * P.cellx;
+            total = build_rows_quad(
+                [&](int oy, int oz) { return union_row<DIM>(P, g.cell_start, T0, T1, dxc, ry, rz, oy, oz); }, ny,
+                nz, min(0, ry) - R, (DIM == 3) ? min(0, rz) - R : 0, list, nq);
+        } else {
+            list[0] = make_uint2(kListEndStart, kListEndEnd);
+        }
+        real d0 = 0, c0 = 0, d1 = 0, c1 = 0;
+        // one record a lane a batch: two targets' terms per record hold the
+        // kernel at 83 VGPRs (five wavefronts per SIMD, no spill); two
+        // records took 127 VGPRs and ran 2-4% slower
+        walk_list_fn<4, 1>(k0, list, nq, total, lj, fetch, [&](const GPart<DIM, real>& c, bool keep) {
+            const real dx = (real)(int32_t)(T0.ux - c.x);
+            const real dy = (real)(int32_t)(T0.uy - c.y);
+            const real dz = (DIM == 3) ? (real)(int32_t)(T0.uz - c.z) : (real)0;
+            gen_term<DIM, real, KERN>(A0, c, dx, dy, dz, true, invHu, gam, d0, c0);
+            gen_term<DIM, real, KERN>(A1, c, dx + bx, dy + by, dz + bz, keep, invHu, gam, d1, c1);
+        });
+        if (second) {
+            dispB = d0;
+            convB = c0;
+        } else {
+            dispA = d0;
+            convA = c0;
+            dispB = d1;
+            convB = c1;
+        }
+    }
+    // the quad's partial sums (fixed order: deterministic); lane 0 finishes
+    // a, lane 1 b
+    dispA += __shfl_xor(dispA, 1, kWave);
+    dispA += __shfl_xor(dispA, 2, kWave);
+    convA += __shfl_xor(convA, 1, kWave);
+    convA += __shfl_xor(convA, 2, kWave);
+    dispB += __shfl_xor(dispB, 1, kWave);
+    dispB += __shfl_xor(dispB, 2, kWave);
+    convB += __shfl_xor(convB, 1, kWave);
+    convB += __shfl_xor(convB, 2, kWave);
+    const bool fa = lj == 0 && actA, fb = lj == 1 && actB;
+    if (!fa && !fb) return;
+    const uint32_t i = fa ? iA : iB;
+    const GPart<DIM, real> A = load_part<DIM, real>(S, i);
+    gen_finish<DIM, real, KERN, MODE>(g, P, make_target<DIM>(P, A.x, A.y, A.z), A, i, fa ? dispA : dispB,
+                                      fa ? convA : convB);
 }
 
 // dD/dtheta_k of Eq. (3) at velocity v, in the stored component order (k =
@@ -588,8 +710,33 @@ static hipError_t launch_gen_l(int mode, const GenLaunch& g, hipStream_t s) {
     return hipGetLastError();
 }
 
+// four lanes per two targets (2D FP32): a work item holds block / 2 targets
+template <int DIM, typename real, int KERN>
+static hipError_t launch_gen_42(int mode, const GenLaunch& g, hipStream_t s) {
+    const uint32_t block = (uint32_t)g.block;
+    if (block != 64 && block != 128 && block != 256) return hipErrorInvalidValue;
+    const size_t shm = (size_t)(block / 4u) * (size_t)g.list_cap * 8u;
+    if (shm > kPairLdsMax || !g.S.grec) return hipErrorInvalidValue;
+    dim3 gr(g.ntiles * (kTile / (block / 2u))), b(block);
+    auto kern = (mode == kModeStep)   ? k_pair_gen42<DIM, real, KERN, kModeStep>
+                : (mode == kModeHalf) ? k_pair_gen42<DIM, real, KERN, kModeHalf>
+                : (mode == kModeFull) ? k_pair_gen42<DIM, real, KERN, kModeFull>
+                                      : k_pair_gen42<DIM, real, KERN, kModeRhs>;
+    if (g.ev0)
+        hipExtLaunchKernelGGL(kern, gr, b, (uint32_t)shm, s, g.ev0, g.ev1, 0u, g);
+    else
+        hipLaunchKernelGGL(kern, gr, b, shm, s, g);
+    return hipGetLastError();
+}
+
 template <int DIM, typename real, int KERN>
 static hipError_t launch_gen_t(int mode, const GenLaunch& g, hipStream_t s) {
+    if (g.targets == 2) {
+        if constexpr (DIM == 2 && sizeof(real) == 4) {
+            if (g.lanes == 4) return launch_gen_42<DIM, real, KERN>(mode, g, s);
+        }
+        return hipErrorInvalidValue;
+    }
     if (g.lanes == 4) return launch_gen_l<DIM, real, KERN, 4>(mode, g, s);
     if (g.lanes == 2) return launch_gen_l<DIM, real, KERN, 2>(mode, g, s);
     if (g.lanes == 1) return launch_gen_l<DIM, real, KERN, 1>(mode, g, s);

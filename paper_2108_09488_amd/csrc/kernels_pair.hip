@@ -142,96 +142,6 @@ __device__ __forceinline__ Cand<real> unpack(const uint4& r) {
 // the end of a lane's share re-reads the target's own record (index self),
 // which the predicate rejects (r2 = 0).  So every load is unconditional, and
 // the loads of one batch stay in flight, in order, while the previous batch
-// is evaluated.
-template <int LANES, int B, typename Fetch, typename Eval>
-__device__ __forceinline__ void walk_list_fn(uint32_t self, const uint2* list, uint32_t stride, uint32_t total,
-                                             uint32_t lj, Fetch&& fetch, Eval&& evalrec) {
-    using CandT = decltype(fetch(0u));
-    // batches of the wavefront: the largest share of its lanes, in batches
-    const uint32_t own = total > lj ? (total - lj + LANES - 1) / LANES : 0u;
-    uint32_t share = own, least = own;
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) {
-        share = max(share, (uint32_t)__shfl_xor((int)share, o, kWave));
-        least = min(least, (uint32_t)__shfl_xor((int)least, o, kWave));
-    }
-    const uint32_t nb = __builtin_amdgcn_readfirstlane((share + B - 1) / B);
-    if (nb == 0) return;
-    // batches in which every lane of the wavefront still has records of its
-    // own: their slots need no end-of-list test
-    const uint32_t nfull = __builtin_amdgcn_readfirstlane(least / B);
-
-    Cursor<LANES> cur;
-    cur.b = lj * kRecBytes;
-    cur.e = 0;
-    cur.lp = list;
-    cur.stride = stride;
-    cur.nx = list[0];
-    cur.settle();
-
-    // nothing older than the first batch is in flight when the loop starts,
-    // so both entries into the loop carry the same outstanding loads
-    __builtin_amdgcn_s_waitcnt(0);
-    CandT c0[B], c1[B];
-    bool k0[B], k1[B];  // false: a padding slot
-    // fill batch `it`: past the full batches a slot beyond the lane's share
-    // re-reads the target's own record
-    auto fill = [&](CandT(&c)[B], bool(&keep)[B], uint32_t it) {
-        uint32_t idx[B];
-        if (it < nfull) {
-#pragma unroll
-            for (int q = 0; q < B; ++q) {
-                idx[q] = cur.b;
-                keep[q] = true;
-                cur.b += Cursor<LANES>::kStep;
-                cur.settle();
-            }
-        } else {
-#pragma unroll
-            for (int q = 0; q < B; ++q) {
-                keep[q] = cur.b < cur.e;
-                idx[q] = keep[q] ? cur.b : self * kRecBytes;
-                cur.b += Cursor<LANES>::kStep;
-                cur.settle();
-            }
-        }
-#pragma unroll
-        for (int q = 0; q < B; ++q) c[q] = fetch(idx[q]);
-        // keep the loads here, ahead of the evaluation they overlap with
-        __builtin_amdgcn_sched_barrier(0);
-    };
-    auto eval = [&](const CandT(&c)[B], const bool(&keep)[B], uint32_t it) {
-        if (it < nfull) {
-#pragma unroll
-            for (int q = 0; q < B; ++q) evalrec(c[q], true);
-        } else {
-#pragma unroll
-            for (int q = 0; q < B; ++q) evalrec(c[q], keep[q]);
-        }
-    };
-    fill(c0, k0, 0u);
-    for (uint32_t it = 1;; it += 2) {
-        if (it >= nb) {
-            eval(c0, k0, it - 1);
-            break;
-        }
-        fill(c1, k1, it);
-        eval(c0, k0, it - 1);
-        if (it + 1 >= nb) {
-            eval(c1, k1, it);
-            break;
-        }
-        fill(c0, k0, it + 1);
-        eval(c1, k1, it);
-    }
-}
-
-// Walk a target's list: every lane evaluates its share of the concatenated
-// ranges in batches of B records.  The wavefront runs as many batches as its
-// longest share needs (a uniform count, from the list totals); a slot past
-// the end of a lane's share re-reads the target's own record (index self),
-// which the predicate rejects (r2 = 0).  So every load is unconditional, and
-// the loads of one batch stay in flight, in order, while the previous batch
 // is evaluated.  (walk_list_fn is the same walk with any evaluation of a
 // record.)
 template <int LANES, typename Term, typename real, typename Fetch>
@@ -366,53 +276,6 @@ __device__ __forceinline__ void pair_item(const PairLaunch& a, const PlumeDev* _
 // rows).  A pair whose rows are further apart (sparse plumes) walks a's own
 // list, then b's.
 // ---------------------------------------------------------------------------
-template <int DIM>
-__device__ __forceinline__ bool pair_rows(const PlumeDev& P, const Target& A, const Target& B, int& dy, int& dz) {
-    const int nr = (int)P.nr, span = 2 * P.R + 1;
-    auto circ = [&](int d) {
-        if (2 * d > nr) d -= nr;
-        if (2 * d < -nr) d += nr;
-        return d;
-    };
-    dy = circ(B.ry - A.ry);
-    dz = (DIM == 3) ? circ(B.rz - A.rz) : 0;
-    // |x_b - x_a| + H_u < 2^31 per axis: then for every neighbour c of b the
-    // integer sum (x_b - x_a) + (x_a - x_c) does not wrap, and walk_pair's
-    // separations of b are those of the minimum image
-    auto near = [&](uint32_t ub, uint32_t ua) {
-        const int32_t d = (int32_t)(ub - ua);
-        return (uint32_t)(d < 0 ? -(int64_t)d : (int64_t)d) + P.hx < 0x80000000u;
-    };
-    const bool close = near(B.ux, A.ux) && near(B.uy, A.uy) && (DIM != 3 || near(B.uz, A.uz));
-    return close && span + 1 <= nr && dy >= -1 && dy <= 1 && dz >= -1 && dz <= 1;
-}
-
-// Sorted-index ranges of the pair's row (oy, oz), offsets from a's row:
-// (s1, e1) is the low part of a row cut by the seam (empty otherwise), (s0,
-// e0) the rest.  The arc is the smallest one holding the windows of the
-// targets that reach the row, taken in x cells in a's frame (b at A.xc +
-// dxc, dxc = (x_b - x_a) in x cells), with the slack of row_ranges_at.
-template <int DIM>
-__device__ __forceinline__ RowRanges union_row(const PlumeDev& P, const uint32_t* __restrict__ cs, const Target& A,
-                                               const Target& B, float dxc, int dy, int dz, int oy, int oz) {
-    const int R = P.R;
-    float wa = 0.f, wb = 0.f;
-    const bool ra = abs(oy) <= R && abs(oz) <= R && row_halfwidth_f<DIM>(P, A, oy, oz, wa);
-    const bool rb = abs(oy - dy) <= R && abs(oz - dz) <= R && row_halfwidth_f<DIM>(P, B, oy - dy, oz - dz, wb);
-    if (!ra && !rb) return RowRanges{0u, 0u, 0u, 0u};
-    const float wac = fmar(wa, P.cellx, P.cslack), wbc = fmar(wb, P.cellx, P.cslack);
-    const float xb = A.xc + dxc;
-    float lo = ra ? A.xc - wac : xb - wbc;
-    float hi = ra ? A.xc + wac : xb + wbc;
-    if (ra && rb) {
-        lo = fminf(lo, xb - wbc);
-        hi = fmaxf(hi, xb + wbc);
-    }
-    const int yy = wrap_row(P, A.ry + oy);
-    const int zz = (DIM == 3) ? wrap_row(P, A.rz + oz) : 0;
-    return window_ranges(P, cs, row_base(P, yy, zz), lo, hi);
-}
-
 template <int DIM>
 __device__ __forceinline__ uint32_t build_union(const PlumeDev& P, const uint32_t* __restrict__ cs, const Target& A,
                                                 const Target& B, int dy, int dz, uint2* list, uint32_t stride) {

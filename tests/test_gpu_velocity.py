@@ -362,16 +362,20 @@ def test_velocity_field_validation():
     with pytest.raises(_lib.AdeError) as e:  # after build
         ctx.set_velocities(v)
     assert e.value.code == _lib.ADE_ESTATE
-    # launch shapes: one target per group of lanes, no persistent grid
-    for bad in (dict(block=128, lanes=1, targets=2), dict(block=256, lanes=4, persistent=64),
-                dict(block=96, lanes=4)):
+    # launch shapes: one target per group of lanes, or two per quad; no
+    # persistent grid
+    for bad in (dict(block=128, lanes=1, targets=2), dict(block=128, lanes=2, targets=2),
+                dict(block=256, lanes=4, persistent=64), dict(block=96, lanes=4)):
         with pytest.raises(_lib.AdeError) as e:
             ctx.set_tuning(**bad)
         assert e.value.code == _lib.ADE_EINVAL
     ctx.set_tuning(block=128, lanes=2)
     assert (ctx.get_tuning()["block"], ctx.get_tuning()["lanes"]) == (128, 2)
+    ctx.set_tuning(block=64, lanes=4, targets=2)
+    assert (ctx.get_tuning()["lanes"], ctx.get_tuning()["targets"]) == (4, 2)
     t = ctx.autotune(reps=1)
-    assert t["lanes"] in (1, 2, 4) and t["targets"] == 1 and t["persistent"] == 0
+    assert t["lanes"] in (1, 2, 4) and t["targets"] in (1, 2) and t["persistent"] == 0
+    assert t["targets"] == 1 or t["lanes"] == 4
     # init clears the velocities: build needs them again
     ctx.init(torch.from_numpy(x), torch.from_numpy(C))
     with pytest.raises(_lib.AdeError) as e:
@@ -383,24 +387,127 @@ def test_velocity_field_validation():
 def test_velocity_field_launch_shapes():
     """Every launch shape of the velocity-field kernel gives the oracle's
     right-hand side (FP32 1e-5, FP64 1e-12), and the same bits for the same
-    lanes per target whatever the workgroup size."""
+    lanes and targets per lane group whatever the workgroup size.  Two
+    targets a quad exist in 2D FP32 only."""
     for dim, rb, n_side in [(2, 4, 80), (2, 8, 48), (3, 4, 18)]:
         spec = _spec(dim, rb, n_side, 4, 1.5)
         v = _field(spec, quantise=False)
         ctx, x, C = _ctx(spec, v)
         r = O.rhs(O.model_from_spec(spec), x, C, v=v, mass=spec.mass, rho=spec.rho0)
-        by_lanes = {}
-        for lanes in (1, 2, 4):
+        by_shape = {}
+        for lanes, targets in ((1, 1), (2, 1), (4, 1), (4, 2)):
             for block in (64, 128, 256):
                 try:
-                    ctx.set_tuning(block=block, lanes=lanes)
+                    ctx.set_tuning(block=block, lanes=lanes, targets=targets)
                 except _lib.AdeError:
-                    continue  # lists do not fit in LDS at this shape
+                    assert targets == 2 and (dim, rb) != (2, 4) or targets == 1
+                    continue  # lists do not fit in LDS at this shape, or no such kernel
                 g = ctx.rhs().cpu().numpy()
                 assert _rel(g.astype(np.float64), r) < (1e-12 if rb == 8 else 1e-5), (dim, rb, block, lanes)
-                if lanes in by_lanes:
-                    assert np.array_equal(g, by_lanes[lanes]), (dim, rb, block, lanes)
+                if (lanes, targets) in by_shape:
+                    assert np.array_equal(g, by_shape[(lanes, targets)]), (dim, rb, block, lanes, targets)
                 else:
-                    by_lanes[lanes] = g
-        assert len(by_lanes) == 3
+                    by_shape[(lanes, targets)] = g
+        assert len(by_shape) == (4 if (dim, rb) == (2, 4) else 3)
         ctx.close()
+
+
+@pytest.mark.parametrize("integrator,n_side,hod,block,steps", [("euler", 61, 1.5, 64, 30), ("euler", 80, 3.0, 256, 10),
+                                                               ("pc", 53, 2.0, 128, 20)])
+def test_velocity_field_two_targets_a_quad(integrator, n_side, hod, block, steps):
+    """Four lanes per two targets (2D FP32): every record of the pair's
+    merged list is evaluated for both targets, b's separation formed from a's.
+    Positions bit-exact and C within 1e-5 of the oracle over Euler or
+    predictor-corrector steps (odd plume sizes: ragged tiles and a last quad
+    with one target), the neighbour sets bit-exact, and the same bits as a
+    second run."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = _spec(2, 4, n_side, 4, hod)
+    x = spec.positions()
+    v = I.velocity_field(x, spec.L, quantum=2.0 ** -19).astype(np.float32).astype(np.float64)
+    C0 = spec.concentration(x).astype(np.float32).astype(np.float64)
+    integ = _lib.ADE_PC if integrator == "pc" else _lib.ADE_EULER
+    outs = []
+    for rep in range(2):
+        print(f"[case] velocity field quads {integrator} n={spec.n} h/dp={hod} block={block} rep={rep}", flush=True)
+        ctx = Context([params_from_spec(spec, integrator=integ, flags=_lib.ADE_VELOCITY_FIELD)], [spec.n])
+        ctx.init(torch.from_numpy(x), torch.from_numpy(C0)).set_velocities(torch.from_numpy(v)).build()
+        ctx.set_tuning(block=block, lanes=4, targets=2)
+        if rep == 0:
+            g = ctx.rhs().double().cpu().numpy()
+            r = O.rhs(O.model_from_spec(spec), x, C0, v=v, mass=spec.mass, rho=spec.rho0)
+            assert _rel(g, r) < 1e-5
+        ctx.step(steps)
+        outs.append((ctx.read_C().cpu().numpy().copy(), ctx.read_x().cpu().numpy().copy()))
+        if rep == 0:
+            xo, Co, _ = O.run(O.model_from_spec(spec), x, C0, spec.dt, steps, v=v, mass=spec.mass, rho=spec.rho0,
+                              integrator=2 if integrator == "pc" else 1)
+            assert np.array_equal(outs[0][1], xo)
+            assert _rel(outs[0][0].astype(np.float64), Co) < 1e-5
+            off, ids = ctx.neighbours()
+            off, ids = off.cpu().numpy(), ids.cpu().numpy()
+            seg = np.repeat(np.arange(len(off) - 1), np.diff(off))
+            ids = ids[np.lexsort((ids, seg))]
+            o_off, o_ids = O.neighbours_fixed(2, xo, spec.L, spec.H, 4)
+            assert np.array_equal(off, o_off) and np.array_equal(ids, o_ids)
+        ctx.close()
+    assert np.array_equal(outs[0][0], outs[1][0]) and np.array_equal(outs[0][1], outs[1][1])
+
+
+def test_velocity_field_default_shape_many_neighbours():
+    """A 2D FP32 velocity-field plume of more than 2000 neighbours per
+    particle starts with four lanes per two targets (block 128): its
+    right-hand side matches the oracle at sampled particles, and a step
+    matches the same context at one target a quad (positions bit-exact)."""
+    spec = _spec(2, 4, 96, 4, 14.0)
+    v = _field(spec)
+    ctx, x, C = _ctx(spec, v)
+    t = ctx.get_tuning()
+    assert (t["block"], t["lanes"], t["targets"]) == (128, 4, 2)
+    g = ctx.rhs().double().cpu().numpy()
+    rng = np.random.default_rng(5)
+    idx = np.sort(rng.choice(spec.n, size=400, replace=False))
+    r = O.rhs(O.model_from_spec(spec), x, C, v=v, mass=spec.mass, rho=spec.rho0, idx=idx)
+    assert _rel(g[idx], r) < 1e-5
+    ctx.step(1)
+    one, _, _ = _ctx(spec, v)
+    one.set_tuning(block=128, lanes=4, targets=1)
+    one.step(1)
+    assert np.array_equal(ctx.read_x().cpu().numpy(), one.read_x().cpu().numpy())
+    assert _rel(ctx.read_C().double().cpu().numpy(), one.read_C().double().cpu().numpy()) < 1e-6
+    ctx.close()
+    one.close()
+
+
+def test_velocity_field_two_targets_unmerged_pairs():
+    """Sparse rows two apart (seven particles each): the two targets of many
+    quads cannot share a list, so those wavefronts walk each target's own
+    list in turn.  The right-hand side and four steps match the oracle."""
+    from paper_2108_09488_amd.context import Context, params_from_spec
+    spec = _spec(2, 4, 16, 4, 1.5)
+    rng = np.random.default_rng(27)
+    # the rows of the default cell grid: nr = floor(2 L / H'), H' the
+    # planner's widened support in grid units
+    hc = spec.H / spec.L * TWO32 * (1 + 2.0 ** -16) + 2
+    nr = int(np.floor(TWO32 * 2 / hc))
+    h = spec.L / nr
+    pts = [[rng.uniform(0, spec.L), (y + rng.uniform(0.2, 0.8)) * h] for y in range(0, nr, 2) for _ in range(7)]
+    x = O.to_fixed(np.array(pts).T.copy(), spec.L).astype(np.float64) / TWO32 * spec.L
+    n = x.shape[1]
+    v = I.velocity_field(x, spec.L, quantum=V_QUANTUM).astype(np.float32).astype(np.float64)
+    C = spec.concentration(x).astype(np.float32).astype(np.float64)
+    print(f"[case] velocity field quads, banded rows n={n}", flush=True)
+    ctx = Context([params_from_spec(spec, flags=_lib.ADE_VELOCITY_FIELD)], [n])
+    ctx.init(torch.from_numpy(x), torch.from_numpy(C)).set_velocities(torch.from_numpy(v)).build()
+    ctx.set_tuning(block=64, lanes=4, targets=2)
+    g = ctx.rhs().double().cpu().numpy()
+    r = O.rhs(O.model_from_spec(spec), x, C, v=v, mass=spec.mass, rho=spec.rho0)
+    assert np.linalg.norm(r) > 0
+    assert _rel(g, r) < 1e-5
+    ctx.step(4)
+    Cg = ctx.read_C().double().cpu().numpy()
+    xg = ctx.read_x().cpu().numpy()
+    xo, Co, _ = O.run(O.model_from_spec(spec), x, C, spec.dt, 4, v=v, mass=spec.mass, rho=spec.rho0)
+    assert np.array_equal(xg, xo)
+    assert _rel(Cg, Co) < 1e-5
+    ctx.close()
