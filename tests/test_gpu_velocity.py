@@ -236,9 +236,11 @@ def test_velocity_field_graph_replay_and_determinism():
         assert np.array_equal(C, outs[0][0]) and np.array_equal(xx, outs[0][1])
 
 
-def test_velocity_field_ensemble_matches_single_plumes():
+@pytest.mark.parametrize("shape", [None, (64, 4, 2)])
+def test_velocity_field_ensemble_matches_single_plumes(shape):
     """Several plumes with velocity fields (different sizes, dispersivities and
-    time steps) in one context step to the same bits as each plume alone."""
+    time steps) in one context step to the same bits as each plume alone, at
+    the default launch shape and at four lanes per two targets."""
     from paper_2108_09488_amd.context import Context, params_from_spec
     specs = [_spec(2, 4, n, 4, h) for n, h in ((24, 1.3), (40, 2.0), (33, 1.5))]
     specs[1].alpha_T = 1e-4
@@ -252,6 +254,8 @@ def test_velocity_field_ensemble_matches_single_plumes():
     ens = Context([params_from_spec(s, flags=flags) for s in specs], [s.n for s in specs])
     ens.init(torch.from_numpy(np.concatenate(xs, axis=1)), torch.from_numpy(np.concatenate(Cs)))
     ens.set_velocities(torch.from_numpy(np.concatenate(vs, axis=1))).build()
+    if shape:
+        ens.set_tuning(block=shape[0], lanes=shape[1], targets=shape[2])
     ens.step(12)
     Ce, xe = ens.read_C().cpu().numpy(), ens.read_x().cpu().numpy()
     ens.close()
@@ -259,6 +263,8 @@ def test_velocity_field_ensemble_matches_single_plumes():
     for s, x, C, v in zip(specs, xs, Cs, vs):
         one = Context([params_from_spec(s, flags=flags)], [s.n])
         one.init(torch.from_numpy(x), torch.from_numpy(C)).set_velocities(torch.from_numpy(v)).build()
+        if shape:
+            one.set_tuning(block=shape[0], lanes=shape[1], targets=shape[2])
         one.step(12)
         assert np.array_equal(one.read_C().cpu().numpy(), Ce[off:off + s.n])
         assert np.array_equal(one.read_x().cpu().numpy(), xe[:, off:off + s.n])
@@ -266,14 +272,16 @@ def test_velocity_field_ensemble_matches_single_plumes():
         off += s.n
 
 
-@pytest.mark.parametrize("rb,K,integrator", [(8, 7, 1), (4, 7, 1), (8, 1, 1), (4, 40, 1),
-                                             (8, 7, 2), (4, 7, 2), (8, 1, 2), (4, 40, 2)])
-def test_velocity_field_adjoint_matches_oracle(rb, K, integrator):
+@pytest.mark.parametrize("rb,K,integrator,quads", [(8, 7, 1, 0), (4, 7, 1, 0), (8, 1, 1, 0), (4, 40, 1, 0),
+                                                   (8, 7, 2, 0), (4, 7, 2, 0), (8, 1, 2, 0), (4, 40, 2, 0),
+                                                   (4, 7, 1, 1), (4, 7, 2, 1)])
+def test_velocity_field_adjoint_matches_oracle(rb, K, integrator, quads):
     """J, the gradient w.r.t. (alpha_L, alpha_T, D_m) and the final state of the
     velocity-field Euler or predictor-corrector run against the oracle's
     discrete adjoint (itself pinned by finite differences), for checkpoints
     every 1, 7 and 40 steps.  Velocities in multiples of 2^-19: half steps
-    are whole fixed-point units too."""
+    are whole fixed-point units too.  quads: the forward and its recompute
+    at four lanes per two targets."""
     from paper_2108_09488_amd.context import Context, params_from_spec
     spec = I.config("cfg5", n_side=48, steps=30, dt=DT_EXACT, real_bytes=rb, jitter=0.1, alpha_L=1e-2,
                     alpha_T=5e-3)
@@ -291,9 +299,11 @@ def test_velocity_field_adjoint_matches_oracle(rb, K, integrator):
     obs, _ = O.sensor_interp(truth, (x + spec.steps * spec.dt * v) % spec.L, CN, xs)
     if rb == 4:
         obs = obs.astype(np.float32).astype(np.float64)
-    print(f"[case] velocity field adjoint rb={rb} K={K} integ={integrator}", flush=True)
+    print(f"[case] velocity field adjoint rb={rb} K={K} integ={integrator} quads={quads}", flush=True)
     ctx = Context([params_from_spec(spec, integrator=integrator, flags=_lib.ADE_VELOCITY_FIELD)], [spec.n])
     ctx.init(torch.from_numpy(x), torch.from_numpy(C0)).set_velocities(torch.from_numpy(v)).build()
+    if quads:
+        ctx.set_tuning(block=128, lanes=4, targets=2)
     J, g = ctx.adjoint(spec.steps, K, torch.from_numpy(xs), torch.from_numpy(obs))
     Jo, go, Co = O.adjoint_field(O.model_from_spec(spec), x, C0, v, spec.dt, spec.steps, xs, obs,
                                  mass=spec.mass, rho=spec.rho0, integrator=integrator)
