@@ -481,6 +481,53 @@ def paper_scale(device, steps=3):
     return out
 
 
+def velocity_paper_scale(device, rounds=3, steps=2):
+    """Table 1's first problem (10^6 particles, ~31k neighbours, FP32) with a
+    velocity per particle (inputs.velocity_field at the paper's flow speed,
+    1.16e-5 m/s): the default launch shape of such plumes (four lanes per two
+    targets) against one target a quad, both contexts stepped in lockstep,
+    the pair kernel timed by HIP events round by round (the particles move
+    under the field, so the rounds differ; the two shapes see the same
+    states)."""
+    import numpy as np
+    import torch
+    from paper_2108_09488_amd import _lib
+    from paper_2108_09488_amd import inputs as I
+    from paper_2108_09488_amd.context import Context, params_from_spec
+
+    s = I.config("paper1m")
+    x = s.positions()
+    C = torch.from_numpy(s.concentration(x).astype(np.float32))
+    v = torch.from_numpy(I.velocity_field(x, s.L, U=1.16e-5))
+    shapes = {"two_targets_a_quad": None, "one_target_a_quad": {"block": 128, "lanes": 4, "targets": 1}}
+    ctxs = {}
+    for k, t in shapes.items():
+        c = Context([params_from_spec(s, flags=_lib.ADE_VELOCITY_FIELD)], [s.n], device=device,
+                    stream=torch.cuda.Stream(device=device))
+        c.init(torch.from_numpy(x), C).set_velocities(v).build()
+        if t:
+            c.set_tuning(**t)
+        ctxs[k] = c
+    inter = int(ctxs["two_targets_a_quad"].neighbour_counts()[-1].item())
+    res = {k: [] for k in shapes}
+    for _ in range(rounds):
+        for k, c in ctxs.items():
+            c.timing_start()
+            c.step(steps)
+            _sync()
+            ms, n = c.timing_stop()
+            res[k].append(ms / n)
+    out = {"particles": s.n, "interactions_per_step_initial": inter, "steps_per_round": steps}
+    for k, c in ctxs.items():
+        out[k] = {"tuning": c.get_tuning(), "pair_kernel_ms_min": min(res[k]), "pair_kernel_ms_rounds": res[k]}
+        c.close()
+    out["speedup"] = out["one_target_a_quad"]["pair_kernel_ms_min"] / out["two_targets_a_quad"]["pair_kernel_ms_min"]
+    print(f"[bench] velocity field, 10^6 particles: pair kernel {out['two_targets_a_quad']['pair_kernel_ms_min']:.1f} "
+          f"ms (two targets a quad) vs {out['one_target_a_quad']['pair_kernel_ms_min']:.1f} ms (one)",
+          file=sys.stderr, flush=True)
+    return out
+
+
 def velocity_field_adjoint(device, steps=200, ckpt=20):
     """The inverse problem of fwd_adjoint (256^2 particles, 1024 sensors, guess
     alpha_L = 1e-2, alpha_T = 5e-3) with the velocity field of
@@ -542,7 +589,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip every workload but the headline")
     ap.add_argument("--extras", default="sweep,batched,fwd_adjoint,velocity_field,paper_scale",
-                    help="comma-separated extras to run (unless --no-extras)")
+                    help="comma-separated extras to run (unless --no-extras); velocity_paper (the "
+                         "10^6-particle problem with a velocity field) only when named")
     ap.add_argument("--cells", default="", help="comma-separated subset of the sweep plumes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size "
@@ -619,6 +667,8 @@ def main():
         print(f"[bench] fwd+adjoint: {extras['fwd_adjoint']['ms_fwd_adjoint']:.1f} ms", file=sys.stderr, flush=True)
     if "paper_scale" in want:
         extras["paper_scale"] = paper_scale(device)
+    if "velocity_paper" in want:
+        extras["velocity_paper"] = velocity_paper_scale(device)
     if "velocity_field" in want:
         vf = velocity_field(device, steps=min(args.steps, 100))
         extras["velocity_field"] = vf
