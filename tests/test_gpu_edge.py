@@ -61,11 +61,12 @@ def test_degenerate_flows(dim, rb, v, aL, aT, Dm):
     ctx.close()
 
 
-@pytest.mark.parametrize("rb", [8, 4])
-def test_velocity_field_with_zero_tensors(rb):
+@pytest.mark.parametrize("rb,quads", [(8, 0), (4, 0), (4, 1)])
+def test_velocity_field_with_zero_tensors(rb, quads):
     """With D_m = 0, particles at rest have D = 0: their reciprocals are
     infinite and every harmonic mean with them vanishes (Eq. 5 with the zero
-    product rule), while the convective term still acts."""
+    product rule), while the convective term still acts.  quads: four lanes
+    per two targets (b's separations formed from a's)."""
     from paper_2108_09488_amd.context import Context, params_from_spec
     spec = I.config("cfg1", n_side=40, real_bytes=rb, kernel=4, h_over_dp=1.5, jitter=0.1, D_m=0.0,
                     dt=2.0 ** -12)
@@ -77,9 +78,11 @@ def test_velocity_field_with_zero_tensors(rb):
     C = spec.concentration(x)
     if rb == 4:
         C = C.astype(np.float32).astype(np.float64)
-    print(f"[case] velocity field with zero tensors rb={rb}", flush=True)
+    print(f"[case] velocity field with zero tensors rb={rb} quads={quads}", flush=True)
     ctx = Context([params_from_spec(spec, flags=_lib.ADE_VELOCITY_FIELD)], [spec.n])
     ctx.init(torch.from_numpy(x), torch.from_numpy(C)).set_velocities(torch.from_numpy(v)).build()
+    if quads:
+        ctx.set_tuning(block=64, lanes=4, targets=2)
     g = ctx.rhs().double().cpu().numpy()
     assert np.all(np.isfinite(g))
     m = O.model_from_spec(spec)
