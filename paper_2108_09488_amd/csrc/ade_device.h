@@ -57,6 +57,24 @@ __device__ __forceinline__ void enlist(const CellLists& L, uint32_t key, uint32_
     }
 }
 
+// Two particles of one cell counted with one atomic: their ids take
+// consecutive slots of the cell's bucket (or the overflow list past kBucket).
+// The order inside a cell's entries is free: placement ranks a cell's
+// particles by id.
+__device__ __forceinline__ void enlist2(const CellLists& L, uint32_t key, uint32_t id0, uint32_t id1) {
+    const uint32_t t = atomicAdd(&L.count[key], 2u);
+    const uint32_t ids[2] = {id0, id1};
+#pragma unroll
+    for (uint32_t q = 0; q < 2; ++q) {
+        if (t + q < kBucket) {
+            L.bucket[(size_t)key * kBucket + t + q] = ids[q];
+        } else {
+            const uint32_t p = atomicAdd(&L.ovf_count[0], 1u);
+            L.ovf[p] = make_uint2(key, ids[q]);
+        }
+    }
+}
+
 template <typename T>
 __device__ __forceinline__ T wave_inclusive_scan(T x) {
     const int lane = threadIdx.x & (kWave - 1);

@@ -155,18 +155,20 @@ __device__ __forceinline__ void walk_list(const Term& term, const Target& T,
 
 // The end of a target's pair sum acc: rhs mode writes the right-hand side
 // (vphi * acc) in id order; half mode the half-step concentration (and its
-// candidate record); step mode updates C and x and hashes the moved particle
-// into the next build's cell counts.
+// candidate record); step mode updates C and x and returns the moved
+// particle's cell key (its id in id), which the caller enters into the next
+// build's cell lists (enlist).
 template <int DIM, typename real, int KERN, int MODE>
-__device__ __forceinline__ void finish_target(const PairLaunch& a, const PlumeDev& P, const Target& T, uint32_t i,
-                                              real acc) {
+__device__ __forceinline__ uint32_t finish_core(const PairLaunch& a, const PlumeDev& P, const Target& T, uint32_t i,
+                                                real acc, uint32_t& id) {
     constexpr bool kRec = Rec<DIM, real>::kStageable;
     // the kernel factor's constant and the bracket's sign S (the pair term
     // sums S times the bracket)
     const double kS = kPolyScale<KERN> * P.dterm[4];
+    id = 0u;
     if (MODE == kModeRhs) {
         static_cast<real*>(a.out)[a.sid[i]] = (real)(kS * P.vphi) * acc;
-        return;
+        return 0u;
     }
     const real sc = (real)(a.scale * P.dt * P.vphi * kS);
     const real Cb = static_cast<const real*>(a.Cbase)[i];
@@ -174,9 +176,9 @@ __device__ __forceinline__ void finish_target(const PairLaunch& a, const PlumeDe
         const real Ch = fmar(sc, acc, Cb);
         static_cast<real*>(a.out)[i] = Ch;
         if (kRec) a.out_rec[i] = Rec<DIM, real>::pack(T.ux, T.uy, T.uz, Ch);
-        return;
+        return 0u;
     }
-    // step: update C and x, hash the moved particle for the next build
+    // step: update C and x, key of the moved particle for the next build
     const int64_t k = *a.step;
     uint32_t u[3] = {T.ux, T.uy, T.uz};
 #pragma unroll
@@ -188,11 +190,20 @@ __device__ __forceinline__ void finish_target(const PairLaunch& a, const PlumeDe
         a.upos[c][i] = u[c];
     }
     static_cast<real*>(a.uC)[i] = fmar(sc, acc, Cb);
-    const uint32_t id = a.sid[i];
+    id = a.sid[i];
     a.uid[i] = id;
     const uint32_t key = cell_key<DIM>(P, u[0], u[1], u[2]);
     a.ukey[i] = key;
-    enlist(a.lists, key, id);
+    return key;
+}
+
+// finish_core, and in step mode the moved particle entered into its cell.
+template <int DIM, typename real, int KERN, int MODE>
+__device__ __forceinline__ void finish_target(const PairLaunch& a, const PlumeDev& P, const Target& T, uint32_t i,
+                                              real acc) {
+    uint32_t id;
+    const uint32_t key = finish_core<DIM, real, KERN, MODE>(a, P, T, i, acc, id);
+    if (MODE == kModeStep) enlist(a.lists, key, id);
 }
 
 // One work item = `block / LANES` consecutive target particles of one tile.
@@ -383,8 +394,18 @@ __device__ __forceinline__ void pair_item2(const PairLaunch& a, const PlumeDev* 
     else list[0] = make_uint2(kListEndStart, kListEndEnd);
     const PairTerm<DIM, real, KERN, ZC> term = make_term<DIM, real, KERN, ZC>(P);
     walk_pair<DIM>(term, TA, TB, CA, CB, iA, list, stride, total, fetch, accA, accB);
-    if (actA) finish_target<DIM, real, KERN, MODE>(a, P, TA, iA, accA);
-    if (merged) finish_target<DIM, real, KERN, MODE>(a, P, TB, iB, accB);
+    // the pair's moved particles: two of one cell are counted with one atomic
+    uint32_t idA = 0u, idB = 0u, kA = 0u, kB = 0u;
+    if (actA) kA = finish_core<DIM, real, KERN, MODE>(a, P, TA, iA, accA, idA);
+    if (merged) kB = finish_core<DIM, real, KERN, MODE>(a, P, TB, iB, accB, idB);
+    if (MODE == kModeStep) {
+        if (merged && kA == kB) {
+            enlist2(a.lists, kA, idA, idB);
+        } else {
+            if (actA) enlist(a.lists, kA, idA);
+            if (merged) enlist(a.lists, kB, idB);
+        }
+    }
 
     // b of a pair that could not be merged walks its own list (a second walk
     // that only wavefronts holding such a pair enter)
