@@ -46,7 +46,12 @@ __global__ __launch_bounds__(kTile) void k_init(const PlumeDev* __restrict__ plu
 // launches and each chunk reads its own prefix.
 // ---------------------------------------------------------------------------
 constexpr int kCellVec = kCellChunk / (256 * 4);  // uint4 of counts per thread, contiguous
-constexpr uint32_t kDirectChunks = 2048;           // chunks whose prefixes the final launch sums itself
+// chunks whose prefixes the final launch sums itself: 4096 for the cell scan
+// of every step (the 2D sweep's 2.1M cells and the 3D plume's 3.6M take the
+// two-launch path; a third launch for the totals cost the sweep's step 1.3%),
+// 2048 for the neighbour-offset scan
+constexpr uint32_t kDirectChunks = 4096;
+constexpr uint32_t kDirectChunks64 = 2048;
 constexpr int kPrefixBlock = 1024;                 // the workgroup of k_scan_prefix
 
 // Exclusive scan in place of n chunk totals by one workgroup, in passes of
@@ -185,7 +190,7 @@ __global__ __launch_bounds__(kScanBlock) void k_scan64_final(int64_t* __restrict
 
 hipError_t launch_scan64(int64_t* data, uint32_t n, int64_t* partial, hipStream_t s) {
     const uint32_t nb = (n + kScanChunk - 1) / kScanChunk;
-    const uint32_t direct = nb <= kDirectChunks ? 1u : 0u;
+    const uint32_t direct = nb <= kDirectChunks64 ? 1u : 0u;
     hipLaunchKernelGGL(k_scan64_partial, dim3(nb), dim3(kScanBlock), 0, s, data, partial, n);
     if (!direct) hipLaunchKernelGGL((k_scan_prefix<int64_t>), dim3(1), dim3(kPrefixBlock), 0, s, partial, nb);
     hipLaunchKernelGGL(k_scan64_final, dim3(nb), dim3(kScanBlock), 0, s, data, partial, n, nb, direct);

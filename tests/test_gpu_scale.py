@@ -19,7 +19,7 @@ from paper_2108_09488_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-DIRECT_CELLS = 2048 * 1024     # cells the cell scan's final launch still sums directly
+DIRECT_CELLS = 4096 * 1024     # cells the cell scan's final launch still sums directly
 DIRECT_OFFSETS = 2048 * 4096   # neighbour-offset entries the same holds for
 LIMIT = (1 << 28) - 256        # particles per context
 
