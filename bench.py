@@ -588,9 +588,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extras", action="store_true", help="skip every workload but the headline")
-    ap.add_argument("--extras", default="sweep,batched,fwd_adjoint,velocity_field,paper_scale",
-                    help="comma-separated extras to run (unless --no-extras); velocity_paper (the "
-                         "10^6-particle problem with a velocity field) only when named")
+    ap.add_argument("--extras", default="sweep,batched,fwd_adjoint,velocity_field,paper_scale,velocity_paper",
+                    help="comma-separated extras to run (unless --no-extras)")
     ap.add_argument("--cells", default="", help="comma-separated subset of the sweep plumes")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run one device-to-device copy of this many MiB (a known-size "
