@@ -85,8 +85,21 @@ __global__ __launch_bounds__(kPrefixBlock) void k_scan_prefix(T* __restrict__ p,
 template <typename T>
 __device__ __forceinline__ T chunk_prefix(const T* __restrict__ partial, uint32_t direct, T* lds) {
     if (!direct) return partial[blockIdx.x];
+    // 16-byte loads of the totals (the array is 256-byte aligned), then the
+    // few past the last whole vector
+    constexpr uint32_t kPer = 16 / sizeof(T);
+    struct alignas(16) Vec {
+        T v[kPer];
+    };
+    const Vec* __restrict__ pv = reinterpret_cast<const Vec*>(partial);
+    const uint32_t nv = blockIdx.x / kPer;
     T pre = 0;
-    for (uint32_t b = threadIdx.x; b < blockIdx.x; b += blockDim.x) pre += partial[b];
+    for (uint32_t b = threadIdx.x; b < nv; b += blockDim.x) {
+        const Vec q = pv[b];
+#pragma unroll
+        for (uint32_t k = 0; k < kPer; ++k) pre += q.v[k];
+    }
+    for (uint32_t b = nv * kPer + threadIdx.x; b < blockIdx.x; b += blockDim.x) pre += partial[b];
     return block_sum(pre, lds);
 }
 
