@@ -161,7 +161,7 @@ def batched(device, steps, warmup, n_plumes=256):
     ctx.init(torch.from_numpy(xs), torch.from_numpy(Cs.astype(np.float32))).build()
     off, _ = ctx.neighbours()
     inter = int(off[-1].item())
-    tuned = ctx.autotune(reps=3)
+    tuned = ctx.autotune(reps=8)
     ctx.step_graph(warmup)
     _sync()
     t0 = time.perf_counter()
@@ -302,7 +302,7 @@ def headline_3d(device, steps, warmup, shape=None):
         c.set_tuning(**shape)
         tuned = c.get_tuning()
     else:
-        tuned = c.autotune(reps=2)
+        tuned = c.autotune(reps=5)
     print(f"[bench] 3D plume built: {inter} interactions per step, tuning {tuned}", file=sys.stderr, flush=True)
     c.step_graph(warmup)
     _sync()
@@ -636,7 +636,7 @@ def main():
             sweep["ctx"].set_tuning(**parse_shape(args.shape_sweep))
             sweep["tuning"] = sweep["ctx"].get_tuning()
         else:
-            sweep["tuning"] = sweep["ctx"].autotune(reps=3)
+            sweep["tuning"] = sweep["ctx"].autotune(reps=8)
         inter_step = sum(sweep["interactions"])
         wall, _ = time_sweep(sweep, args.steps, args.warmup, graph=True)
         ewall, pair = time_sweep(sweep, args.steps, args.warmup, graph=False)
